@@ -1,0 +1,161 @@
+/* gs4d.h - C ABI of the MI355X (gfx950) differentiable Gaussian-splatting library.
+ *
+ * The library implements the rendering hot path of 4DGCPro (arXiv 2509.17513):
+ * projection of anisotropic 3D Gaussians with spherical-harmonic colour
+ * (Sec. 3.1, Eq. 1 and the covariance factorisation), front-to-back alpha
+ * compositing of depth-ordered Gaussians (Eq. 2) for every nested layer
+ * (progressive rendering, Eq. 4), frame composition of a group from its
+ * keyframe and residuals (Sec. 3.2, pose update and Eq. 7), the backward of
+ * all of these for the layer-weighted L1 colour loss (Sec. 3.3, keyframe loss,
+ * D-SSIM weight 0), and the rate terms of the attributes.
+ *
+ * General rules
+ *  - Every buffer pointer is a DEVICE pointer owned by the caller, unless a
+ *    parameter says "host". The library never allocates device memory; all
+ *    scratch state lives in the caller's workspace `ws`.
+ *  - Every launch is asynchronous on `stream` (a hipStream_t; NULL = the
+ *    default stream). Only gs_check_status synchronises.
+ *  - Functions return GS_OK (0) or a negative GS_ERR_* code. Argument checks
+ *    happen on the host before any launch. HIP launch errors are reported as
+ *    GS_ERR_HIP with a message available from gs_last_error().
+ *  - Floating-point layouts are float32, planar ("[C][N]" = C rows of N).
+ *  - Concurrent calls that share a workspace race; calls on different
+ *    workspaces are independent.
+ */
+#ifndef GS4D_H
+#define GS4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARG = -1,   /* bad size, pointer, degree or level layout */
+  GS_ERR_WORKSPACE = -2,     /* ws_bytes smaller than gs_workspace_size() */
+  GS_ERR_PAIR_OVERFLOW = -3, /* more (tile, Gaussian) pairs than pair_capacity */
+  GS_ERR_HIP = -4,           /* a HIP runtime call or launch failed */
+  GS_ERR_NO_DEVICE = -5,     /* no gfx950 device is visible */
+  GS_ERR_UNSUPPORTED = -6    /* a valid request this build does not implement */
+};
+
+/* One pinhole camera (64 bytes). Cameras are passed as a DEVICE array of
+ * F * V entries, frame-major (camera of frame f, view v at f * V + v).
+ * viewmat is the row-major world-to-camera [R | t] (3 x 4) with OpenCV axes
+ * (x right, y down, z forward). Pixel (u, v) is sampled at (u + 0.5, v + 0.5). */
+typedef struct {
+  float viewmat[12];
+  float fx, fy, cx, cy;
+} gs_camera;
+
+/* Render settings (host struct, read at call time).
+ *  sh_degree     0..3; the parameter array has C = 11 + 3 (sh_degree + 1)^2 rows.
+ *  n_levels      1..8 nested layers; level_counts ascending, the last == n.
+ *                Layer l renders the Gaussians with index < level_counts[l]
+ *                (progressive rendering over the index sets N^l, Eq. 4).
+ *  level_weights lambda^l of the layer-weighted loss (App. A uses 0.5 / l for
+ *                l < L and 1 for l = L); used by the fused L1 gradient.
+ *  res_channels  0 (no residuals), 8 (translation 3, rotation quaternion 4,
+ *                opacity logit 1), 11 (+ log-scale 3) or 11 + 3 (d+1)^2 (+ SH).
+ *  near_plane    Gaussians whose camera depth is <= near_plane are culled.
+ *  dilation      added to the diagonal of every 2D covariance (pixels^2).
+ *  alpha_min     a Gaussian contributes to a pixel iff min(alpha_max, o G) >= alpha_min.
+ *  alpha_max     upper clamp of the per-pixel alpha.
+ *  t_stop        compositing stops before a Gaussian that would bring the
+ *                transmittance below t_stop (that Gaussian is not included).
+ *  bg            background colour added with the final transmittance.
+ *  tile_w/tile_h screen tile in pixels; 0/0 selects 16 x 16, the only shape
+ *                this build implements. */
+typedef struct {
+  int32_t width, height;
+  int32_t sh_degree;
+  int32_t n_levels;
+  int32_t level_counts[8];
+  float level_weights[8];
+  int32_t res_channels;
+  float near_plane, dilation, alpha_min, alpha_max, t_stop;
+  float bg[3];
+  int32_t tile_w, tile_h;
+} gs_settings;
+
+/* Bytes of workspace needed for a render of n Gaussians, n_frames frames of
+ * n_views views each, with room for pair_capacity (tile, Gaussian) pairs.
+ * A forward that needs more pairs flags GS_ERR_PAIR_OVERFLOW, reported by
+ * gs_check_status together with the number it needed. */
+int gs_workspace_size(const gs_settings* s, int32_t n, int32_t n_frames, int32_t n_views,
+                      int64_t pair_capacity, size_t* bytes_out);
+
+/* Byte offsets of the workspace regions (for inspection by tests). */
+typedef struct {
+  size_t status, records, rects, keys, vals, ranges, lists, t_final, n_last, grad2d, composed;
+  size_t total;
+  int32_t tiles_x, tiles_y;
+  int64_t pair_capacity;
+} gs_workspace_layout;
+int gs_workspace_describe(const gs_settings* s, int32_t n, int32_t n_frames, int32_t n_views,
+                          int64_t pair_capacity, gs_workspace_layout* out);
+
+/* Forward render (Eq. 2 for every layer of Eq. 4, every view and frame).
+ *  params     [C][n] keyframe parameters: 0..2 mean, 3..5 log-scale,
+ *             6..9 rotation quaternion (w, x, y, z; need not be unit),
+ *             10 opacity logit, 11 + 3k + c SH coefficient k of colour c.
+ *             Activations: scale = exp, opacity = sigmoid, rotation = R(q/|q|).
+ *  residuals  [n_frames][res_channels][n] per-frame deltas, or NULL (then
+ *             every frame renders the keyframe). Frame f composes the
+ *             keyframe with the deltas of frames 0..f: means, logit,
+ *             log-scales and SH add; rotation q_f = dq_f (x) q_{f-1}.
+ *  cams       DEVICE [n_frames * n_views] cameras.
+ *  image      [n_frames][n_views][n_levels][3][height][width] output.
+ *  ws         workspace of at least gs_workspace_size() bytes; it keeps the
+ *             state the backward needs, so do not reuse it in between. */
+int gs_render_forward(const gs_settings* s, int32_t n, const float* params, int32_t n_frames,
+                      const float* residuals, int32_t n_views, const gs_camera* cams, float* image,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of the last gs_render_forward made with the same arguments and ws.
+ *  d_image    dL/d image in the image layout, or NULL when target != NULL.
+ *  target     [n_frames][n_views][3][height][width]: fuse the gradient of
+ *             L = sum_{f,v,l} lambda^l mean_{pixel,channel} |C^l - target|
+ *             (needs image = the forward's output); NULL when d_image != NULL.
+ *  d_params   [C][n], accumulated (+=).
+ *  d_residuals[n_frames][res_channels][n], accumulated (+=), or NULL.
+ *  loss_out   one float, accumulated (+=) with L in the fused mode, or NULL. */
+int gs_render_backward(const gs_settings* s, int32_t n, const float* params, int32_t n_frames,
+                       const float* residuals, int32_t n_views, const gs_camera* cams, const float* image,
+                       const float* d_image, const float* target, float* d_params, float* d_residuals,
+                       float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronises `stream` and reports the status of the last forward on ws:
+ * GS_ERR_PAIR_OVERFLOW (and *needed_pairs) if its pair list did not fit. */
+int gs_check_status(void* ws, void* stream, int64_t* needed_pairs);
+
+/* Work counters of the last forward and backward on ws (synchronises stream).
+ *  fwd_evals / bwd_evals       (pixel, list entry) pairs whose Gaussian weight
+ *                              was evaluated by the raster pass
+ *  fwd_contribs / bwd_contribs (pixel, entry, layer) compositing updates */
+typedef struct {
+  int32_t overflow, pad;
+  int64_t needed_pairs, fwd_evals, fwd_contribs, bwd_evals, bwd_contribs;
+} gs_stats;
+int gs_workspace_stats(void* ws, void* stream, gs_stats* out);
+
+/* Text of an error code, and the last HIP error message of this thread. */
+const char* gs_error_string(int code);
+const char* gs_last_error(void);
+
+/* Per-kernel timing. While enabled, every kernel launch of the library is
+ * bracketed by HIP events recorded on its launch stream (do not enable it
+ * during hipGraph capture). gs_profile_collect waits for the recorded events,
+ * writes the summed milliseconds and launch counts per kernel id
+ * (0 <= id < max_ids; gs_kernel_name gives the names) and clears the record. */
+int gs_profile_enable(int on);
+int gs_profile_collect(int32_t max_ids, double* total_ms, int32_t* counts);
+const char* gs_kernel_name(int32_t id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS4D_H */

@@ -720,6 +720,10 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
           cand = all.data(); ncand = (int)all.size();
         }
         const double px = x + 0.5, py = y + 0.5;
+        bool any_w = false;
+        for (int l = 0; l < L && !any_w; ++l)
+          for (int c = 0; c < 3; ++c) any_w = any_w || d_image[(((size_t)b * L + l) * 3 + c) * npix + pix] != 0.0;
+        if (!any_w) continue;
         pixel_candidates(recs, cand, ncand, px, py, S, kept);
         for (int l = 0; l < L; ++l) {
           const size_t o = (size_t)b * L + l;

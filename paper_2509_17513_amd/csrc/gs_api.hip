@@ -1,0 +1,387 @@
+// Host side of the C ABI: argument validation, workspace layout and the
+// launch sequence of the forward and backward render.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstddef>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gs4d.h"
+#include "gs_internal.h"
+#include "gs_prof.h"
+
+namespace gs {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail_hip(hipError_t e, const char* where) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+  g_last_error = buf;
+  return GS_ERR_HIP;
+}
+
+int fail_arg(const char* msg) {
+  g_last_error = msg;
+  return GS_ERR_INVALID_ARG;
+}
+
+// Checks once per process that the current device is a gfx950.
+int check_device() {
+  static std::once_flag once;
+  static int status = GS_OK;
+  std::call_once(once, [] {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+      status = GS_ERR_NO_DEVICE;
+      return;
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      status = GS_ERR_NO_DEVICE;
+      return;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) status = GS_ERR_NO_DEVICE;
+  });
+  if (status != GS_OK) g_last_error = "no gfx950 device visible";
+  return status;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap, RenderDims& d) {
+  if (!s) return fail_arg("settings is NULL");
+  if (n < 0) return fail_arg("n < 0");
+  if (F < 1 || V < 1) return fail_arg("n_frames and n_views must be >= 1");
+  if (s->width < 1 || s->height < 1) return fail_arg("width and height must be >= 1");
+  if (s->sh_degree < 0 || s->sh_degree > 3) return fail_arg("sh_degree must be in 0..3");
+  if (s->n_levels < 1 || s->n_levels > kMaxLevels) return fail_arg("n_levels must be in 1..8");
+  for (int l = 0; l < s->n_levels; ++l) {
+    if (s->level_counts[l] < 0 || s->level_counts[l] > n) return fail_arg("level_counts out of range");
+    if (l > 0 && s->level_counts[l] < s->level_counts[l - 1]) return fail_arg("level_counts not ascending");
+  }
+  if (s->level_counts[s->n_levels - 1] != n) return fail_arg("last level count must equal n");
+  const int K = (s->sh_degree + 1) * (s->sh_degree + 1);
+  const int C = 11 + 3 * K;
+  if (!(s->res_channels == 0 || s->res_channels == 8 || s->res_channels == 11 || s->res_channels == C))
+    return fail_arg("res_channels must be 0, 8, 11 or 11 + 3 (d+1)^2");
+  if ((s->tile_w != 0 || s->tile_h != 0) && (s->tile_w != kTile || s->tile_h != kTile)) {
+    g_last_error = "only 16x16 tiles are implemented";
+    return GS_ERR_UNSUPPORTED;
+  }
+  if (!(s->alpha_min > 0.f) || !(s->alpha_max <= 1.f) || !(s->alpha_min <= s->alpha_max))
+    return fail_arg("need 0 < alpha_min <= alpha_max <= 1");
+  if (!(s->t_stop >= 0.f) || !(s->near_plane > 0.f) || !(s->dilation >= 0.f))
+    return fail_arg("need t_stop >= 0, near_plane > 0, dilation >= 0");
+  if (cap < 0 || cap > 0xFFFFFFFFll) return fail_arg("pair_capacity must be in [0, 2^32)");
+  d.n = n; d.F = F; d.V = V; d.B = F * V; d.W = s->width; d.H = s->height;
+  d.TX = (d.W + kTile - 1) / kTile;
+  d.TY = (d.H + kTile - 1) / kTile;
+  d.T = d.TX * d.TY;
+  if (d.T > kMaxTilesPerView) return fail_arg("image has more than 16384 tiles");
+  if ((int64_t)d.B * n > (int64_t)1 << 31) return fail_arg("n_frames * n_views * n too large");
+  d.deg = s->sh_degree; d.K = K; d.C = C; d.L = s->n_levels; d.Rc = s->res_channels;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    d.lv[l] = l < d.L ? s->level_counts[l] : n;
+    d.lw[l] = l < d.L ? s->level_weights[l] : 0.f;
+  }
+  d.near_plane = s->near_plane; d.dilation = s->dilation; d.alpha_min = s->alpha_min;
+  d.alpha_max = s->alpha_max; d.t_stop = s->t_stop;
+  for (int c = 0; c < 3; ++c) d.bg[c] = s->bg[c];
+  d.n_sort_chunks = (n + kSortChunk - 1) / kSortChunk;
+  d.n_bin_chunks = (n + kBinChunk - 1) / kBinChunk;
+  d.capacity = (unsigned long long)cap;
+  return GS_OK;
+}
+
+}  // namespace
+
+
+// ------------------------------------------------------------ profiling
+namespace {
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+const char* kKernelNames[K_COUNT] = {
+    "compose_fwd", "project_fwd", "radix_hist", "radix_scan", "radix_scatter", "bin_count", "bin_chunk_scan",
+    "tile_ranges", "bin_emit", "raster_fwd", "zero", "raster_bwd", "project_bwd", "compose_bwd", "rate_ctx",
+    "rate_mlp", "rate_hist_minmax", "rate_hist_count", "rate_hist_bits", "adam"};
+}  // namespace
+
+int prof_begin(int id, hipStream_t st) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (!g_prof_on) return -1;
+  ProfRec r{id, prof_event(), prof_event()};
+  if (!r.a || !r.b) return -1;
+  hipEventRecord(r.a, st);
+  g_prof_recs.push_back(r);
+  return (int)g_prof_recs.size() - 1;
+}
+
+void prof_end(int slot, hipStream_t st) {
+  if (slot < 0) return;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (slot < (int)g_prof_recs.size()) hipEventRecord(g_prof_recs[slot].b, st);
+}
+
+Layout make_layout(const RenderDims& d) {
+  Layout lo;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t Bn = (size_t)d.B * d.n;
+  const size_t HW = (size_t)d.W * d.H;
+  lo.status = take(256);
+  lo.records = take(Bn * 48);
+  lo.rects = take(Bn * 8);
+  lo.keys0 = take(Bn * 4);
+  lo.vals0 = take(Bn * 4);
+  lo.keys1 = take(Bn * 4);
+  lo.vals1 = take(Bn * 4);
+  lo.sort_hist = take((size_t)d.B * 256 * d.n_sort_chunks * 4);
+  lo.bin_hist = take((size_t)d.B * d.n_bin_chunks * d.T * 4);
+  lo.tile_tot = take((size_t)d.B * d.T * 4);
+  lo.ranges = take((size_t)d.B * d.T * 8);
+  lo.t_final = take((size_t)d.B * d.L * HW * 4);
+  lo.n_last = take((size_t)d.B * d.L * HW * 4);
+  lo.grad2d = take(Bn * 9 * 4);
+  lo.composed = take((size_t)d.F * d.Rc * d.n * 4);
+  lo.d_composed = take((size_t)d.F * d.Rc * d.n * 4);
+  // the pair list is last, so every other offset is independent of its capacity
+  lo.lists = take((size_t)d.capacity * 4);
+  lo.total = off;
+  return lo;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+int gs_workspace_size(const gs_settings* s, int32_t n, int32_t n_frames, int32_t n_views, int64_t pair_capacity,
+                      size_t* bytes_out) {
+  if (!bytes_out) return fail_arg("bytes_out is NULL");
+  RenderDims d;
+  int rc = make_dims(s, n, n_frames, n_views, pair_capacity, d);
+  if (rc) return rc;
+  *bytes_out = make_layout(d).total;
+  return GS_OK;
+}
+
+int gs_workspace_describe(const gs_settings* s, int32_t n, int32_t n_frames, int32_t n_views,
+                          int64_t pair_capacity, gs_workspace_layout* out) {
+  if (!out) return fail_arg("out is NULL");
+  RenderDims d;
+  int rc = make_dims(s, n, n_frames, n_views, pair_capacity, d);
+  if (rc) return rc;
+  Layout lo = make_layout(d);
+  out->status = lo.status;
+  out->records = lo.records;
+  out->rects = lo.rects;
+  out->keys = lo.keys0;
+  out->vals = lo.vals0;
+  out->ranges = lo.ranges;
+  out->lists = lo.lists;
+  out->t_final = lo.t_final;
+  out->n_last = lo.n_last;
+  out->grad2d = lo.grad2d;
+  out->composed = lo.composed;
+  out->total = lo.total;
+  out->tiles_x = d.TX;
+  out->tiles_y = d.TY;
+  out->pair_capacity = (int64_t)d.capacity;
+  return GS_OK;
+}
+
+int gs_render_forward(const gs_settings* s, int32_t n, const float* params, int32_t n_frames,
+                      const float* residuals, int32_t n_views, const gs_camera* cams, float* image, void* ws,
+                      size_t ws_bytes, void* stream) {
+  RenderDims d;
+  // the pair capacity is whatever the workspace holds after the fixed regions
+  int rc = make_dims(s, n, n_frames, n_views, 0, d);
+  if (rc) return rc;
+  if ((n > 0 && !params) || !cams || !image || !ws) return fail_arg("NULL buffer");
+  if (d.Rc > 0 && !residuals) return fail_arg("res_channels > 0 needs residuals");
+  if (!d.Rc && residuals) return fail_arg("residuals given but res_channels == 0");
+  Layout lo0 = make_layout(d);
+  if (ws_bytes < lo0.total) {
+    g_last_error = "workspace too small";
+    return GS_ERR_WORKSPACE;
+  }
+  d.capacity = std::min<unsigned long long>((ws_bytes - lo0.total) / 4, 0xFFFFFFFFull);
+  const Layout lo = make_layout(d);
+  if ((rc = check_device())) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  hipError_t e;
+  if (d.Rc > 0 && n > 0) {
+    if ((e = launch_compose_fwd(d, params, residuals, (float*)(w + lo.composed), st)) != hipSuccess)
+      return fail_hip(e, "compose_fwd");
+  }
+  if (n > 0) {
+    if ((e = launch_project_fwd(d, params, (const float*)(w + lo.composed), cams, w, lo, st)) != hipSuccess)
+      return fail_hip(e, "project_fwd");
+    uint32_t *sk, *sv;
+    if ((e = launch_sort(d, w, lo, &sk, &sv, st)) != hipSuccess) return fail_hip(e, "sort");
+    if ((e = launch_bin(d, sk, sv, w, lo, st)) != hipSuccess) return fail_hip(e, "bin");
+  } else {
+    if ((e = launch_bin(d, nullptr, nullptr, w, lo, st)) != hipSuccess) return fail_hip(e, "bin");
+  }
+  if ((e = launch_raster_fwd(d, w, lo, image, st)) != hipSuccess) return fail_hip(e, "raster_fwd");
+  return GS_OK;
+}
+
+int gs_render_backward(const gs_settings* s, int32_t n, const float* params, int32_t n_frames,
+                       const float* residuals, int32_t n_views, const gs_camera* cams, const float* image,
+                       const float* d_image, const float* target, float* d_params, float* d_residuals,
+                       float* loss_out, void* ws, size_t ws_bytes, void* stream) {
+  RenderDims d;
+  int rc = make_dims(s, n, n_frames, n_views, 0, d);
+  if (rc) return rc;
+  if ((n > 0 && (!params || !d_params)) || !cams || !ws) return fail_arg("NULL buffer");
+  if ((d_image == nullptr) == (target == nullptr)) return fail_arg("exactly one of d_image and target");
+  if (target && !image) return fail_arg("the fused L1 gradient needs the forward image");
+  if (d.Rc > 0 && !residuals) return fail_arg("res_channels > 0 needs residuals");
+  if (!d.Rc && (residuals || d_residuals)) return fail_arg("residuals given but res_channels == 0");
+  Layout lo0 = make_layout(d);
+  if (ws_bytes < lo0.total) {
+    g_last_error = "workspace too small";
+    return GS_ERR_WORKSPACE;
+  }
+  d.capacity = std::min<unsigned long long>((ws_bytes - lo0.total) / 4, 0xFFFFFFFFull);
+  const Layout lo = make_layout(d);
+  if ((rc = check_device())) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  hipError_t e;
+  if ((e = launch_zero(w + lo.status + offsetof(Status, bwd_evals), 16, st)) != hipSuccess) return fail_hip(e, "zero");
+  if (n == 0) {
+    if (loss_out || target) {
+      // the loss of an empty scene still depends on the background; run the raster backward for it
+      if ((e = launch_raster_bwd(d, w, lo, image, d_image, target, loss_out, st)) != hipSuccess)
+        return fail_hip(e, "raster_bwd");
+    }
+    return GS_OK;
+  }
+  if ((e = launch_zero(w + lo.grad2d, (size_t)d.B * d.n * 9 * 4, st)) != hipSuccess) return fail_hip(e, "zero");
+  if (d.Rc > 0 && (e = launch_zero(w + lo.d_composed, (size_t)d.F * d.Rc * d.n * 4, st)) != hipSuccess)
+    return fail_hip(e, "zero");
+  if ((e = launch_raster_bwd(d, w, lo, image, d_image, target, loss_out, st)) != hipSuccess)
+    return fail_hip(e, "raster_bwd");
+  if ((e = launch_project_bwd(d, params, (const float*)(w + lo.composed), cams, w, lo, d_params, st)) != hipSuccess)
+    return fail_hip(e, "project_bwd");
+  if (d.Rc > 0) {
+    if ((e = launch_compose_bwd(d, params, residuals, (const float*)(w + lo.composed),
+                                (const float*)(w + lo.d_composed), d_params, d_residuals, st)) != hipSuccess)
+      return fail_hip(e, "compose_bwd");
+  }
+  return GS_OK;
+}
+
+int gs_check_status(void* ws, void* stream, int64_t* needed_pairs) {
+  if (!ws) return fail_arg("ws is NULL");
+  int rc = check_device();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Status h;
+  hipError_t e = hipMemcpyAsync(&h, ws, sizeof(Status), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return fail_hip(e, "check_status copy");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail_hip(e, "check_status sync");
+  if (needed_pairs) *needed_pairs = (int64_t)h.needed_pairs;
+  return h.overflow ? GS_ERR_PAIR_OVERFLOW : GS_OK;
+}
+
+int gs_workspace_stats(void* ws, void* stream, gs_stats* out) {
+  if (!ws || !out) return fail_arg("NULL argument");
+  int rc = check_device();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Status h;
+  hipError_t e = hipMemcpyAsync(&h, ws, sizeof(Status), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail_hip(e, "workspace_stats");
+  out->overflow = (int32_t)h.overflow;
+  out->needed_pairs = (int64_t)h.needed_pairs;
+  out->fwd_evals = (int64_t)h.fwd_evals;
+  out->fwd_contribs = (int64_t)h.fwd_contribs;
+  out->bwd_evals = (int64_t)h.bwd_evals;
+  out->bwd_contribs = (int64_t)h.bwd_contribs;
+  return GS_OK;
+}
+
+const char* gs_error_string(int code) {
+  switch (code) {
+    case GS_OK: return "ok";
+    case GS_ERR_INVALID_ARG: return "invalid argument";
+    case GS_ERR_WORKSPACE: return "workspace too small";
+    case GS_ERR_PAIR_OVERFLOW: return "pair list capacity exceeded";
+    case GS_ERR_HIP: return "HIP runtime error";
+    case GS_ERR_NO_DEVICE: return "no gfx950 device";
+    case GS_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+const char* gs_last_error(void) { return g_last_error.c_str(); }
+
+int gs_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  return GS_OK;
+}
+
+int gs_profile_collect(int32_t max_ids, double* total_ms, int32_t* counts) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (int k = 0; k < max_ids; ++k) {
+    if (total_ms) total_ms[k] = 0.0;
+    if (counts) counts[k] = 0;
+  }
+  int rc = GS_OK;
+  for (auto& r : g_prof_recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) rc = fail_hip(e, "profile");
+    if (r.id < max_ids) {
+      if (total_ms) total_ms[r.id] += ms;
+      if (counts) counts[r.id] += 1;
+    }
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_recs.clear();
+  return rc;
+}
+
+const char* gs_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "?"; }
+
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Internal declarations shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs4d.h"
+
+namespace gs {
+
+constexpr int kTile = 16;            // screen tile edge (pixels); one tile = one 256-thread block
+constexpr int kTilePix = kTile * kTile;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortChunk = kSortThreads * kSortItems;  // keys per radix block
+constexpr int kBinChunk = 1024;      // depth-sorted Gaussians per binning wave
+constexpr int kMaxTilesPerView = 16384;
+constexpr int kMaxLevels = 8;
+
+// Status word at the start of the workspace.
+struct Status {
+  uint32_t overflow;      // 1 if the pair list did not fit
+  uint32_t pad;
+  unsigned long long needed_pairs;
+  // work counters of the last forward / backward raster pass:
+  // evals = (pixel, list entry) pairs whose Gaussian weight was evaluated,
+  // contribs = (pixel, entry, layer) compositing updates
+  unsigned long long fwd_evals, fwd_contribs, bwd_evals, bwd_contribs;
+};
+
+// Everything a kernel needs to know about one render call.
+struct RenderDims {
+  int n, F, V, B, W, H, TX, TY, T;  // T = tiles per view
+  int deg, C, K, L, Rc;
+  int lv[kMaxLevels];
+  float lw[kMaxLevels];
+  float near_plane, dilation, alpha_min, alpha_max, t_stop;
+  float bg[3];
+  int n_sort_chunks, n_bin_chunks;
+  unsigned long long capacity;
+};
+
+// Byte offsets inside the workspace.
+struct Layout {
+  size_t status, records, rects, keys0, vals0, keys1, vals1, sort_hist, bin_hist, tile_tot, ranges, lists, t_final,
+      n_last, grad2d, composed, d_composed, total;
+};
+
+Layout make_layout(const RenderDims& d);
+
+// ---- launchers (gs_render.hip) ----
+hipError_t launch_compose_fwd(const RenderDims& d, const float* params, const float* res, float* composed,
+                              hipStream_t st);
+hipError_t launch_project_fwd(const RenderDims& d, const float* params, const float* composed,
+                              const gs_camera* cams, char* ws, const Layout& lo, hipStream_t st);
+hipError_t launch_sort(const RenderDims& d, char* ws, const Layout& lo, uint32_t** keys_out, uint32_t** vals_out,
+                       hipStream_t st);
+hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t* svals, char* ws, const Layout& lo,
+                      hipStream_t st);
+hipError_t launch_raster_fwd(const RenderDims& d, char* ws, const Layout& lo, float* image, hipStream_t st);
+hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, const float* image,
+                             const float* d_image, const float* target, float* loss_out, hipStream_t st);
+hipError_t launch_project_bwd(const RenderDims& d, const float* params, const float* composed,
+                              const gs_camera* cams, char* ws, const Layout& lo, float* d_params, hipStream_t st);
+hipError_t launch_compose_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,
+                              const float* d_composed, float* d_params, float* d_res, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace gs

@@ -1,0 +1,1245 @@
+// gfx950 kernels of the differentiable Gaussian rasterizer.
+//
+// Pipeline of one forward (all frames, views and layers in the same launches):
+//   k_compose_fwd     frame composition of a group (Sec. 3.2, pose update, Eq. 7)
+//   k_project_fwd     one thread per Gaussian, looping over frames and views:
+//                     activations, covariance R diag(s^2) R^T (Sec. 3.1),
+//                     EWA projection, conic, footprint, tile rectangle and
+//                     view-dependent SH colour; writes 48-byte records
+//   k_radix_*         segmented stable LSD radix sort of float32 depth keys
+//                     (one segment per frame-view, 4 passes of 8 bits)
+//   k_bin_*           stable counting scatter of the depth-sorted Gaussians
+//                     into per-(view, tile) lists: the (tile, depth) order
+//   k_raster_fwd      one 256-thread block per (view, 16x16 tile): records are
+//                     staged through LDS in batches of 256; every pixel
+//                     composites all layers at once (Eq. 2 for each index set
+//                     of Eq. 4) and stops when every layer has reached the
+//                     transmittance floor
+// Backward:
+//   k_raster_bwd      reverse traversal from each layer's last contributor;
+//                     the transmittance is recovered by division, so no
+//                     per-pixel lists are stored; wave reductions, then one
+//                     atomic per (wave, record, value)
+//   k_project_bwd     one thread per Gaussian, all views and frames in registers
+//   k_compose_bwd     suffix sums and the quaternion-product chain over frames
+#include <hip/hip_runtime.h>
+
+#include "gs_internal.h"
+#include "gs_prof.h"
+
+namespace gs {
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ float rcp_f(float x) { return 1.0f / x; }
+
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float* R) {
+  R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+  R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+  R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// SH constants of the real orthonormal basis (Condon-Shortley phase).
+constexpr float kC0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+constexpr float kC1 = 0.4886025119029199f;    // sqrt(3 / (4 pi))
+constexpr float kC2a = 1.0925484305920792f;   // sqrt(15 / pi) / 2
+constexpr float kC2b = 0.31539156525252005f;  // sqrt(5 / pi) / 4
+constexpr float kC2c = 0.5462742152960396f;   // sqrt(15 / pi) / 4
+constexpr float kC3a = 0.5900435899266435f;   // sqrt(35 / (2 pi)) / 4
+constexpr float kC3b = 2.890611442640554f;    // sqrt(105 / pi) / 2
+constexpr float kC3c = 0.4570457994644658f;   // sqrt(21 / (2 pi)) / 4
+constexpr float kC3d = 0.3731763325901154f;   // sqrt(7 / pi) / 4
+constexpr float kC3e = 1.445305721320277f;    // sqrt(105 / pi) / 4
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+  Y[0] = kC0;
+  if constexpr (DEG >= 1) { Y[1] = -kC1 * y; Y[2] = kC1 * z; Y[3] = -kC1 * x; }
+  if constexpr (DEG >= 2) {
+    Y[4] = kC2a * (x * y); Y[5] = -kC2a * (y * z); Y[6] = kC2b * (3.f * z * z - 1.f);
+    Y[7] = -kC2a * (x * z); Y[8] = kC2c * (x * x - y * y);
+  }
+  if constexpr (DEG >= 3) {
+    Y[9] = -kC3a * y * (3.f * x * x - y * y);
+    Y[10] = kC3b * x * y * z;
+    Y[11] = -kC3c * y * (5.f * z * z - 1.f);
+    Y[12] = kC3d * z * (5.f * z * z - 3.f);
+    Y[13] = -kC3c * x * (5.f * z * z - 1.f);
+    Y[14] = kC3e * z * (x * x - y * y);
+    Y[15] = -kC3a * x * (x * x - 3.f * y * y);
+  }
+}
+
+// Gradient of sum_k w_k Y_k with respect to the (unnormalised) direction components.
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const float* w, float* g) {
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  if constexpr (DEG >= 1) { gy += -kC1 * w[1]; gz += kC1 * w[2]; gx += -kC1 * w[3]; }
+  if constexpr (DEG >= 2) {
+    gx += kC2a * y * w[4]; gy += kC2a * x * w[4];
+    gy += -kC2a * z * w[5]; gz += -kC2a * y * w[5];
+    gz += 6.f * kC2b * z * w[6];
+    gx += -kC2a * z * w[7]; gz += -kC2a * x * w[7];
+    gx += 2.f * kC2c * x * w[8]; gy += -2.f * kC2c * y * w[8];
+  }
+  if constexpr (DEG >= 3) {
+    gx += -6.f * kC3a * x * y * w[9]; gy += -3.f * kC3a * (x * x - y * y) * w[9];
+    gx += kC3b * y * z * w[10]; gy += kC3b * x * z * w[10]; gz += kC3b * x * y * w[10];
+    gy += -kC3c * (5.f * z * z - 1.f) * w[11]; gz += -10.f * kC3c * y * z * w[11];
+    gz += kC3d * (15.f * z * z - 3.f) * w[12];
+    gx += -kC3c * (5.f * z * z - 1.f) * w[13]; gz += -10.f * kC3c * x * z * w[13];
+    gx += 2.f * kC3e * x * z * w[14]; gy += -2.f * kC3e * y * z * w[14]; gz += kC3e * (x * x - y * y) * w[14];
+    gx += -3.f * kC3a * (x * x - y * y) * w[15]; gy += 6.f * kC3a * x * y * w[15];
+  }
+  g[0] = gx; g[1] = gy; g[2] = gz;
+}
+
+// Camera-space depth; the same float32 expression decides the depth order
+// and the near-plane test.
+__device__ __forceinline__ float cam_z(const gs_camera& c, float x, float y, float z) {
+  return fmaf(c.viewmat[10], z, fmaf(c.viewmat[9], y, fmaf(c.viewmat[8], x, c.viewmat[11])));
+}
+__device__ __forceinline__ float cam_x(const gs_camera& c, float x, float y, float z) {
+  return fmaf(c.viewmat[2], z, fmaf(c.viewmat[1], y, fmaf(c.viewmat[0], x, c.viewmat[3])));
+}
+__device__ __forceinline__ float cam_y(const gs_camera& c, float x, float y, float z) {
+  return fmaf(c.viewmat[6], z, fmaf(c.viewmat[5], y, fmaf(c.viewmat[4], x, c.viewmat[7])));
+}
+
+// Per-pixel Gaussian weight. Forward and backward call this one function on
+// the same inputs, so they take identical float32 decisions.
+struct AlphaEval {
+  float dx, dy, G, ga;  // ga = o * G before the alpha_max clamp
+};
+__device__ __forceinline__ AlphaEval alpha_eval(float px, float py, float mx, float my, float A, float B, float C,
+                                                float o) {
+  AlphaEval r;
+  r.dx = px - mx;
+  r.dy = py - my;
+  const float q = fmaf(A, r.dx * r.dx, fmaf(C, r.dy * r.dy, 2.0f * B * (r.dx * r.dy)));
+  r.G = __builtin_amdgcn_exp2f((-0.5f * q) * kLog2e);
+  r.ga = o * r.G;
+  return r;
+}
+
+// Residual channel r -> parameter channel.
+__device__ __forceinline__ int res_to_param(int r) {
+  if (r < 3) return r;
+  if (r < 7) return r + 3;
+  if (r == 7) return 10;
+  if (r < 11) return r - 5;
+  return r;
+}
+
+__device__ __forceinline__ void quat_mul(const float* a, const float* b, float* o) {
+  o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+// XCD-aware work mapping: consecutive work items land on the same XCD (the
+// dispatcher deals blocks round-robin to the 8 XCDs), so neighbouring tiles
+// of one view share that XCD's L2.
+__device__ __forceinline__ int xcd_item(int bid, int per_xcd) { return (bid & 7) * per_xcd + (bid >> 3); }
+
+// ============================================================ composition
+__global__ __launch_bounds__(256) void k_compose_fwd(RenderDims d, const float* __restrict__ P,
+                                                     const float* __restrict__ res, float* __restrict__ comp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const size_t n = d.n;
+  const int Rc = d.Rc;
+  // additive channels: everything but the quaternion (3..6)
+  for (int r = 0; r < Rc; ++r) {
+    if (r >= 3 && r <= 6) continue;
+    float v = P[(size_t)res_to_param(r) * n + i];
+    for (int f = 0; f < d.F; ++f) {
+      v = v + res[((size_t)f * Rc + r) * n + i];
+      comp[((size_t)f * Rc + r) * n + i] = v;
+    }
+  }
+  float q[4] = {P[6 * n + i], P[7 * n + i], P[8 * n + i], P[9 * n + i]};
+  for (int f = 0; f < d.F; ++f) {
+    float dq[4], o[4];
+    for (int c = 0; c < 4; ++c) dq[c] = res[((size_t)f * Rc + 3 + c) * n + i];
+    quat_mul(dq, q, o);
+    for (int c = 0; c < 4; ++c) {
+      q[c] = o[c];
+      comp[((size_t)f * Rc + 3 + c) * n + i] = o[c];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_compose_bwd(RenderDims d, const float* __restrict__ P,
+                                                     const float* __restrict__ res, const float* __restrict__ comp,
+                                                     const float* __restrict__ dcomp, float* __restrict__ dP,
+                                                     float* __restrict__ dres) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const size_t n = d.n;
+  const int Rc = d.Rc;
+  for (int r = 0; r < Rc; ++r) {
+    if (r >= 3 && r <= 6) continue;
+    float acc = 0.f;
+    for (int f = d.F - 1; f >= 0; --f) {
+      acc += dcomp[((size_t)f * Rc + r) * n + i];
+      if (dres) dres[((size_t)f * Rc + r) * n + i] += acc;
+    }
+    dP[(size_t)res_to_param(r) * n + i] += acc;
+  }
+  float carry[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int f = d.F - 1; f >= 0; --f) {
+    float g[4], a[4], b[4];
+    for (int c = 0; c < 4; ++c) {
+      g[c] = dcomp[((size_t)f * Rc + 3 + c) * n + i] + carry[c];
+      a[c] = res[((size_t)f * Rc + 3 + c) * n + i];
+      b[c] = f == 0 ? P[(size_t)(6 + c) * n + i] : comp[((size_t)(f - 1) * Rc + 3 + c) * n + i];
+    }
+    // p = a (x) b; gradients of <g, p> with respect to a and b
+    const float ga0 = b[0] * g[0] + b[1] * g[1] + b[2] * g[2] + b[3] * g[3];
+    const float ga1 = -b[1] * g[0] + b[0] * g[1] - b[3] * g[2] + b[2] * g[3];
+    const float ga2 = -b[2] * g[0] + b[3] * g[1] + b[0] * g[2] - b[1] * g[3];
+    const float ga3 = -b[3] * g[0] - b[2] * g[1] + b[1] * g[2] + b[0] * g[3];
+    carry[0] = a[0] * g[0] + a[1] * g[1] + a[2] * g[2] + a[3] * g[3];
+    carry[1] = -a[1] * g[0] + a[0] * g[1] + a[3] * g[2] - a[2] * g[3];
+    carry[2] = -a[2] * g[0] - a[3] * g[1] + a[0] * g[2] + a[1] * g[3];
+    carry[3] = -a[3] * g[0] + a[2] * g[1] - a[1] * g[2] + a[0] * g[3];
+    if (dres) {
+      dres[((size_t)f * Rc + 3) * n + i] += ga0;
+      dres[((size_t)f * Rc + 4) * n + i] += ga1;
+      dres[((size_t)f * Rc + 5) * n + i] += ga2;
+      dres[((size_t)f * Rc + 6) * n + i] += ga3;
+    }
+  }
+  for (int c = 0; c < 4; ++c) dP[(size_t)(6 + c) * n + i] += carry[c];
+}
+
+// ============================================================ projection
+// Frame-level quantities of one Gaussian (shared by its views).
+template <int DEG>
+struct GaussFrame {
+  float mu[3], ls[3], q[4], logit;
+  float sh[3 * (DEG + 1) * (DEG + 1)];
+};
+
+template <int DEG>
+__device__ __forceinline__ void load_frame(const RenderDims& d, const float* __restrict__ P,
+                                           const float* __restrict__ comp, int f, int i, GaussFrame<DEG>& g) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const size_t n = d.n;
+  if (d.Rc == 0 || f < 0) {
+    for (int c = 0; c < 3; ++c) g.mu[c] = P[c * n + i];
+    for (int c = 0; c < 3; ++c) g.ls[c] = P[(3 + c) * n + i];
+    for (int c = 0; c < 4; ++c) g.q[c] = P[(6 + c) * n + i];
+    g.logit = P[10 * n + i];
+#pragma unroll
+    for (int c = 0; c < 3 * K; ++c) g.sh[c] = P[(11 + c) * n + i];
+    return;
+  }
+  const float* cf = comp + (size_t)f * d.Rc * n;
+  for (int c = 0; c < 3; ++c) g.mu[c] = cf[c * n + i];
+  for (int c = 0; c < 4; ++c) g.q[c] = cf[(3 + c) * n + i];
+  g.logit = cf[7 * n + i];
+  for (int c = 0; c < 3; ++c) g.ls[c] = d.Rc >= 11 ? cf[(8 + c) * n + i] : P[(3 + c) * n + i];
+#pragma unroll
+  for (int c = 0; c < 3 * K; ++c) g.sh[c] = d.Rc > 11 ? cf[(11 + c) * n + i] : P[(11 + c) * n + i];
+}
+
+struct FrameGeom {
+  float R[9], s2[3], Sig[6];  // Sigma: xx, xy, xz, yy, yz, zz
+  float o, rf;                // opacity, sqrt(2 ln(255 o))
+  float qinv;                 // 1 / |q|
+  float qn[4];
+  bool valid;
+};
+
+template <int DEG>
+__device__ __forceinline__ FrameGeom frame_geom(const GaussFrame<DEG>& g) {
+  FrameGeom fg;
+  const float qq = g.q[0] * g.q[0] + g.q[1] * g.q[1] + g.q[2] * g.q[2] + g.q[3] * g.q[3];
+  fg.valid = qq > 0.f;
+  fg.qinv = fg.valid ? 1.0f / sqrtf(qq) : 0.f;
+  for (int c = 0; c < 4; ++c) fg.qn[c] = g.q[c] * fg.qinv;
+  quat_rot(fg.qn[0], fg.qn[1], fg.qn[2], fg.qn[3], fg.R);
+  for (int c = 0; c < 3; ++c) {
+    const float s = expf(g.ls[c]);
+    fg.s2[c] = s * s;
+  }
+  const float* R = fg.R;
+  auto sig = [&](int a, int b) {
+    return R[3 * a] * fg.s2[0] * R[3 * b] + R[3 * a + 1] * fg.s2[1] * R[3 * b + 1] + R[3 * a + 2] * fg.s2[2] * R[3 * b + 2];
+  };
+  fg.Sig[0] = sig(0, 0); fg.Sig[1] = sig(0, 1); fg.Sig[2] = sig(0, 2);
+  fg.Sig[3] = sig(1, 1); fg.Sig[4] = sig(1, 2); fg.Sig[5] = sig(2, 2);
+  fg.o = 1.0f / (1.0f + expf(-g.logit));
+  fg.valid = fg.valid && (255.0f * fg.o >= 1.0f);
+  fg.rf = fg.valid ? sqrtf(2.0f * logf(255.0f * fg.o)) : 0.f;
+  return fg;
+}
+
+// View-level projection of one Gaussian.
+struct ViewProj {
+  float tx, ty, tz, ux, uy;
+  bool clx, cly;
+  float m0[3], m1[3];  // rows of J W
+  float a, b, c;       // 2D covariance (with dilation)
+  float A, B, C;       // conic
+  float mx, my;
+  bool valid;
+};
+
+__device__ __forceinline__ ViewProj view_proj(const RenderDims& d, const gs_camera& cam, const float* mu,
+                                              const FrameGeom& fg) {
+  ViewProj v;
+  v.tz = cam_z(cam, mu[0], mu[1], mu[2]);
+  v.valid = fg.valid && (v.tz > d.near_plane);
+  v.tx = cam_x(cam, mu[0], mu[1], mu[2]);
+  v.ty = cam_y(cam, mu[0], mu[1], mu[2]);
+  const float itz = 1.0f / v.tz;
+  const float limx = 1.3f * (0.5f * (float)d.W / cam.fx);
+  const float limy = 1.3f * (0.5f * (float)d.H / cam.fy);
+  const float rx = v.tx * itz, ry = v.ty * itz;
+  v.clx = (rx > limx) || (rx < -limx);
+  v.cly = (ry > limy) || (ry < -limy);
+  v.ux = fminf(fmaxf(rx, -limx), limx);
+  v.uy = fminf(fmaxf(ry, -limy), limy);
+  const float J00 = cam.fx * itz, J02 = -cam.fx * v.ux * itz;
+  const float J11 = cam.fy * itz, J12 = -cam.fy * v.uy * itz;
+  const float* Wm = cam.viewmat;
+  for (int k = 0; k < 3; ++k) {
+    v.m0[k] = J00 * Wm[k] + J02 * Wm[8 + k];
+    v.m1[k] = J11 * Wm[4 + k] + J12 * Wm[8 + k];
+  }
+  const float* S = fg.Sig;
+  float s0[3], s1[3];  // Sigma m0, Sigma m1
+  s0[0] = S[0] * v.m0[0] + S[1] * v.m0[1] + S[2] * v.m0[2];
+  s0[1] = S[1] * v.m0[0] + S[3] * v.m0[1] + S[4] * v.m0[2];
+  s0[2] = S[2] * v.m0[0] + S[4] * v.m0[1] + S[5] * v.m0[2];
+  s1[0] = S[0] * v.m1[0] + S[1] * v.m1[1] + S[2] * v.m1[2];
+  s1[1] = S[1] * v.m1[0] + S[3] * v.m1[1] + S[4] * v.m1[2];
+  s1[2] = S[2] * v.m1[0] + S[4] * v.m1[1] + S[5] * v.m1[2];
+  v.a = v.m0[0] * s0[0] + v.m0[1] * s0[1] + v.m0[2] * s0[2] + d.dilation;
+  v.b = v.m0[0] * s1[0] + v.m0[1] * s1[1] + v.m0[2] * s1[2];
+  v.c = v.m1[0] * s1[0] + v.m1[1] * s1[1] + v.m1[2] * s1[2] + d.dilation;
+  const float det = v.a * v.c - v.b * v.b;
+  v.valid = v.valid && (det > 0.f);
+  const float idet = 1.0f / det;
+  v.A = v.c * idet;
+  v.B = -v.b * idet;
+  v.C = v.a * idet;
+  v.mx = cam.fx * v.tx * itz + cam.cx;
+  v.my = cam.fy * v.ty * itz + cam.cy;
+  v.valid = v.valid && isfinite(v.mx) && isfinite(v.my) && isfinite(v.A) && isfinite(v.B) && isfinite(v.C);
+  return v;
+}
+
+__device__ __forceinline__ void cam_center(const gs_camera& c, float* p) {
+  const float* Wm = c.viewmat;
+  for (int a = 0; a < 3; ++a) p[a] = -(Wm[a] * Wm[3] + Wm[4 + a] * Wm[7] + Wm[8 + a] * Wm[11]);
+}
+
+template <int DEG>
+__device__ __forceinline__ void view_color(const gs_camera& cam, const GaussFrame<DEG>& g, float* rgb, float* raw,
+                                           float* dir, float* inv_len, float* Y) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  float cp[3];
+  cam_center(cam, cp);
+  float v0 = g.mu[0] - cp[0], v1 = g.mu[1] - cp[1], v2 = g.mu[2] - cp[2];
+  const float il = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+  dir[0] = v0 * il; dir[1] = v1 * il; dir[2] = v2 * il;
+  *inv_len = il;
+  sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
+  for (int c = 0; c < 3; ++c) {
+    float acc = 0.5f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = fmaf(g.sh[3 * k + c], Y[k], acc);
+    raw[c] = acc;
+    rgb[c] = fmaxf(acc, 0.f);
+  }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_fwd(RenderDims d, const float* __restrict__ P,
+                                                     const float* __restrict__ comp,
+                                                     const gs_camera* __restrict__ cams, float4* __restrict__ rec,
+                                                     uint2* __restrict__ rects, uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  GaussFrame<DEG> g;
+  for (int f = 0; f < d.F; ++f) {
+    load_frame<DEG>(d, P, comp, d.Rc ? f : -1, i, g);
+    const FrameGeom fg = frame_geom<DEG>(g);
+    for (int v = 0; v < d.V; ++v) {
+      const int b = f * d.V + v;
+      const gs_camera cam = cams[b];
+      const size_t bi = (size_t)b * d.n + i;
+      uint32_t key = 0xFFFFFFFFu;
+      const ViewProj vp = view_proj(d, cam, g.mu, fg);
+      if (vp.valid) {
+        const float mid = 0.5f * (vp.a + vp.c);
+        const float hd = 0.5f * (vp.a - vp.c);
+        const float lmax = mid + sqrtf(fmaxf(0.f, hd * hd + vp.b * vp.b));
+        const float r = ceilf(fg.rf * sqrtf(lmax)) + 1.0f;
+        const float ulo = (vp.mx - r - 0.5f) * (1.0f / kTile), uhi = (vp.mx + r - 0.5f) * (1.0f / kTile);
+        const float vlo = (vp.my - r - 0.5f) * (1.0f / kTile), vhi = (vp.my + r - 0.5f) * (1.0f / kTile);
+        const int x0 = (int)floorf(fmaxf(ulo, -1.f)), x1 = (int)floorf(fminf(uhi, (float)d.TX));
+        const int y0 = (int)floorf(fmaxf(vlo, -1.f)), y1 = (int)floorf(fminf(vhi, (float)d.TY));
+        const int cx0 = max(x0, 0), cx1 = min(x1, d.TX - 1), cy0 = max(y0, 0), cy1 = min(y1, d.TY - 1);
+        if (isfinite(r) && cx0 <= cx1 && cy0 <= cy1) {
+          float rgb[3], raw[3], dir[3], il, Y[K];
+          view_color<DEG>(cam, g, rgb, raw, dir, &il, Y);
+          rec[3 * bi + 0] = make_float4(vp.mx, vp.my, vp.A, vp.B);
+          rec[3 * bi + 1] = make_float4(vp.C, fg.o, rgb[0], rgb[1]);
+          rec[3 * bi + 2] = make_float4(rgb[2], vp.tz, 0.f, 0.f);
+          rects[bi] = make_uint2((uint32_t)cx0 | ((uint32_t)cx1 << 16), (uint32_t)cy0 | ((uint32_t)cy1 << 16));
+          key = __float_as_uint(vp.tz);
+        }
+      }
+      keys[bi] = key;
+      vals[bi] = (uint32_t)i;
+    }
+  }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_bwd(RenderDims d, const float* __restrict__ P,
+                                                     const float* __restrict__ comp,
+                                                     const gs_camera* __restrict__ cams,
+                                                     const float* __restrict__ g2d, float* __restrict__ dP,
+                                                     float* __restrict__ dcomp) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const size_t n = d.n;
+  GaussFrame<DEG> g;
+  float t_mu[3] = {0, 0, 0}, t_ls[3] = {0, 0, 0}, t_q[4] = {0, 0, 0, 0}, t_lg = 0.f;
+  float t_sh[3 * K];
+#pragma unroll
+  for (int c = 0; c < 3 * K; ++c) t_sh[c] = 0.f;
+  for (int f = 0; f < d.F; ++f) {
+    load_frame<DEG>(d, P, comp, d.Rc ? f : -1, i, g);
+    const FrameGeom fg = frame_geom<DEG>(g);
+    if (!fg.valid) continue;
+    float Gs[6] = {0, 0, 0, 0, 0, 0};  // (G + G^T) of dL/dSigma: xx, xy, xz, yy, yz, zz
+    float dmu[3] = {0, 0, 0}, dlg = 0.f;
+    float dsh[3 * K];
+#pragma unroll
+    for (int c = 0; c < 3 * K; ++c) dsh[c] = 0.f;
+    for (int v = 0; v < d.V; ++v) {
+      const int b = f * d.V + v;
+      float gr[9];
+      bool any = false;
+      for (int c = 0; c < 9; ++c) {
+        gr[c] = g2d[((size_t)b * 9 + c) * n + i];
+        any = any || (gr[c] != 0.f);
+      }
+      if (!any) continue;
+      const gs_camera cam = cams[b];
+      const ViewProj vp = view_proj(d, cam, g.mu, fg);
+      if (!vp.valid) continue;
+      // conic (A, B, C) -> covariance (a, b, c)
+      const float A = vp.A, B = vp.B, C = vp.C;
+      const float gA = gr[2], gB = gr[3], gC = gr[4];
+      const float ga = -(gA * A * A + gB * A * B + gC * B * B);
+      const float gb = -(2.f * gA * A * B + gB * (A * C + B * B) + 2.f * gC * B * C);
+      const float gc = -(gA * B * B + gB * B * C + gC * C * C);
+      // covariance -> Sigma (symmetrised) and M = J W
+      const float* S = fg.Sig;
+      const float* m0 = vp.m0;
+      const float* m1 = vp.m1;
+      Gs[0] += 2.f * ga * m0[0] * m0[0] + 2.f * gb * m0[0] * m1[0] + 2.f * gc * m1[0] * m1[0];
+      Gs[1] += 2.f * ga * m0[0] * m0[1] + gb * (m0[0] * m1[1] + m1[0] * m0[1]) + 2.f * gc * m1[0] * m1[1];
+      Gs[2] += 2.f * ga * m0[0] * m0[2] + gb * (m0[0] * m1[2] + m1[0] * m0[2]) + 2.f * gc * m1[0] * m1[2];
+      Gs[3] += 2.f * ga * m0[1] * m0[1] + 2.f * gb * m0[1] * m1[1] + 2.f * gc * m1[1] * m1[1];
+      Gs[4] += 2.f * ga * m0[1] * m0[2] + gb * (m0[1] * m1[2] + m1[1] * m0[2]) + 2.f * gc * m1[1] * m1[2];
+      Gs[5] += 2.f * ga * m0[2] * m0[2] + 2.f * gb * m0[2] * m1[2] + 2.f * gc * m1[2] * m1[2];
+      float s0[3], s1[3];
+      s0[0] = S[0] * m0[0] + S[1] * m0[1] + S[2] * m0[2];
+      s0[1] = S[1] * m0[0] + S[3] * m0[1] + S[4] * m0[2];
+      s0[2] = S[2] * m0[0] + S[4] * m0[1] + S[5] * m0[2];
+      s1[0] = S[0] * m1[0] + S[1] * m1[1] + S[2] * m1[2];
+      s1[1] = S[1] * m1[0] + S[3] * m1[1] + S[4] * m1[2];
+      s1[2] = S[2] * m1[0] + S[4] * m1[1] + S[5] * m1[2];
+      float dm0[3], dm1[3];
+      for (int k = 0; k < 3; ++k) {
+        dm0[k] = 2.f * ga * s0[k] + gb * s1[k];
+        dm1[k] = gb * s0[k] + 2.f * gc * s1[k];
+      }
+      const float* Wm = cam.viewmat;
+      const float dJ00 = dm0[0] * Wm[0] + dm0[1] * Wm[1] + dm0[2] * Wm[2];
+      const float dJ02 = dm0[0] * Wm[8] + dm0[1] * Wm[9] + dm0[2] * Wm[10];
+      const float dJ11 = dm1[0] * Wm[4] + dm1[1] * Wm[5] + dm1[2] * Wm[6];
+      const float dJ12 = dm1[0] * Wm[8] + dm1[1] * Wm[9] + dm1[2] * Wm[10];
+      const float itz = 1.0f / vp.tz, itz2 = itz * itz;
+      float dtx = 0.f, dty = 0.f, dtz = 0.f;
+      dtz += -(dJ00 * cam.fx + dJ11 * cam.fy) * itz2;
+      if (!vp.clx) {
+        dtx += -dJ02 * cam.fx * itz2;
+        dtz += 2.f * dJ02 * cam.fx * vp.tx * itz2 * itz;
+      } else {
+        dtz += dJ02 * cam.fx * vp.ux * itz2;
+      }
+      if (!vp.cly) {
+        dty += -dJ12 * cam.fy * itz2;
+        dtz += 2.f * dJ12 * cam.fy * vp.ty * itz2 * itz;
+      } else {
+        dtz += dJ12 * cam.fy * vp.uy * itz2;
+      }
+      // mean2D
+      dtx += gr[0] * cam.fx * itz;
+      dty += gr[1] * cam.fy * itz;
+      dtz += -(gr[0] * cam.fx * vp.tx + gr[1] * cam.fy * vp.ty) * itz2;
+      for (int k = 0; k < 3; ++k) dmu[k] += Wm[k] * dtx + Wm[4 + k] * dty + Wm[8 + k] * dtz;
+      // opacity
+      dlg += gr[5] * fg.o * (1.f - fg.o);
+      // colour
+      float rgb[3], raw[3], dir[3], il, Y[K];
+      view_color<DEG>(cam, g, rgb, raw, dir, &il, Y);
+      float gcol[3];
+      for (int c = 0; c < 3; ++c) gcol[c] = raw[c] < 0.f ? 0.f : gr[6 + c];
+      float wk[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        dsh[3 * k + 0] += gcol[0] * Y[k];
+        dsh[3 * k + 1] += gcol[1] * Y[k];
+        dsh[3 * k + 2] += gcol[2] * Y[k];
+        wk[k] = gcol[0] * g.sh[3 * k] + gcol[1] * g.sh[3 * k + 1] + gcol[2] * g.sh[3 * k + 2];
+      }
+      if constexpr (DEG > 0) {
+        float gd[3];
+        sh_basis_grad<DEG>(dir[0], dir[1], dir[2], wk, gd);
+        const float dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
+        for (int k = 0; k < 3; ++k) dmu[k] += (gd[k] - dir[k] * dd) * il;
+      }
+    }
+    // Sigma = R D R^T:  dL/dR = Gs R D,  dL/ds2_j = 1/2 (R^T Gs R)_jj
+    const float* R = fg.R;
+    const float Gm[9] = {Gs[0], Gs[1], Gs[2], Gs[1], Gs[3], Gs[4], Gs[2], Gs[4], Gs[5]};
+    float dR[9];
+    for (int a = 0; a < 3; ++a)
+      for (int j = 0; j < 3; ++j)
+        dR[3 * a + j] = (Gm[3 * a] * R[j] + Gm[3 * a + 1] * R[3 + j] + Gm[3 * a + 2] * R[6 + j]) * fg.s2[j];
+    float dls[3];
+    for (int j = 0; j < 3; ++j) {
+      float acc = 0.f;
+      for (int a = 0; a < 3; ++a)
+        for (int b2 = 0; b2 < 3; ++b2) acc += R[3 * a + j] * Gm[3 * a + b2] * R[3 * b2 + j];
+      dls[j] = acc * fg.s2[j];  // 1/2 * (R^T Gs R)_jj * d(s^2)/d(log s) = (.)_jj * s^2
+    }
+    const float w = fg.qn[0], x = fg.qn[1], y = fg.qn[2], z = fg.qn[3];
+    float dqn[4];
+    dqn[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dqn[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                    2.f * x * dR[8]);
+    dqn[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                    2.f * y * dR[8]);
+    dqn[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] +
+                    x * dR[6] + y * dR[7]);
+    const float qd = dqn[0] * fg.qn[0] + dqn[1] * fg.qn[1] + dqn[2] * fg.qn[2] + dqn[3] * fg.qn[3];
+    float dq[4];
+    for (int c = 0; c < 4; ++c) dq[c] = (dqn[c] - fg.qn[c] * qd) * fg.qinv;
+    if (d.Rc > 0) {
+      float* df = dcomp + (size_t)f * d.Rc * n;
+      for (int c = 0; c < 3; ++c) df[c * n + i] = dmu[c];
+      for (int c = 0; c < 4; ++c) df[(3 + c) * n + i] = dq[c];
+      df[7 * n + i] = dlg;
+      if (d.Rc >= 11) {
+        for (int c = 0; c < 3; ++c) df[(8 + c) * n + i] = dls[c];
+      } else {
+        for (int c = 0; c < 3; ++c) t_ls[c] += dls[c];
+      }
+      if (d.Rc > 11) {
+#pragma unroll
+        for (int c = 0; c < 3 * K; ++c) df[(11 + c) * n + i] = dsh[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3 * K; ++c) t_sh[c] += dsh[c];
+      }
+    } else {
+      for (int c = 0; c < 3; ++c) { t_mu[c] += dmu[c]; t_ls[c] += dls[c]; }
+      for (int c = 0; c < 4; ++c) t_q[c] += dq[c];
+      t_lg += dlg;
+#pragma unroll
+      for (int c = 0; c < 3 * K; ++c) t_sh[c] += dsh[c];
+    }
+  }
+  if (d.Rc == 0) {
+    for (int c = 0; c < 3; ++c) dP[c * n + i] += t_mu[c];
+    for (int c = 0; c < 4; ++c) dP[(6 + c) * n + i] += t_q[c];
+    dP[10 * n + i] += t_lg;
+  }
+  if (d.Rc < 11)
+    for (int c = 0; c < 3; ++c) dP[(3 + c) * n + i] += t_ls[c];
+  if (d.Rc <= 11) {
+#pragma unroll
+    for (int c = 0; c < 3 * K; ++c) dP[(11 + c) * n + i] += t_sh[c];
+  }
+}
+
+// ============================================================ radix sort
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+__device__ __forceinline__ uint32_t popc_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(RenderDims d, const uint32_t* __restrict__ keys,
+                                                            uint32_t* __restrict__ hist, int shift) {
+  __shared__ uint32_t h[256];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int b = blockIdx.y, chunk = blockIdx.x;
+  const size_t seg = (size_t)b * d.n;
+  const int start = chunk * kSortChunk;
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int e = start + it * kSortThreads + t;
+    if (e < d.n) atomicAdd(&h[(keys[seg + e] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[((size_t)b * 256 + t) * d.n_sort_chunks + chunk] = h[t];
+}
+
+// Exclusive scan of one segment's [256][chunks] digit-major histogram.
+__global__ __launch_bounds__(1024) void k_radix_scan(RenderDims d, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t part[1024];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int total = 256 * d.n_sort_chunks;
+  uint32_t* h = hist + (size_t)b * total;
+  const int per = (total + 1023) / 1024;
+  const int lo = t * per, hi = min(lo + per, total);
+  uint32_t s = 0;
+  for (int j = lo; j < hi; ++j) s += h[j];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;
+  for (int j = lo; j < hi; ++j) {
+    const uint32_t v = h[j];
+    h[j] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RenderDims d, const uint32_t* __restrict__ kin,
+                                                               const uint32_t* __restrict__ vin,
+                                                               uint32_t* __restrict__ kout,
+                                                               uint32_t* __restrict__ vout,
+                                                               const uint32_t* __restrict__ hist, int shift) {
+  __shared__ uint32_t goff[256], base[256];
+  __shared__ uint32_t wcnt[4][256], woff[4][256];
+  const int t = threadIdx.x, w = t >> 6;
+  const int b = blockIdx.y, chunk = blockIdx.x;
+  const size_t seg = (size_t)b * d.n;
+  goff[t] = hist[((size_t)b * 256 + t) * d.n_sort_chunks + chunk];
+  base[t] = 0;
+  for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
+  __syncthreads();
+  const int start = chunk * kSortChunk;
+  for (int it = 0; it < kSortItems; ++it) {
+    const int e = start + it * kSortThreads + t;
+    const bool valid = e < d.n;
+    uint32_t key = 0, val = 0, dg = 0;
+    if (valid) {
+      key = kin[seg + e];
+      val = vin[seg + e];
+      dg = (key >> shift) & 255u;
+    }
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (dg >> bit) & 1u;
+      const unsigned long long bb = __ballot(valid && on);
+      peers &= on ? bb : ~bb;
+    }
+    const uint32_t rank = popc_below(peers);
+    if (valid && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    {
+      uint32_t run = base[t];
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t c = wcnt[k][t];
+        woff[k][t] = run;
+        wcnt[k][t] = 0;
+        run += c;
+      }
+      base[t] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = goff[dg] + woff[w][dg] + rank;
+      kout[seg + pos] = key;
+      vout[seg + pos] = val;
+    }
+  }
+}
+
+// ============================================================ binning
+// Each wave walks kBinChunk depth-sorted Gaussians of one frame-view in order;
+// its 64 lanes cover the tiles of one Gaussian at a time, so the per-tile
+// counters in LDS see the Gaussians in depth order (a stable counting sort).
+__device__ __forceinline__ void rect_unpack(uint2 r, int& x0, int& x1, int& y0, int& y1) {
+  x0 = r.x & 0xFFFF; x1 = r.x >> 16; y0 = r.y & 0xFFFF; y1 = r.y >> 16;
+}
+
+template <bool EMIT>
+__global__ __launch_bounds__(64) void k_bin(RenderDims d, const uint32_t* __restrict__ skeys,
+                                            const uint32_t* __restrict__ svals, const uint2* __restrict__ rects,
+                                            uint32_t* __restrict__ bhist, const uint2* __restrict__ ranges,
+                                            uint32_t* __restrict__ lists) {
+  extern __shared__ uint32_t cnt[];
+  const int lane = threadIdx.x;
+  const int b = blockIdx.y, chunk = blockIdx.x;
+  const int T = d.T;
+  uint32_t* bh = bhist + ((size_t)b * d.n_bin_chunks + chunk) * T;
+  for (int t = lane; t < T; t += 64) cnt[t] = EMIT ? ranges[(size_t)b * T + t].x + bh[t] : 0u;
+  __syncthreads();
+  const size_t seg = (size_t)b * d.n;
+  const int start = chunk * kBinChunk;
+  const int end = min(start + kBinChunk, d.n);
+  for (int base = start; base < end; base += 64) {
+    const int e = base + lane;
+    uint32_t idx = 0;
+    uint2 rc = make_uint2(1u, 0u);  // empty: x0 = 1 > x1 = 0
+    bool ok = false;
+    if (e < end) {
+      ok = skeys[seg + e] != 0xFFFFFFFFu;
+      if (ok) {
+        idx = svals[seg + e];
+        rc = rects[seg + idx];
+      }
+    }
+    const unsigned long long live = __ballot(ok);
+    if (live == 0ull) break;  // culled keys sort last
+    const int nlive = 64 - __clzll(live);  // keys are sorted, so live lanes are a prefix
+    for (int j = 0; j < nlive; ++j) {
+      const uint32_t gi = __shfl(idx, j);
+      uint2 r;
+      r.x = __shfl(rc.x, j);
+      r.y = __shfl(rc.y, j);
+      int x0, x1, y0, y1;
+      rect_unpack(r, x0, x1, y0, y1);
+      const int w = x1 - x0 + 1, h = y1 - y0 + 1;
+      const int total = w * h;
+      for (int l = lane; l < total; l += 64) {
+        const int ly = l / w;
+        const int tile = (y0 + ly) * d.TX + x0 + (l - ly * w);
+        if (EMIT) {
+          const uint32_t pos = cnt[tile];
+          if (pos < d.capacity) lists[pos] = gi;
+          cnt[tile] = pos + 1;
+        } else {
+          cnt[tile] += 1u;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!EMIT)
+    for (int t = lane; t < T; t += 64) bh[t] = cnt[t];
+}
+
+// Per (frame-view, tile): exclusive prefix over chunks, total count.
+__global__ __launch_bounds__(256) void k_bin_chunk_scan(RenderDims d, uint32_t* __restrict__ bhist,
+                                                        uint32_t* __restrict__ tot) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.B * d.T) return;
+  const int b = g / d.T, t = g - b * d.T;
+  uint32_t run = 0;
+  for (int c = 0; c < d.n_bin_chunks; ++c) {
+    const size_t o = ((size_t)b * d.n_bin_chunks + c) * d.T + t;
+    const uint32_t v = bhist[o];
+    bhist[o] = run;
+    run += v;
+  }
+  tot[g] = run;
+}
+
+// Exclusive scan over all (frame-view, tile) totals -> list ranges; flags overflow.
+__global__ __launch_bounds__(1024) void k_tile_ranges(RenderDims d, const uint32_t* __restrict__ tot,
+                                                      uint2* __restrict__ ranges, Status* __restrict__ st) {
+  __shared__ unsigned long long part[1024];
+  const int t = threadIdx.x;
+  const int total = d.B * d.T;
+  const int per = (total + 1023) / 1024;
+  const int lo = t * per, hi = min(lo + per, total);
+  unsigned long long s = 0;
+  for (int j = lo; j < hi; ++j) s += tot[j];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    unsigned long long v = t >= off ? part[t - off] : 0ull;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  unsigned long long run = part[t] - s;
+  for (int j = lo; j < hi; ++j) {
+    const uint32_t v = tot[j];
+    const unsigned long long e = run + v;
+    ranges[j] = make_uint2((uint32_t)min(run, 0xFFFFFFFFull), (uint32_t)min(e, 0xFFFFFFFFull));
+    run = e;
+  }
+  if (t == 1023) {
+    st->needed_pairs = part[1023];
+    st->overflow = part[1023] > d.capacity ? 1u : 0u;
+    st->fwd_evals = 0;
+    st->fwd_contribs = 0;
+  }
+}
+
+// ============================================================ rasterization
+struct TileCtx {
+  int b, tile, px, py;
+  bool inside;
+  uint2 range;
+};
+
+__device__ __forceinline__ bool tile_ctx(const RenderDims& d, const uint2* ranges, TileCtx& c) {
+  const int per = (d.B * d.T + 7) / 8;
+  const int wid = xcd_item(blockIdx.x, per);
+  if (wid >= d.B * d.T) return false;
+  c.b = wid / d.T;
+  c.tile = wid - c.b * d.T;
+  const int tx = c.tile % d.TX, ty = c.tile / d.TX;
+  c.px = tx * kTile + (threadIdx.x & (kTile - 1));
+  c.py = ty * kTile + (threadIdx.x / kTile);
+  c.inside = c.px < d.W && c.py < d.H;
+  c.range = ranges[(size_t)c.b * d.T + c.tile];
+  return true;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off);
+  return v;
+}
+
+// Adds the per-thread work counters of a block to the status word (one atomic per wave).
+__device__ __forceinline__ void flush_counters(uint32_t evals, uint32_t contribs, unsigned long long* e,
+                                               unsigned long long* c) {
+  evals = wave_sum_u(evals);
+  contribs = wave_sum_u(contribs);
+  if ((threadIdx.x & 63) == 0) {
+    if (evals) atomicAdd(e, (unsigned long long)evals);
+    if (contribs) atomicAdd(c, (unsigned long long)contribs);
+  }
+}
+
+template <int MAXL>
+__global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* __restrict__ st,
+                                                         const uint2* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ lists,
+                                                         const float4* __restrict__ rec, float* __restrict__ image,
+                                                         float* __restrict__ t_final, uint32_t* __restrict__ n_last) {
+  if (st->overflow) return;
+  TileCtx c;
+  if (!tile_ctx(d, ranges, c)) return;
+  __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
+  __shared__ float4 s_b[kTilePix];  // conic A, B, C
+  __shared__ float4 s_c[kTilePix];  // r, g, b
+  const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
+  float Tr[MAXL], Cr[MAXL], Cg[MAXL], Cb[MAXL];
+  uint32_t last[MAXL];
+#pragma unroll
+  for (int l = 0; l < MAXL; ++l) { Tr[l] = 1.f; Cr[l] = Cg[l] = Cb[l] = 0.f; last[l] = 0; }
+  uint32_t alive = c.inside ? ((1u << d.L) - 1u) : 0u;
+  uint32_t nlhi = alive ? (uint32_t)d.lv[d.L - 1] : 0u;
+  const size_t recbase = (size_t)c.b * d.n;
+  const int t = threadIdx.x;
+  uint32_t n_eval = 0, n_contrib = 0;
+  for (uint32_t base = c.range.x; base < c.range.y; base += kTilePix) {
+    if (__syncthreads_count(alive != 0u) == 0) break;
+    const uint32_t k = base + t;
+    if (k < c.range.y) {
+      const uint32_t gi = lists[k];
+      const float4* r = rec + 3 * (recbase + gi);
+      const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+      s_a[t] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
+      s_b[t] = make_float4(r0.z, r0.w, r1.x, 0.f);
+      s_c[t] = make_float4(r1.z, r1.w, r2.x, 0.f);
+    }
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)kTilePix, c.range.y - base);
+    if (alive) {
+      for (int j = 0; j < cnt; ++j) {
+        const float4 a = s_a[j];
+        const uint32_t gi = __float_as_uint(a.w);
+        if (gi >= nlhi) continue;
+        const float4 cb = s_b[j];
+        const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
+        ++n_eval;
+        if (!(ev.ga >= d.alpha_min)) continue;
+        const float al = fminf(d.alpha_max, ev.ga);
+        const float oma = 1.f - al;
+        const float4 col = s_c[j];
+#pragma unroll
+        for (int l = 0; l < MAXL; ++l) {
+          if (!((alive >> l) & 1u) || gi >= (uint32_t)d.lv[l]) continue;
+          const float Tn = Tr[l] * oma;
+          if (Tn < d.t_stop) {
+            alive &= ~(1u << l);
+            continue;
+          }
+          const float wgt = al * Tr[l];
+          Cr[l] = fmaf(col.x, wgt, Cr[l]);
+          Cg[l] = fmaf(col.y, wgt, Cg[l]);
+          Cb[l] = fmaf(col.z, wgt, Cb[l]);
+          Tr[l] = Tn;
+          last[l] = base + j + 1 - c.range.x;
+          ++n_contrib;
+        }
+        if (!alive) break;
+        nlhi = (uint32_t)d.lv[31 - __clz(alive)];
+      }
+    }
+  }
+  flush_counters(n_eval, n_contrib, &st->fwd_evals, &st->fwd_contribs);
+  if (!c.inside) return;
+  const size_t HW = (size_t)d.W * d.H;
+  const size_t pix = (size_t)c.py * d.W + c.px;
+#pragma unroll
+  for (int l = 0; l < MAXL; ++l) {
+    if (l >= d.L) break;
+    const size_t o = (size_t)c.b * d.L + l;
+    image[(o * 3 + 0) * HW + pix] = fmaf(Tr[l], d.bg[0], Cr[l]);
+    image[(o * 3 + 1) * HW + pix] = fmaf(Tr[l], d.bg[1], Cg[l]);
+    image[(o * 3 + 2) * HW + pix] = fmaf(Tr[l], d.bg[2], Cb[l]);
+    t_final[o * HW + pix] = Tr[l];
+    n_last[o * HW + pix] = last[l];
+  }
+}
+
+template <int MAXL>
+__global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* __restrict__ st,
+                                                         const uint2* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ lists,
+                                                         const float4* __restrict__ rec,
+                                                         const float* __restrict__ t_final,
+                                                         const uint32_t* __restrict__ n_last,
+                                                         const float* __restrict__ image,
+                                                         const float* __restrict__ d_image,
+                                                         const float* __restrict__ target,
+                                                         float* __restrict__ g2d, float* __restrict__ loss_out) {
+  if (st->overflow) return;
+  TileCtx c;
+  if (!tile_ctx(d, ranges, c)) return;
+  __shared__ float4 s_a[kTilePix];
+  __shared__ float4 s_b[kTilePix];
+  __shared__ float4 s_c[kTilePix];
+  __shared__ uint32_t s_kmax;
+  __shared__ float s_loss;
+  const int t = threadIdx.x;
+  if (t == 0) { s_kmax = 0; s_loss = 0.f; }
+  __syncthreads();
+  const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
+  const size_t HW = (size_t)d.W * d.H;
+  const size_t pix = (size_t)c.py * d.W + c.px;
+  float Tr[MAXL], wr[MAXL], wg[MAXL], wb[MAXL], Sr[MAXL], Sg[MAXL], Sb[MAXL];
+  uint32_t last[MAXL];
+  uint32_t kmax = 0;
+  float loss = 0.f;
+  const float inv3hw = 1.0f / (3.0f * (float)HW);
+#pragma unroll
+  for (int l = 0; l < MAXL; ++l) {
+    Tr[l] = 0.f; wr[l] = wg[l] = wb[l] = 0.f; last[l] = 0;
+    if (c.inside && l < d.L) {
+      const size_t o = (size_t)c.b * d.L + l;
+      Tr[l] = t_final[o * HW + pix];
+      last[l] = n_last[o * HW + pix];
+      float w3[3];
+      for (int ch = 0; ch < 3; ++ch) {
+        if (d_image) {
+          w3[ch] = d_image[(o * 3 + ch) * HW + pix];
+        } else {
+          const float diff = image[(o * 3 + ch) * HW + pix] - target[((size_t)c.b * 3 + ch) * HW + pix];
+          const float sgn = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
+          w3[ch] = d.lw[l] * sgn * inv3hw;
+          loss += d.lw[l] * fabsf(diff) * inv3hw;
+        }
+      }
+      wr[l] = w3[0]; wg[l] = w3[1]; wb[l] = w3[2];
+      kmax = max(kmax, last[l]);
+    }
+    Sr[l] = Tr[l] * d.bg[0]; Sg[l] = Tr[l] * d.bg[1]; Sb[l] = Tr[l] * d.bg[2];
+  }
+  if (loss_out) {
+    loss = wave_sum(loss);
+    if ((t & 63) == 0) atomicAdd(&s_loss, loss);
+  }
+  atomicMax(&s_kmax, kmax);
+  __syncthreads();
+  if (loss_out && t == 0) unsafeAtomicAdd(loss_out, s_loss);
+  const uint32_t ktop = s_kmax;
+  const size_t recbase = (size_t)c.b * d.n;
+  const int lane = t & 63;
+  uint32_t n_eval = 0, n_contrib = 0;
+  for (int top = (int)ktop; top > 0; top -= kTilePix) {
+    const int lo = max(0, top - kTilePix);
+    const int cnt = top - lo;
+    __syncthreads();
+    if (t < cnt) {
+      const uint32_t gi = lists[c.range.x + lo + t];
+      const float4* r = rec + 3 * (recbase + gi);
+      const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+      s_a[t] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
+      s_b[t] = make_float4(r0.z, r0.w, r1.x, 0.f);
+      s_c[t] = make_float4(r1.z, r1.w, r2.x, 0.f);
+    }
+    __syncthreads();
+    for (int j = cnt - 1; j >= 0; --j) {
+      const uint32_t k = (uint32_t)(lo + j);
+      const float4 a = s_a[j];
+      const uint32_t gi = __float_as_uint(a.w);
+      bool cand = false;
+#pragma unroll
+      for (int l = 0; l < MAXL; ++l) cand = cand || (k < last[l] && gi < (uint32_t)d.lv[l]);
+      float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      bool contrib = false;
+      if (cand) {
+        const float4 cb = s_b[j];
+        const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
+        ++n_eval;
+        if (ev.ga >= d.alpha_min) {
+          const float al = fminf(d.alpha_max, ev.ga);
+          const float oma = 1.f - al;
+          const float ioma = 1.0f / oma;
+          const float4 col = s_c[j];
+          float dal = 0.f;
+#pragma unroll
+          for (int l = 0; l < MAXL; ++l) {
+            if (!(k < last[l] && gi < (uint32_t)d.lv[l])) continue;
+            const float Tb = Tr[l] * ioma;  // transmittance in front of this Gaussian
+            const float wT = al * Tb;
+            g[6] = fmaf(wr[l], wT, g[6]);
+            g[7] = fmaf(wg[l], wT, g[7]);
+            g[8] = fmaf(wb[l], wT, g[8]);
+            dal += wr[l] * (col.x * Tb - Sr[l] * ioma) + wg[l] * (col.y * Tb - Sg[l] * ioma) +
+                   wb[l] * (col.z * Tb - Sb[l] * ioma);
+            Sr[l] = fmaf(col.x, wT, Sr[l]);
+            Sg[l] = fmaf(col.y, wT, Sg[l]);
+            Sb[l] = fmaf(col.z, wT, Sb[l]);
+            Tr[l] = Tb;
+            contrib = true;
+            ++n_contrib;
+          }
+          if (contrib && ev.ga <= d.alpha_max) {
+            g[5] = dal * ev.G;
+            const float dp = dal * ev.ga;
+            g[0] = dp * (cb.x * ev.dx + cb.y * ev.dy);
+            g[1] = dp * (cb.y * ev.dx + cb.z * ev.dy);
+            g[2] = -0.5f * dp * ev.dx * ev.dx;
+            g[3] = -dp * ev.dx * ev.dy;
+            g[4] = -0.5f * dp * ev.dy * ev.dy;
+          }
+        }
+      }
+      if (__ballot(contrib) != 0ull) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) g[m] = wave_sum(g[m]);
+        if (lane == 0) {
+          float* dst = g2d + (size_t)c.b * 9 * d.n + gi;
+#pragma unroll
+          for (int m = 0; m < 9; ++m)
+            if (g[m] != 0.f) unsafeAtomicAdd(dst + (size_t)m * d.n, g[m]);
+        }
+      }
+    }
+  }
+  flush_counters(n_eval, n_contrib, &st->bwd_evals, &st->bwd_contribs);
+}
+
+__global__ void k_zero(uint32_t* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t j = i; j < n; j += stride) p[j] = 0u;
+}
+
+}  // namespace
+
+// ============================================================ launchers
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+  {
+    ProfScope ps_(K_ZERO, st);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, (uint32_t*)p, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_fwd(const RenderDims& d, const float* params, const float* res, float* composed,
+                              hipStream_t st) {
+  {
+    ProfScope ps_(K_COMPOSE_FWD, st);
+    hipLaunchKernelGGL(k_compose_fwd, dim3((d.n + 255) / 256), dim3(256), 0, st, d, params, res, composed);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,
+                              const float* d_composed, float* d_params, float* d_res, hipStream_t st) {
+  {
+    ProfScope ps_(K_COMPOSE_BWD, st);
+    hipLaunchKernelGGL(k_compose_bwd, dim3((d.n + 255) / 256), dim3(256), 0, st, d, params, res, composed, d_composed,
+                     d_params, d_res);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_fwd(const RenderDims& d, const float* params, const float* composed,
+                              const gs_camera* cams, char* ws, const Layout& lo, hipStream_t st) {
+  dim3 grid((d.n + 255) / 256), block(256);
+  float4* rec = (float4*)(ws + lo.records);
+  uint2* rects = (uint2*)(ws + lo.rects);
+  uint32_t* keys = (uint32_t*)(ws + lo.keys0);
+  uint32_t* vals = (uint32_t*)(ws + lo.vals0);
+  ProfScope ps_(K_PROJECT_FWD, st);
+  switch (d.deg) {
+    case 0: hipLaunchKernelGGL(k_project_fwd<0>, grid, block, 0, st, d, params, composed, cams, rec, rects, keys, vals); break;
+    case 1: hipLaunchKernelGGL(k_project_fwd<1>, grid, block, 0, st, d, params, composed, cams, rec, rects, keys, vals); break;
+    case 2: hipLaunchKernelGGL(k_project_fwd<2>, grid, block, 0, st, d, params, composed, cams, rec, rects, keys, vals); break;
+    default: hipLaunchKernelGGL(k_project_fwd<3>, grid, block, 0, st, d, params, composed, cams, rec, rects, keys, vals); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const RenderDims& d, const float* params, const float* composed,
+                              const gs_camera* cams, char* ws, const Layout& lo, float* d_params, hipStream_t st) {
+  dim3 grid((d.n + 255) / 256), block(256);
+  const float* g2d = (const float*)(ws + lo.grad2d);
+  float* dcomp = (float*)(ws + lo.d_composed);
+  ProfScope ps_(K_PROJECT_BWD, st);
+  switch (d.deg) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, st, d, params, composed, cams, g2d, d_params, dcomp); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, st, d, params, composed, cams, g2d, d_params, dcomp); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, st, d, params, composed, cams, g2d, d_params, dcomp); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, st, d, params, composed, cams, g2d, d_params, dcomp); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(const RenderDims& d, char* ws, const Layout& lo, uint32_t** keys_out, uint32_t** vals_out,
+                       hipStream_t st) {
+  uint32_t* k[2] = {(uint32_t*)(ws + lo.keys0), (uint32_t*)(ws + lo.keys1)};
+  uint32_t* v[2] = {(uint32_t*)(ws + lo.vals0), (uint32_t*)(ws + lo.vals1)};
+  uint32_t* hist = (uint32_t*)(ws + lo.sort_hist);
+  dim3 grid(d.n_sort_chunks, d.B);
+  int cur = 0;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 8 * pass;
+    {
+      ProfScope ps_(K_RADIX_HIST, st);
+      hipLaunchKernelGGL(k_radix_hist, grid, dim3(kSortThreads), 0, st, d, k[cur], hist, shift);
+    }
+    {
+      ProfScope ps_(K_RADIX_SCAN, st);
+      hipLaunchKernelGGL(k_radix_scan, dim3(d.B), dim3(1024), 0, st, d, hist);
+    }
+    {
+      ProfScope ps_(K_RADIX_SCATTER, st);
+      hipLaunchKernelGGL(k_radix_scatter, grid, dim3(kSortThreads), 0, st, d, k[cur], v[cur], k[cur ^ 1], v[cur ^ 1],
+                       hist, shift);
+    }
+    cur ^= 1;
+  }
+  *keys_out = k[cur];
+  *vals_out = v[cur];
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t* svals, char* ws, const Layout& lo,
+                      hipStream_t st) {
+  const uint2* rects = (const uint2*)(ws + lo.rects);
+  uint32_t* bhist = (uint32_t*)(ws + lo.bin_hist);
+  uint2* ranges = (uint2*)(ws + lo.ranges);
+  uint32_t* lists = (uint32_t*)(ws + lo.lists);
+  uint32_t* tot = (uint32_t*)(ws + lo.tile_tot);
+  Status* status = (Status*)(ws + lo.status);
+  dim3 grid(d.n_bin_chunks, d.B);
+  const size_t lds = (size_t)d.T * sizeof(uint32_t);
+  if (d.n_bin_chunks > 0)
+    {
+      ProfScope ps_(K_BIN_COUNT, st);
+      hipLaunchKernelGGL(k_bin<false>, grid, dim3(64), lds, st, d, skeys, svals, rects, bhist, ranges, lists);
+    }
+  {
+    ProfScope ps_(K_BIN_CHUNK_SCAN, st);
+    hipLaunchKernelGGL(k_bin_chunk_scan, dim3((d.B * d.T + 255) / 256), dim3(256), 0, st, d, bhist, tot);
+  }
+  {
+    ProfScope ps_(K_TILE_RANGES, st);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(1), dim3(1024), 0, st, d, tot, ranges, status);
+  }
+  if (d.n_bin_chunks > 0)
+    {
+      ProfScope ps_(K_BIN_EMIT, st);
+      hipLaunchKernelGGL(k_bin<true>, grid, dim3(64), lds, st, d, skeys, svals, rects, bhist, ranges, lists);
+    }
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_fwd(const RenderDims& d, char* ws, const Layout& lo, float* image, hipStream_t st) {
+  Status* status = (Status*)(ws + lo.status);
+  const uint2* ranges = (const uint2*)(ws + lo.ranges);
+  const uint32_t* lists = (const uint32_t*)(ws + lo.lists);
+  const float4* rec = (const float4*)(ws + lo.records);
+  float* tf = (float*)(ws + lo.t_final);
+  uint32_t* nl = (uint32_t*)(ws + lo.n_last);
+  const int per = (d.B * d.T + 7) / 8;
+  dim3 grid(per * 8), block(kTilePix);
+  ProfScope ps_(K_RASTER_FWD, st);
+  if (d.L == 1)
+    hipLaunchKernelGGL(k_raster_fwd<1>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+  else if (d.L == 2)
+    hipLaunchKernelGGL(k_raster_fwd<2>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+  else if (d.L <= 4)
+    hipLaunchKernelGGL(k_raster_fwd<4>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+  else if (d.L <= 6)
+    hipLaunchKernelGGL(k_raster_fwd<6>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+  else
+    hipLaunchKernelGGL(k_raster_fwd<8>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, const float* image,
+                             const float* d_image, const float* target, float* loss_out, hipStream_t st) {
+  Status* status = (Status*)(ws + lo.status);
+  const uint2* ranges = (const uint2*)(ws + lo.ranges);
+  const uint32_t* lists = (const uint32_t*)(ws + lo.lists);
+  const float4* rec = (const float4*)(ws + lo.records);
+  const float* tf = (const float*)(ws + lo.t_final);
+  const uint32_t* nl = (const uint32_t*)(ws + lo.n_last);
+  float* g2d = (float*)(ws + lo.grad2d);
+  const int per = (d.B * d.T + 7) / 8;
+  dim3 grid(per * 8), block(kTilePix);
+#define GS_BWD(L_)                                                                                            \
+  hipLaunchKernelGGL(k_raster_bwd<L_>, grid, block, 0, st, d, status, ranges, lists, rec, tf, nl, image, d_image, \
+                     target, g2d, loss_out)
+  ProfScope ps_(K_RASTER_BWD, st);
+  if (d.L == 1) GS_BWD(1);
+  else if (d.L == 2) GS_BWD(2);
+  else if (d.L <= 4) GS_BWD(4);
+  else if (d.L <= 6) GS_BWD(6);
+  else GS_BWD(8);
+#undef GS_BWD
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,198 @@
+"""Python binding of the render entry points: argument marshalling only.
+
+Every step of the forward and backward runs in the HIP kernels of libgs4d.so;
+torch provides the device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib
+from ._lib import GsSettings, GsWorkspaceLayout, check, lib
+
+
+@dataclasses.dataclass
+class RenderSettings:
+    width: int
+    height: int
+    sh_degree: int = 0
+    level_counts: tuple = ()
+    level_weights: tuple = ()
+    res_channels: int = 0
+    near_plane: float = 0.2
+    dilation: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_stop: float = 1e-4
+    bg: tuple = (0.0, 0.0, 0.0)
+
+    def c_struct(self, n: int) -> GsSettings:
+        s = GsSettings()
+        s.width, s.height, s.sh_degree = self.width, self.height, self.sh_degree
+        lv = list(self.level_counts) if self.level_counts else [n]
+        lw = list(self.level_weights) if self.level_weights else [1.0] * len(lv)
+        if len(lv) > 8 or len(lw) != len(lv):
+            raise ValueError("1..8 levels with one weight each")
+        s.n_levels = len(lv)
+        for i in range(len(lv)):
+            s.level_counts[i] = int(lv[i])
+            s.level_weights[i] = float(lw[i])
+        s.res_channels = self.res_channels
+        s.near_plane, s.dilation = self.near_plane, self.dilation
+        s.alpha_min, s.alpha_max, s.t_stop = self.alpha_min, self.alpha_max, self.t_stop
+        for i in range(3):
+            s.bg[i] = self.bg[i]
+        s.tile_w = s.tile_h = 0
+        return s
+
+    @property
+    def n_levels(self):
+        return max(1, len(self.level_counts))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_tensor(t, name, shape=None, dtype=torch.float32, device=None):
+    if t is None:
+        return
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Workspace:
+    """Device workspace of one render configuration. Grows when a forward reports that the
+    (tile, Gaussian) pair list did not fit."""
+
+    def __init__(self, settings: RenderSettings, n: int, n_frames: int, n_views: int, device,
+                 pair_capacity: int | None = None):
+        self.settings, self.n, self.F, self.V, self.device = settings, n, n_frames, n_views, device
+        if pair_capacity is None:
+            pair_capacity = max(1 << 16, 24 * n * n_frames * n_views)
+        self.allocate(pair_capacity)
+
+    def allocate(self, pair_capacity: int):
+        pair_capacity = int(min(pair_capacity, (1 << 32) - 1))
+        s = self.settings.c_struct(self.n)
+        nbytes = ctypes.c_size_t()
+        check(lib().gs_workspace_size(ctypes.byref(s), self.n, self.F, self.V, pair_capacity, ctypes.byref(nbytes)),
+              "gs_workspace_size")
+        self.pair_capacity = pair_capacity
+        self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+
+    @property
+    def nbytes(self):
+        return self.buf.numel()
+
+    def layout(self) -> GsWorkspaceLayout:
+        s = self.settings.c_struct(self.n)
+        lo = GsWorkspaceLayout()
+        check(lib().gs_workspace_describe(ctypes.byref(s), self.n, self.F, self.V, self.pair_capacity,
+                                          ctypes.byref(lo)), "gs_workspace_describe")
+        return lo
+
+    def status(self):
+        """(ok, needed_pairs); synchronises the current stream."""
+        needed = ctypes.c_int64()
+        rc = lib().gs_check_status(_ptr(self.buf), _stream(self.device), ctypes.byref(needed))
+        if rc not in (_lib.GS_OK, _lib.GS_ERR_PAIR_OVERFLOW):
+            check(rc, "gs_check_status")
+        return rc == _lib.GS_OK, needed.value
+
+
+def render_forward(settings: RenderSettings, params: torch.Tensor, cams: torch.Tensor, n_frames: int = 1,
+                   residuals: torch.Tensor | None = None, ws: Workspace | None = None, image: torch.Tensor | None = None,
+                   check_overflow: bool = True):
+    """image [F][V][L][3][H][W]; returns (image, workspace)."""
+    dev = params.device
+    C = 11 + 3 * (settings.sh_degree + 1) ** 2
+    n = params.shape[1]
+    B = cams.shape[0]
+    if params.dim() != 2 or params.shape[0] != C:
+        raise ValueError(f"params must be [{C}][n]")
+    if cams.dim() != 2 or cams.shape[1] != 16 or B % n_frames:
+        raise ValueError("cams must be [n_frames * n_views][16]")
+    V = B // n_frames
+    _check_tensor(params, "params", device=dev)
+    _check_tensor(cams, "cams", device=dev)
+    if residuals is not None:
+        _check_tensor(residuals, "residuals", (n_frames, settings.res_channels, n), device=dev)
+    L = settings.n_levels
+    shape = (n_frames, V, L, 3, settings.height, settings.width)
+    if image is None:
+        image = torch.empty(shape, dtype=torch.float32, device=dev)
+    _check_tensor(image, "image", shape, device=dev)
+    if ws is None:
+        ws = Workspace(settings, n, n_frames, V, dev)
+    s = settings.c_struct(n)
+    for _ in range(3):
+        check(lib().gs_render_forward(ctypes.byref(s), n, _ptr(params), n_frames, _ptr(residuals), V, _ptr(cams),
+                                      _ptr(image), _ptr(ws.buf), ws.nbytes, _stream(dev)), "gs_render_forward")
+        if not check_overflow:
+            break
+        ok, needed = ws.status()
+        if ok:
+            break
+        ws.allocate(int(needed * 1.15) + 1024)
+    else:
+        raise RuntimeError("pair list kept overflowing")
+    return image, ws
+
+
+def render_backward(settings: RenderSettings, params: torch.Tensor, cams: torch.Tensor, ws: Workspace,
+                    n_frames: int = 1, residuals: torch.Tensor | None = None, image: torch.Tensor | None = None,
+                    d_image: torch.Tensor | None = None, target: torch.Tensor | None = None,
+                    d_params: torch.Tensor | None = None, d_residuals: torch.Tensor | None = None,
+                    loss: torch.Tensor | None = None):
+    """Accumulates into d_params [C][n] (and d_residuals); returns (d_params, d_residuals)."""
+    dev = params.device
+    n = params.shape[1]
+    V = cams.shape[0] // n_frames
+    if d_params is None:
+        d_params = torch.zeros_like(params)
+    if residuals is not None and d_residuals is None:
+        d_residuals = torch.zeros_like(residuals)
+    for t, nm in ((d_image, "d_image"), (target, "target"), (image, "image"), (d_params, "d_params"),
+                  (d_residuals, "d_residuals"), (loss, "loss")):
+        _check_tensor(t, nm, device=dev)
+    s = settings.c_struct(n)
+    check(lib().gs_render_backward(ctypes.byref(s), n, _ptr(params), n_frames, _ptr(residuals), V, _ptr(cams),
+                                   _ptr(image), _ptr(d_image), _ptr(target), _ptr(d_params), _ptr(d_residuals),
+                                   _ptr(loss), _ptr(ws.buf), ws.nbytes, _stream(dev)), "gs_render_backward")
+    return d_params, d_residuals
+
+
+class RenderFunction(torch.autograd.Function):
+    """Differentiable render: params (and residuals) -> image [F][V][L][3][H][W]."""
+
+    @staticmethod
+    def forward(ctx, params, residuals, cams, settings, n_frames):
+        image, ws = render_forward(settings, params.detach(), cams, n_frames,
+                                   None if residuals is None else residuals.detach())
+        ctx.settings, ctx.n_frames, ctx.ws = settings, n_frames, ws
+        ctx.save_for_backward(params, residuals, cams)
+        return image
+
+    @staticmethod
+    def backward(ctx, d_image):
+        params, residuals, cams = ctx.saved_tensors
+        dp, dr = render_backward(ctx.settings, params.detach(), cams, ctx.ws, ctx.n_frames,
+                                 None if residuals is None else residuals.detach(),
+                                 d_image=d_image.contiguous())
+        return dp, dr, None, None, None
+
+
+def render(params, cams, settings: RenderSettings, n_frames: int = 1, residuals=None):
+    return RenderFunction.apply(params, residuals, cams, settings, n_frames)

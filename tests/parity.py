@@ -1,0 +1,85 @@
+"""Helpers shared by the parity tests: one place that turns a seeded workload into the
+oracle's and the GPU library's settings, and the comparison rules."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+IMG_TOL = 1e-4  # max-abs on [0, 1] colours
+
+
+def oracle_settings(w, **kw):
+    return oracle.Settings(width=w.width, height=w.height, sh_degree=w.sh_degree, level_counts=tuple(w.level_counts),
+                           res_channels=0 if w.residuals is None else w.residuals.shape[1], **kw)
+
+
+def gpu_settings(w, **kw):
+    from paper_2509_17513_amd import RenderSettings
+    return RenderSettings(width=w.width, height=w.height, sh_degree=w.sh_degree,
+                          level_counts=tuple(w.level_counts), level_weights=tuple(w.level_weights),
+                          res_channels=0 if w.residuals is None else w.residuals.shape[1], **kw)
+
+
+def image_mismatch(gpu_img, ref, tol=IMG_TOL):
+    """gpu_img [B][L][3][H][W] (or [B][L][3][S]) vs oracle render with variants.
+    Returns (n_bad, n_ambiguous, n_excluded, max_err over accepted pixels)."""
+    main = ref["image"]
+    nvar = ref["nvar"]
+    var = ref["var"]
+    err_main = np.abs(gpu_img - main).max(axis=2)  # [B][L][...]
+    ok = err_main <= tol
+    amb = nvar > 0
+    if amb.any():
+        g = np.moveaxis(gpu_img, 2, -1)[amb]  # [m][3]
+        v = var[amb]  # [m][16][3]
+        k = nvar[amb]
+        e = np.abs(v - g[:, None, :]).max(axis=2)  # [m][16]
+        e[np.arange(16)[None, :] >= k[:, None]] = np.inf
+        ok_amb = e.min(axis=1) <= tol
+        ok[amb] = ok[amb] | ok_amb
+    excl = nvar < 0
+    ok[excl] = True
+    accepted = (~excl) & (~amb)
+    max_err = float(err_main[accepted].max()) if accepted.any() else 0.0
+    return int((~ok).sum()), int(amb.sum()), int(excl.sum()), max_err
+
+
+def l1_dimage(ref, target, level_weights):
+    """dL/dC of the layer-weighted mean L1 from the oracle's image, zero at ambiguous or excluded
+    pixel-levels and where |C - target| is within 1e-5 (a sign the float32 image may take the other way)."""
+    img = ref["image"]
+    g = oracle.l1_grad(img, target, level_weights)
+    g[np.abs(img - target[:, None].astype(np.float64)) < 1e-5] = 0.0
+    mask = (ref["nvar"] != 0)[:, :, None]
+    g = np.where(mask, 0.0, g)
+    return g
+
+
+def grad_mismatch(g, ref, groups, rtol=1e-3, floor=1e-3):
+    """|g - ref| <= rtol |ref| + floor * RMS(ref over the channel group). Returns (n_bad, worst ratio)."""
+    bad = 0
+    worst = 0.0
+    for lo, hi in groups:
+        r = ref[lo:hi]
+        x = g[lo:hi]
+        rms = float(np.sqrt(np.mean(r ** 2))) + 1e-30
+        tol = rtol * np.abs(r) + floor * rms
+        ratio = np.abs(x - r) / tol
+        bad += int((ratio > 1).sum())
+        worst = max(worst, float(ratio.max()) if ratio.size else 0.0)
+    return bad, worst
+
+
+def param_groups(sh_degree):
+    K = (sh_degree + 1) ** 2
+    return [(0, 3), (3, 6), (6, 10), (10, 11), (11, 14)] + ([(14, 11 + 3 * K)] if K > 1 else [])
+
+
+def residual_groups(rc):
+    g = [(0, 3), (3, 7), (7, 8)]
+    if rc >= 11:
+        g.append((8, 11))
+    if rc > 11:
+        g.append((11, rc))
+    return g

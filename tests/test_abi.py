@@ -1,0 +1,96 @@
+"""CPU tier of the C ABI: the library loads, exports every entry point that include/gs4d.h
+declares, and rejects invalid arguments on the host before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2509_17513_amd import _lib
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 7
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def _settings(n, w=64, h=48, deg=0):
+    from paper_2509_17513_amd import RenderSettings
+    return RenderSettings(w, h, deg, (n,), (1.0,)).c_struct(n)
+
+
+def test_workspace_size_and_validation(L):
+    sz = ctypes.c_size_t()
+    s = _settings(1000)
+    assert L.gs_workspace_size(ctypes.byref(s), 1000, 1, 2, 10000, ctypes.byref(sz)) == 0
+    assert sz.value > 10000 * 4
+    # bigger capacity -> exactly 4 bytes per pair more (after 256-byte alignment)
+    sz2 = ctypes.c_size_t()
+    assert L.gs_workspace_size(ctypes.byref(s), 1000, 1, 2, 10000 + 64 * 10, ctypes.byref(sz2)) == 0
+    assert sz2.value - sz.value == 2560
+    bad = [
+        (_settings(1000), -1, 1, 1, 10),
+        (_settings(1000), 1000, 0, 1, 10),
+        (_settings(1000), 999, 1, 1, 10),       # last level count != n
+        (_settings(1000, deg=4), 1000, 1, 1, 10),
+        (_settings(1000, w=0), 1000, 1, 1, 10),
+        (_settings(1000), 1000, 1, 1, -5),
+    ]
+    for st, n, F, V, cap in bad:
+        assert L.gs_workspace_size(ctypes.byref(st), n, F, V, cap, ctypes.byref(sz)) == -1
+    st = _settings(1000)
+    st.level_counts[0] = 5
+    st.n_levels = 2
+    st.level_counts[1] = 4  # not ascending
+    assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 1, 10, ctypes.byref(sz)) == -1
+    st = _settings(1000)
+    st.res_channels = 9
+    assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 1, 10, ctypes.byref(sz)) == -1
+    st = _settings(1000)
+    st.tile_w = st.tile_h = 8
+    assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 1, 10, ctypes.byref(sz)) == -6
+    assert L.gs_error_string(-3) == b"pair list capacity exceeded"
+
+
+def test_render_calls_reject_bad_args_before_launch(L):
+    s = _settings(10)
+    P = ctypes.c_void_p
+    # NULL image
+    assert L.gs_render_forward(ctypes.byref(s), 10, P(8), 1, None, 1, P(8), None, P(8), 1 << 20, None) == -1
+    # workspace too small
+    assert L.gs_render_forward(ctypes.byref(s), 10, P(8), 1, None, 1, P(8), P(8), P(8), 16, None) == -2
+    # backward needs exactly one of d_image / target
+    assert L.gs_render_backward(ctypes.byref(s), 10, P(8), 1, None, 1, P(8), None, None, None, P(8), None, None,
+                                P(8), 1 << 20, None) == -1
+    # residuals without res_channels
+    assert L.gs_render_forward(ctypes.byref(s), 10, P(8), 1, P(8), 1, P(8), P(8), P(8), 1 << 20, None) == -1
+
+
+def test_workspace_layout_regions_are_disjoint(L):
+    from paper_2509_17513_amd._lib import GsWorkspaceLayout
+    s = _settings(5000, 200, 120, 3)
+    lo = GsWorkspaceLayout()
+    assert L.gs_workspace_describe(ctypes.byref(s), 5000, 2, 3, 123456, ctypes.byref(lo)) == 0
+    offs = [lo.status, lo.records, lo.rects, lo.keys, lo.vals, lo.ranges, lo.t_final, lo.n_last, lo.grad2d,
+            lo.lists]
+    assert offs == sorted(offs) and len(set(offs)) == len(offs)
+    assert lo.lists + 4 * 123456 <= lo.total
+    assert lo.tiles_x == 13 and lo.tiles_y == 8

@@ -1,0 +1,248 @@
+"""GPU parity of the render path (HIP kernels through the C ABI) against the FP64 oracle.
+
+Forward: images within 1e-4 max-abs of the oracle (an ambiguous pixel passes if it matches
+any of the oracle's accepted alternative outcomes). Backward: gradients of the layer-weighted
+L1 loss against the oracle's analytic FP64 backward. Batching: all views, frames and layers in
+one launch equal the per-view, per-frame and per-layer renders bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import (gpu_settings, grad_mismatch, image_mismatch, l1_dimage, oracle_settings, param_groups,
+                    residual_groups)
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    return torch.device("cuda:0")
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _gpu_forward(w, settings=None):
+    from paper_2509_17513_amd import render_forward
+    dev = _dev()
+    st = settings or gpu_settings(w)
+    p = torch.from_numpy(w.params).to(dev)
+    c = torch.from_numpy(w.cams).to(dev)
+    r = None if w.residuals is None else torch.from_numpy(w.residuals).to(dev)
+    img, ws = render_forward(st, p, c, w.n_frames, r)
+    torch.cuda.synchronize()
+    return img, ws, (p, c, r, st)
+
+
+def _flat(img):
+    a = img.cpu().numpy()
+    F, V, L = a.shape[:3]
+    return a.reshape((F * V, L) + a.shape[3:])
+
+
+def _small_ring(n=3000, seed=41, w=200, h=120, views=(0, 5), deg=3, levels=True):
+    p = synth.cube_scene(n, seed, deg)
+    cams = synth.ring_cameras(list(views), 24, 4.0, w, h)
+    lv = synth.nested_levels(n) if levels else [n]
+    lw = synth.paper_level_weights(len(lv))
+    tgt = synth.target_images(len(views), w, h, seed + 1)
+    return synth.Workload("small_ring", p, cams, w, h, deg, lv, lw, target=tgt)
+
+
+def test_forward_plain_4096_128x128():
+    _case("forward 4096 Gaussians 128x128 SH0")
+    w = synth.config_plain_forward()
+    img, _, _ = _gpu_forward(w)
+    ref = oracle.render(oracle_settings(w), w.params, w.cams, variants=True)
+    bad, amb, excl, err = image_mismatch(_flat(img), ref)
+    print(f"bad={bad} ambiguous={amb} excluded={excl} max_err={err:.3g}")
+    assert bad == 0 and excl == 0
+    assert err <= 1e-4
+
+
+def test_forward_ring_levels_views_ragged():
+    _case("forward 3000 Gaussians 2 ring views 200x120 (ragged tiles) SH3, six nested levels")
+    w = _small_ring()
+    img, _, _ = _gpu_forward(w)
+    ref = oracle.render(oracle_settings(w), w.params, w.cams, variants=True)
+    bad, amb, excl, err = image_mismatch(_flat(img), ref)
+    print(f"bad={bad} ambiguous={amb} excluded={excl} max_err={err:.3g}")
+    assert bad == 0
+    assert excl <= 1e-4 * ref["nvar"].size + 2
+
+
+def test_forward_background_and_empty_scene():
+    _case("empty scene renders the background")
+    from paper_2509_17513_amd import RenderSettings, render_forward
+    dev = _dev()
+    st = RenderSettings(37, 21, 0, (0,), (1.0,), bg=(0.25, 0.5, 0.75))
+    p = torch.zeros((14, 0), dtype=torch.float32, device=dev)
+    c = torch.from_numpy(synth.identity_camera(37, 21, 37.0)[None]).to(dev)
+    img, _ = render_forward(st, p, c)
+    a = img.cpu().numpy()[0, 0, 0]
+    for ch, v in enumerate((0.25, 0.5, 0.75)):
+        assert np.all(a[ch] == np.float32(v))
+
+
+def test_batched_views_and_levels_equal_plain_launches():
+    _case("batched views+levels == per-view per-level launches (bitwise)")
+    from paper_2509_17513_amd import RenderSettings
+    w = _small_ring(n=2500, seed=43, views=(0, 3, 9))
+    img, _, _ = _gpu_forward(w)
+    a = img.cpu().numpy()
+    for v in range(3):
+        for l, nl in enumerate(w.level_counts):
+            wv = synth.Workload("one", np.ascontiguousarray(w.params[:, :nl]), w.cams[v:v + 1], w.width, w.height,
+                                w.sh_degree, [nl], [1.0])
+            one, _, _ = _gpu_forward(wv)
+            assert np.array_equal(one.cpu().numpy()[0, 0, 0], a[0, v, l]), (v, l)
+
+
+def test_permutation_invariance():
+    _case("permuted input order")
+    w = _small_ring(n=2000, seed=45, views=(2,), levels=False)
+    img, _, _ = _gpu_forward(w)
+    perm = np.random.default_rng(46).permutation(w.n)
+    w2 = synth.Workload("perm", np.ascontiguousarray(w.params[:, perm]), w.cams, w.width, w.height, w.sh_degree,
+                        [w.n], [1.0])
+    img2, _, _ = _gpu_forward(w2)
+    ref = oracle.render(oracle_settings(w), w.params, w.cams, variants=True)
+    d = np.abs(img.cpu().numpy() - img2.cpu().numpy()).max(axis=3)[0]
+    ok = ref["nvar"] == 0
+    assert d[ok].max() <= 2e-6
+
+
+def test_overflow_reports_needed_pairs_and_retry_matches():
+    _case("pair-capacity overflow and retry")
+    from paper_2509_17513_amd import Workspace, render_forward
+    w = _small_ring(n=2000, seed=47, views=(0,), levels=False)
+    dev = _dev()
+    st = gpu_settings(w)
+    p = torch.from_numpy(w.params).to(dev)
+    c = torch.from_numpy(w.cams).to(dev)
+    ws = Workspace(st, w.n, 1, 1, dev, pair_capacity=100)
+    img0 = torch.full((1, 1, 1, 3, w.height, w.width), -7.0, device=dev)
+    render_forward(st, p, c, 1, None, ws, image=img0, check_overflow=False)
+    ok, needed = ws.status()
+    assert not ok and needed > 100
+    assert torch.all(img0 == -7.0)  # an overflowing forward leaves the image untouched
+    ws.allocate(needed)
+    img1, _ = render_forward(st, p, c, 1, None, ws, check_overflow=False)
+    ok, needed2 = ws.status()
+    assert ok and needed2 == needed
+    img2, _, _ = _gpu_forward(w)
+    assert torch.equal(img1, img2)
+
+
+def test_tile_coverage_is_conservative():
+    _case("every oracle contribution lies in an emitted tile")
+    w = _small_ring(n=1500, seed=49, w=96, h=80, views=(4,), levels=False)
+    img, ws, _ = _gpu_forward(w)
+    lo = ws.layout()
+    buf = ws.buf.cpu().numpy()
+    T = lo.tiles_x * lo.tiles_y
+    ranges = buf[lo.ranges:lo.ranges + 8 * T].view(np.uint32).reshape(T, 2)
+    lists = buf[lo.lists:lo.lists + 4 * int(ranges[-1, 1])].view(np.uint32)
+    in_tile = [set(lists[s:e].tolist()) for s, e in ranges]
+    pr = oracle.project(oracle_settings(w), w.params, w.cams)[0]
+    u = np.arange(w.width) + 0.5
+    v = np.arange(w.height) + 0.5
+    amin = float(np.float32(1 / 255))
+    missed = 0
+    for i in range(w.n):
+        if pr[i, 0] != 1.0 or 255 * pr[i, 10] < 1:
+            continue
+        dx = u[None, :] - pr[i, 2]
+        dy = v[:, None] - pr[i, 3]
+        a = pr[i, 10] * np.exp(-0.5 * (pr[i, 7] * dx * dx + 2 * pr[i, 8] * dx * dy + pr[i, 9] * dy * dy))
+        ys, xs = np.nonzero(a >= amin * (1 - 1e-4))
+        for t in set(((ys // 16) * lo.tiles_x + xs // 16).tolist()):
+            if i not in in_tile[t]:
+                missed += 1
+    assert missed == 0
+
+
+def test_backward_l1_matches_oracle_ring():
+    _case("backward: layer-weighted L1, 2 views, 6 levels, SH3")
+    from paper_2509_17513_amd import render_backward
+    w = _small_ring(n=2000, seed=51, w=160, h=96)
+    img, ws, (p, c, r, st) = _gpu_forward(w)
+    ost = oracle_settings(w)
+    ref = oracle.render(ost, w.params, w.cams, variants=True)
+    bad, amb, excl, err = image_mismatch(_flat(img), ref)
+    assert bad == 0
+    dimg = l1_dimage(ref, w.target, w.level_weights)
+    dp_ref, _, _ = oracle.backward(ost, w.params, w.cams, dimg)
+    d_image = torch.from_numpy(dimg.astype(np.float32).reshape(img.shape)).to(p.device)
+    dp, _ = render_backward(st, p, c, ws, image=img, d_image=d_image)
+    torch.cuda.synchronize()
+    bad, worst = grad_mismatch(dp.cpu().numpy().astype(np.float64), dp_ref, param_groups(w.sh_degree))
+    print(f"grad bad={bad} of {dp.numel()} worst_ratio={worst:.3g}")
+    assert bad <= 1e-3 * dp.numel()
+
+
+def test_backward_fused_target_equals_dimage_path():
+    _case("fused L1 target gradient == explicit d_image gradient (GPU vs GPU, same image)")
+    from paper_2509_17513_amd import render_backward
+    w = _small_ring(n=1500, seed=53, w=128, h=80)
+    img, ws, (p, c, r, st) = _gpu_forward(w)
+    tgt = torch.from_numpy(w.target).to(p.device)
+    loss = torch.zeros(1, device=p.device)
+    dp1, _ = render_backward(st, p, c, ws, image=img, target=tgt, loss=loss)
+    lw = torch.tensor(w.level_weights, device=p.device).view(1, 1, -1, 1, 1, 1)
+    diff = img - tgt.view(1, tgt.shape[0], 1, 3, w.height, w.width)
+    d_image = (lw * torch.sign(diff) / (3 * w.width * w.height)).contiguous()
+    dp2, _ = render_backward(st, p, c, ws, image=img, d_image=d_image)
+    torch.cuda.synchronize()
+    a, b = dp1.cpu().numpy(), dp2.cpu().numpy()
+    assert np.allclose(a, b, rtol=1e-5, atol=1e-7 * np.abs(b).max())
+    per = diff.abs().mean(dim=(3, 4, 5))  # [F][V][L]
+    exp = float((per * lw.view(1, 1, -1)).sum())
+    assert abs(loss.item() - exp) <= 1e-5 * abs(exp)
+
+
+def test_frames_forward_backward_match_oracle():
+    _case("group: 3 frames x 2 views with rigid+opacity residuals, forward and backward")
+    from paper_2509_17513_amd import render_backward
+    n, F = 1200, 3
+    p = synth.cube_scene(n, 55, 1)
+    res = synth.frame_residuals(n, F, 56, channels=8, sd_mean=0.03, sd_angle=0.2, sd_logit=0.2)
+    cams1 = synth.ring_cameras([1, 8], 24, 4.0, 96, 64)
+    cams = np.ascontiguousarray(np.concatenate([cams1] * F))
+    tgt = synth.target_images(F * 2, 96, 64, 57)
+    w = synth.Workload("group", p, cams, 96, 64, 1, [n], [1.0], n_frames=F, residuals=res, target=tgt)
+    img, ws, (pt, ct, rt, st) = _gpu_forward(w)
+    ost = oracle_settings(w)
+    ref = oracle.render(ost, p, cams, n_frames=F, residuals=res, variants=True)
+    bad, amb, excl, err = image_mismatch(_flat(img), ref)
+    print(f"bad={bad} ambiguous={amb} excluded={excl} max_err={err:.3g}")
+    assert bad == 0
+    dimg = l1_dimage(ref, tgt, w.level_weights)
+    dp_ref, dr_ref, _ = oracle.backward(ost, p, cams, dimg, n_frames=F, residuals=res)
+    d_image = torch.from_numpy(dimg.astype(np.float32).reshape(img.shape)).to(pt.device)
+    dp, dr = render_backward(st, pt, ct, ws, F, rt, image=img, d_image=d_image)
+    torch.cuda.synchronize()
+    b1, w1 = grad_mismatch(dp.cpu().numpy().astype(np.float64), dp_ref, param_groups(1))
+    b2, w2 = grad_mismatch(dr.cpu().numpy().astype(np.float64).transpose(1, 0, 2),
+                           dr_ref.transpose(1, 0, 2), residual_groups(8))
+    print(f"params bad={b1} worst={w1:.3g}; residuals bad={b2} worst={w2:.3g}")
+    assert b1 <= 1e-3 * dp.numel() and b2 <= 1e-3 * dr.numel()
+
+
+def test_autograd_function_matches_direct_backward():
+    _case("torch.autograd.Function wrapper")
+    from paper_2509_17513_amd import render, render_backward
+    w = _small_ring(n=800, seed=59, w=64, h=48, views=(0,), levels=False, deg=2)
+    img, ws, (p, c, r, st) = _gpu_forward(w)
+    pg = p.clone().requires_grad_(True)
+    out = render(pg, c, st)
+    gimg = torch.randn_like(out)
+    out.backward(gimg)
+    dp, _ = render_backward(st, p, c, ws, image=img, d_image=gimg.contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(out, img)
+    assert torch.allclose(pg.grad, dp, rtol=1e-5, atol=1e-6 * float(dp.abs().max()))
