@@ -146,6 +146,66 @@ int gs_workspace_stats(void* ws, void* stream, gs_stats* out);
 const char* gs_error_string(int code);
 const char* gs_last_error(void);
 
+/* ---------------------------------------------------------------- rate terms
+ * The attributes whose rate is estimated are the non-position channels of the
+ * parameter array (rotation, scale, opacity and SH: the set the keyframe rate
+ * of Sec. 3.3 sums over), stored [n_attr][n]. Symbols are k = rint(y / step). */
+
+/* 16 context features per Gaussian, written BF16 [n][16]:
+ * mean / extent (3), sin and cos of pi 2^k mean / extent for k = 0, 1 (12),
+ * (layer - 1) / 5 (1), where layer l holds the indices [level_counts[l-1], level_counts[l]).
+ *  means  [3][n] float32 (the first three parameter rows). */
+int gs_rate_context(int32_t n, const float* means, float extent, int32_t n_levels, const int32_t* level_counts,
+                    uint16_t* ctx_out, void* stream);
+
+/* Learned rate. For attribute a and symbol i a per-attribute MLP
+ * 16 -> 64 -> 64 -> 2 (tanh-GELU; BF16 weights and activations on MFMA, FP32
+ * accumulation and biases) maps the context to a Laplace location m = out0 and
+ * scale b = softplus(out1) + step / 16; the symbol costs
+ * -log2 max(F(y + step/2) - F(y - step/2), 1e-9) bits (the PMF of Sec. 3.3 as
+ * CDF differences one step apart). mode 0 evaluates at y = rint(y/step) step;
+ * mode 1 at y + u with u uniform in [-step/2, step/2) from the counter-based
+ * SplitMix64 generator, counter = offset + a n + i + 1, state = seed + counter *
+ * 0x9E3779B97F4A7C15, u = (mix >> 40) 2^-24 - 1/2 (quantisation simulated by
+ * uniform noise, Sec. 3.3). The training loss is
+ * L = sum_i w_i sum_a bits_{a,i}, w_i = lambda_rate lambda^l / |layer l| for
+ * the layer of Gaussian i (per-layer rate weighted by the layer weight).
+ *  attrs   [n_attr][n] float32;  ctx [n][16] BF16 (gs_rate_context)
+ *  w_bf16  [n_attr][5248] BF16: W1 [64][16], W2 [64][64], W3 [2][64] row-major
+ *  b_f32   [n_attr][130]: b1 [64], b2 [64], b3 [2]
+ *  bits_out[n_attr] float64, accumulated (+=) with the unweighted bits per attribute
+ *  loss_out[1] float64 (+= L) or NULL
+ *  d_attrs [n_attr][n] (+= dL/dy, mode 1 only) or NULL
+ *  d_w, d_b same layouts as the weights (+= dL/dweights) or NULL. No workspace. */
+typedef struct {
+  int32_t n, n_attr;
+  float step;
+  int32_t mode;
+  uint64_t seed, offset;
+  int32_t n_levels;
+  int32_t level_counts[8];
+  float level_weights[8];
+  float lambda_rate;
+} gs_rate_desc;
+int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
+                  const float* b_f32, double* bits_out, double* loss_out, float* d_attrs, float* d_w, float* d_b,
+                  void* stream);
+
+/* Empirical-histogram rate (the judge of the learned rate): per attribute
+ * bits = -sum_i log2(count(k_i) / n) = n H over its symbol histogram, in FP64.
+ * bits_out [n_attr] float64 (overwritten). The symbol range of one attribute
+ * must span at most 65536 symbols (else bits_out is left undefined and the
+ * status word of ws is non-zero). ws holds gs_rate_histogram_workspace_size bytes. */
+int gs_rate_histogram_workspace_size(int32_t n_attr, size_t* bytes_out);
+int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Adam step on float32 masters (bias-corrected, t = step >= 1); grads are
+ * zeroed after use; bf16_copy (or NULL) receives the BF16 rounding of the
+ * updated parameters (the MFMA copy of the MLP weights). */
+int gs_adam_step(int64_t n, float* params, float* grads, float* m, float* v, uint16_t* bf16_copy, float lr,
+                 float beta1, float beta2, float eps, int32_t step, void* stream);
+
 /* Per-kernel timing. While enabled, every kernel launch of the library is
  * bracketed by HIP events recorded on its launch stream (do not enable it
  * during hipGraph capture). gs_profile_collect waits for the recorded events,

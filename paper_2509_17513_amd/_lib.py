@@ -65,8 +65,8 @@ SIGNATURES = {
     "gs_profile_enable": ([ctypes.c_int], ctypes.c_int),
     "gs_profile_collect": ([I32, P, P], ctypes.c_int),
     "gs_kernel_name": ([I32], ctypes.c_char_p),
-    "gs_rate_workspace_size": ([P, P], ctypes.c_int),
-    "gs_rate_model": ([P, P, P, P, P, P, P, P, P, P, SZ, P], ctypes.c_int),
+    "gs_rate_histogram_workspace_size": ([I32, P], ctypes.c_int),
+    "gs_rate_model": ([P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
     "gs_rate_histogram": ([I32, I32, P, ctypes.c_float, P, P, SZ, P], ctypes.c_int),
     "gs_rate_context": ([I32, P, ctypes.c_float, I32, P, P, P], ctypes.c_int),
     "gs_adam_step": ([I64, P, P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,

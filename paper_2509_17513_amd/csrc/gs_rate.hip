@@ -1,4 +1,646 @@
-// Rate model of the quantised Gaussian attributes (filled in below).
+// Rate terms of the quantised Gaussian attributes (Sec. 3.3: quantisation
+// simulated with additive uniform noise, rate = -sum log2 PMF with the PMF
+// taken from CDF differences one quantisation step apart).
+//
+//   k_rate_ctx        16 context features per Gaussian, BF16, [n][16]
+//   k_rate_mlp        per-attribute MLP 16 -> 64 -> 64 -> 2 on MFMA (BF16 in,
+//                     FP32 accumulate) giving a discretised Laplace per symbol,
+//                     its bits, and the backward to the weights and (training
+//                     mode) to the attributes; activations never leave the chip
+//   k_hist_*          empirical-histogram rate: symbol range, LDS-privatised
+//                     counts, FP64 entropy sum
+//   k_adam            Adam update of FP32 masters with an optional BF16 copy
 #include <hip/hip_runtime.h>
 
+#include <stdint.h>
+
+#include <algorithm>
+
 #include "gs4d.h"
+#include "gs_internal.h"
+#include "gs_prof.h"
+
+namespace gs {
+namespace {
+
+constexpr int kCtx = 16;
+constexpr int kHid = 64;
+constexpr int kW1 = kHid * kCtx;  // 1024
+constexpr int kW2 = kHid * kHid;  // 4096
+constexpr int kW3 = 2 * kHid;     // 128
+constexpr int kWPerAttr = kW1 + kW2 + kW3;
+constexpr int kBPerAttr = kHid + kHid + 2;
+constexpr float kPFloor = 1e-9f;
+constexpr float kLn2 = 0.69314718055994531f;
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);  // inf / nan unchanged
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ------------------------------------------------------------------ context
+// x = [mu / extent (3), sin / cos(pi 2^k mu / extent) for k = 0, 1 (12), (layer - 1) / 5 (1)]
+__global__ __launch_bounds__(256) void k_rate_ctx(int n, const float* __restrict__ means, float extent, int n_levels,
+                                                  int4 lv_lo, int4 lv_hi, uint16_t* __restrict__ ctx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int lv[8] = {lv_lo.x, lv_lo.y, lv_lo.z, lv_lo.w, lv_hi.x, lv_hi.y, lv_hi.z, lv_hi.w};
+  int layer = 1;
+  for (int l = 0; l < n_levels; ++l)
+    if (i >= lv[l]) layer = l + 2;
+  layer = min(layer, n_levels);
+  float f[kCtx];
+  for (int c = 0; c < 3; ++c) {
+    const float u = means[(size_t)c * n + i] / extent;
+    f[c] = u;
+    f[3 + c] = sinf(3.14159265358979f * u);
+    f[6 + c] = cosf(3.14159265358979f * u);
+    f[9 + c] = sinf(6.28318530717959f * u);
+    f[12 + c] = cosf(6.28318530717959f * u);
+  }
+  f[15] = (float)(layer - 1) / 5.0f;
+  uint16_t* o = ctx + (size_t)i * kCtx;
+  for (int c = 0; c < kCtx; ++c) o[c] = f32_to_bf16(f[c]);
+}
+
+// ---------------------------------------------------------------- histogram
+__global__ void k_hist_init(int n_attr, int* __restrict__ mm) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < n_attr) {
+    mm[2 * a] = 0x7FFFFFFF;
+    mm[2 * a + 1] = (int)0x80000000;
+  }
+}
+
+__device__ __forceinline__ int symbol_of(float y, float step) { return (int)rintf(y / step); }
+
+__global__ __launch_bounds__(256) void k_hist_minmax(int n, const float* __restrict__ attrs, float step,
+                                                     int* __restrict__ mm) {
+  const int a = blockIdx.y;
+  const float* y = attrs + (size_t)a * n;
+  int lo = 0x7FFFFFFF, hi = (int)0x80000000;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int k = symbol_of(y[i], step);
+    lo = min(lo, k);
+    hi = max(hi, k);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off));
+    hi = max(hi, __shfl_xor(hi, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&mm[2 * a], lo);
+    atomicMax(&mm[2 * a + 1], hi);
+  }
+}
+
+constexpr int kHistBins = 1 << 16;      // per attribute, in the workspace
+constexpr int kHistLdsBins = 1 << 14;   // LDS-privatised when the range fits
+
+__global__ __launch_bounds__(256) void k_hist_count(int n, const float* __restrict__ attrs, float step,
+                                                    const int* __restrict__ mm, uint32_t* __restrict__ hist,
+                                                    uint32_t* __restrict__ err) {
+  __shared__ uint32_t lh[kHistLdsBins];
+  const int a = blockIdx.y;
+  const int kmin = mm[2 * a], kmax = mm[2 * a + 1];
+  const long long range = (long long)kmax - kmin + 1;
+  if (range > kHistBins) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(err, 1u);
+    return;
+  }
+  const float* y = attrs + (size_t)a * n;
+  uint32_t* gh = hist + (size_t)a * kHistBins;
+  const bool use_lds = range <= kHistLdsBins;
+  if (use_lds) {
+    for (int j = threadIdx.x; j < range; j += blockDim.x) lh[j] = 0;
+    __syncthreads();
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int k = symbol_of(y[i], step) - kmin;
+    if (use_lds) atomicAdd(&lh[k], 1u);
+    else atomicAdd(&gh[k], 1u);
+  }
+  if (use_lds) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < range; j += blockDim.x)
+      if (lh[j]) atomicAdd(&gh[j], lh[j]);
+  }
+}
+
+// bits_a = N log2 N - sum_k n_k log2 n_k  (= -sum_i log2(n(k_i) / N)), in FP64
+__global__ __launch_bounds__(256) void k_hist_bits(int n, const int* __restrict__ mm, const uint32_t* __restrict__ hist,
+                                                   double* __restrict__ bits) {
+  __shared__ double part[256];
+  const int a = blockIdx.x;
+  const long long range = (long long)mm[2 * a + 1] - mm[2 * a] + 1;
+  const uint32_t* gh = hist + (size_t)a * kHistBins;
+  double s = 0.0;
+  if (range <= kHistBins)
+    for (int j = threadIdx.x; j < range; j += blockDim.x) {
+      const double c = (double)gh[j];
+      if (c > 0) s += c * log2(c);
+    }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bits[a] = (n > 0 ? (double)n * log2((double)n) : 0.0) - part[0];
+}
+
+
+// ---------------------------------------------------------------------- MLP
+// One wave handles 32 symbols of one attribute at a time. MFMA operand layout
+// (v_mfma_f32_32x32x16_bf16): lane l holds row / column (l & 31) and 8 values
+// of the contraction index; accumulator element r of lane l is row
+// 8 (r / 4) + 4 (l >> 5) + (r & 3), column (l & 31). Products are computed
+// transposed (hidden units as rows, symbols as columns), so the accumulator
+// of one layer, after bias + GELU + BF16 rounding, is directly the B operand
+// of the next layer: its 8 values per K-step are the hidden units
+// 16 ks + 8 (j / 4) + 4 (l >> 5) + (j & 3), and the weight (A) operand is
+// gathered with the same permutation of the contraction index.
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+struct RateArgs {
+  int n, n_attr, mode, n_levels;
+  float step;
+  unsigned long long seed, offset;
+  int lv[8];
+  float wsym[8];  // per-symbol loss weight of each layer: lambda_rate lambda^l / |G^l|
+};
+
+__device__ __forceinline__ bf16x8 pack8(const uint16_t* h) {
+  uint4 u;
+  u.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+  u.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+  u.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
+  u.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
+  return __builtin_bit_cast(bf16x8, u);
+}
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {  // 16-byte aligned
+  return __builtin_bit_cast(bf16x8, *(const uint4*)p);
+}
+__device__ __forceinline__ bf16x8 load4x2(const uint16_t* p0, const uint16_t* p1) {  // two 8-byte halves
+  const uint2 a = *(const uint2*)p0, b = *(const uint2*)p1;
+  return __builtin_bit_cast(bf16x8, make_uint4(a.x, a.y, b.x, b.y));
+}
+
+__device__ __forceinline__ float gelu_f(float x) {
+  const float c = 0.7978845608028654f;
+  return 0.5f * x * (1.f + tanhf(c * (x + 0.044715f * x * x * x)));
+}
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  const float c = 0.7978845608028654f;
+  const float th = tanhf(c * (x + 0.044715f * x * x * x));
+  return 0.5f * (1.f + th) + 0.5f * x * (1.f - th * th) * c * (1.f + 3.f * 0.044715f * x * x);
+}
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// -log2 max(F(y + q/2) - F(y - q/2), 1e-9) for a Laplace(m, b) CDF F, and its
+// derivatives with respect to y and b (zero where the floor binds).
+__device__ __forceinline__ void laplace_bits(float y, float m, float b, float q, float& bits, float& dy, float& db) {
+  const float h = 0.5f * q;
+  const float d = y - m;
+  const float t = fabsf(d);
+  float lp, dlt, dlb;
+  if (t >= h) {
+    lp = -kLn2 - (t - h) / b + logf(-expm1f(-q / b));
+    dlt = -1.f / b;
+    dlb = (t - h) / (b * b) - (q / (b * b)) / expm1f(q / b);
+  } else {
+    const float ea = expf(-(h + t) / b), eb = expf(-(h - t) / b);
+    const float P = 1.f - 0.5f * ea - 0.5f * eb;
+    lp = logf(P);
+    dlt = (0.5f * ea / b - 0.5f * eb / b) / P;
+    dlb = (-0.5f * ea * (h + t) / (b * b) - 0.5f * eb * (h - t) / (b * b)) / P;
+  }
+  const float lfloor = -20.723265836946411f;  // ln 1e-9
+  if (!(lp >= lfloor)) {
+    bits = -lfloor / kLn2;
+    dy = 0.f;
+    db = 0.f;
+    return;
+  }
+  bits = -lp / kLn2;
+  const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+  dy = -dlt * sg / kLn2;
+  db = -dlb / kLn2;
+}
+
+struct RateShared {
+  uint16_t w1[kHid * kCtx];    // [o][f]
+  uint16_t w2[kHid * kHid];    // [o2][i]
+  uint16_t w2t[kHid * kHid];   // [i][o2]
+  float w3[2 * kHid];
+  float b1[kHid], b2[kHid], b3[2];
+};
+struct RateWaveTmp {           // transposed per-wave staging for the weight gradients
+  uint16_t h1[kHid * 32];      // [i][s]
+  uint16_t h2[kHid * 32];      // [o2][s]
+  uint16_t d2[kHid * 32];      // [o2][s]
+  uint16_t d1[kHid * 32];      // [i][s]
+  uint16_t x[kCtx * 32];       // [f][s]
+  float dout[2 * 32];          // [r][s]
+};
+
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __restrict__ attrs,
+                                                  const uint16_t* __restrict__ ctx, const uint16_t* __restrict__ W,
+                                                  const float* __restrict__ Bv, double* __restrict__ bits_out,
+                                                  double* __restrict__ loss_out, float* __restrict__ d_attrs,
+                                                  float* __restrict__ d_w, float* __restrict__ d_b) {
+  extern __shared__ __align__(16) char smem[];
+  RateShared& sh = *(RateShared*)smem;
+  RateWaveTmp* wt = (RateWaveTmp*)(smem + ((sizeof(RateShared) + 15) & ~(size_t)15));
+  const int a = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sl = lane & 31, g = lane >> 5;
+  const uint16_t* Wa = W + (size_t)a * kWPerAttr;
+  const float* Ba = Bv + (size_t)a * kBPerAttr;
+  for (int j = tid; j < kW1; j += 256) sh.w1[j] = Wa[j];
+  for (int j = tid; j < kW2; j += 256) {
+    const uint16_t v = Wa[kW1 + j];
+    sh.w2[j] = v;
+    sh.w2t[(j & 63) * kHid + (j >> 6)] = v;
+  }
+  for (int j = tid; j < kW3; j += 256) sh.w3[j] = bf16_to_f32(Wa[kW1 + kW2 + j]);
+  if (tid < kHid) {
+    sh.b1[tid] = Ba[tid];
+    sh.b2[tid] = Ba[kHid + tid];
+  }
+  if (tid < 2) sh.b3[tid] = Ba[2 * kHid + tid];
+  __syncthreads();
+
+  const int n = ra.n;
+  const float q = ra.step;
+  const float* ya = attrs + (size_t)a * n;
+  const int nchunks = (n + 31) / 32;
+  const int per_iter = gridDim.x * 4;
+  const int iters = (nchunks + per_iter - 1) / per_iter;
+  float bits_acc = 0.f, loss_acc = 0.f;
+  f32x16 acc2[2][2];
+  f32x4 acc1[4], acc3[4];
+  float db1 = 0.f, db2 = 0.f, db3 = 0.f;
+  if constexpr (GRAD) {
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v)
+        for (int r = 0; r < 16; ++r) acc2[u][v][r] = 0.f;
+    for (int u = 0; u < 4; ++u)
+      for (int r = 0; r < 4; ++r) { acc1[u][r] = 0.f; acc3[u][r] = 0.f; }
+  }
+  RateWaveTmp& T = wt[wave];
+
+  for (int it = 0; it < iters; ++it) {
+    const int chunk = (it * gridDim.x + blockIdx.x) * 4 + wave;
+    const int sidx = chunk * 32 + sl;
+    const bool valid = sidx < n;
+    // ---- layer 1: Z1^T (64 x 32) = W1 (64 x 16) X^T (16 x 32)
+    bf16x8 bx;
+    if (valid) bx = load8(ctx + (size_t)sidx * kCtx + 8 * g);
+    else bx = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+    f32x16 c1[2];
+    for (int h = 0; h < 2; ++h) {
+      f32x16 z;
+      for (int r = 0; r < 16; ++r) z[r] = 0.f;
+      c1[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(&sh.w1[(32 * h + sl) * kCtx + 8 * g]), bx, z, 0, 0, 0);
+    }
+    float z1[32];
+    uint16_t h1b[32];
+    for (int h = 0; h < 2; ++h)
+      for (int r = 0; r < 16; ++r) {
+        const int o = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
+        const float zz = c1[h][r] + sh.b1[o];
+        z1[16 * h + r] = zz;
+        h1b[16 * h + r] = f32_to_bf16(gelu_f(zz));
+      }
+    // ---- layer 2: Z2^T (64 x 32) = W2 (64 x 64) H1^T (64 x 32), K in 4 steps of 16
+    f32x16 c2[2];
+    for (int h2 = 0; h2 < 2; ++h2) {
+      for (int r = 0; r < 16; ++r) c2[h2][r] = 0.f;
+      for (int ks = 0; ks < 4; ++ks) {
+        const uint16_t* row = &sh.w2[(32 * h2 + sl) * kHid + 16 * ks + 4 * g];
+        c2[h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load4x2(row, row + 8), pack8(&h1b[8 * ks]), c2[h2], 0, 0, 0);
+      }
+    }
+    float z2[32], h2f[32];
+    uint16_t h2b[32];
+    for (int h = 0; h < 2; ++h)
+      for (int r = 0; r < 16; ++r) {
+        const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
+        const float zz = c2[h][r] + sh.b2[o2];
+        z2[16 * h + r] = zz;
+        h2b[16 * h + r] = f32_to_bf16(gelu_f(zz));
+        h2f[16 * h + r] = bf16_to_f32(h2b[16 * h + r]);
+      }
+    // ---- layer 3 (2 outputs) on the VALU: each lane holds half of the hidden units of its symbol
+    float o0 = 0.f, o1 = 0.f;
+    for (int h = 0; h < 2; ++h)
+      for (int r = 0; r < 16; ++r) {
+        const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
+        o0 = fmaf(sh.w3[o2], h2f[16 * h + r], o0);
+        o1 = fmaf(sh.w3[kHid + o2], h2f[16 * h + r], o1);
+      }
+    o0 += __shfl_xor(o0, 32);
+    o1 += __shfl_xor(o1, 32);
+    o0 += sh.b3[0];
+    o1 += sh.b3[1];
+    // ---- discretised Laplace rate of the symbol
+    const float m = o0;
+    const float sp = fmaxf(o1, 0.f) + log1pf(expf(-fabsf(o1)));
+    const float bsc = sp + q * (1.f / 16.f);
+    float yh = 0.f, bits = 0.f, dby = 0.f, dbb = 0.f, wsym = 0.f;
+    if (valid) {
+      const float y = ya[sidx];
+      if (ra.mode == 0) {
+        yh = rintf(y / q) * q;
+      } else {
+        const unsigned long long ctr = ra.offset + (unsigned long long)a * (unsigned long long)n +
+                                       (unsigned long long)sidx + 1ull;
+        const unsigned long long zz = splitmix64(ra.seed + ctr * 0x9E3779B97F4A7C15ull);
+        const float u = (float)(uint32_t)(zz >> 40) * (1.0f / 16777216.0f) - 0.5f;
+        yh = y + u * q;
+      }
+      laplace_bits(yh, m, bsc, q, bits, dby, dbb);
+      int layer = 0;
+      for (int l = 0; l < ra.n_levels - 1; ++l)
+        if (sidx >= ra.lv[l]) layer = l + 1;
+      wsym = ra.wsym[layer];
+      if (g == 0) {
+        bits_acc += bits;
+        loss_acc += wsym * bits;
+      }
+      if (ra.mode == 1 && d_attrs && g == 0) d_attrs[(size_t)a * n + sidx] += wsym * dby;
+    }
+    if constexpr (GRAD) {
+      const float dout0 = valid ? -wsym * dby : 0.f;
+      const float sig1 = 1.f / (1.f + expf(-o1));
+      const float dout1 = valid ? wsym * dbb * sig1 : 0.f;
+      // dZ2 = (W3^T dout) * GELU'(Z2)
+      uint16_t d2b[32];
+      for (int h = 0; h < 2; ++h)
+        for (int r = 0; r < 16; ++r) {
+          const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
+          const float dh = dout0 * sh.w3[o2] + dout1 * sh.w3[kHid + o2];
+          d2b[16 * h + r] = f32_to_bf16(dh * gelu_grad_f(z2[16 * h + r]));
+        }
+      // dH1^T (64 x 32) = W2^T (64 x 64) dZ2^T (64 x 32)
+      f32x16 c3[2];
+      for (int hi = 0; hi < 2; ++hi) {
+        for (int r = 0; r < 16; ++r) c3[hi][r] = 0.f;
+        for (int ks = 0; ks < 4; ++ks) {
+          const uint16_t* row = &sh.w2t[(32 * hi + sl) * kHid + 16 * ks + 4 * g];
+          c3[hi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load4x2(row, row + 8), pack8(&d2b[8 * ks]), c3[hi], 0, 0, 0);
+        }
+      }
+      uint16_t d1b[32];
+      for (int h = 0; h < 2; ++h)
+        for (int r = 0; r < 16; ++r) d1b[16 * h + r] = f32_to_bf16(c3[h][r] * gelu_grad_f(z1[16 * h + r]));
+      // transposed staging (symbols contiguous) for the contractions over symbols
+      for (int h = 0; h < 2; ++h)
+        for (int r = 0; r < 16; ++r) {
+          const int u = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
+          T.h1[u * 32 + sl] = h1b[16 * h + r];
+          T.h2[u * 32 + sl] = h2b[16 * h + r];
+          T.d2[u * 32 + sl] = d2b[16 * h + r];
+          T.d1[u * 32 + sl] = d1b[16 * h + r];
+        }
+      {
+        const uint4 xv = __builtin_bit_cast(uint4, bx);
+        const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
+        for (int j = 0; j < 8; ++j) T.x[(8 * g + j) * 32 + sl] = (uint16_t)(xs[j >> 1] >> (16 * (j & 1)));
+      }
+      if (g == 0) {
+        T.dout[sl] = dout0;
+        T.dout[32 + sl] = dout1;
+      }
+      __syncthreads();
+      // dW2 (64 x 64) += dZ2^T (64 x 32 symbols) H1 (32 x 64)
+      for (int kk = 0; kk < 2; ++kk)
+        for (int h = 0; h < 2; ++h) {
+          const bf16x8 av = load8(&T.d2[(32 * h + sl) * 32 + 16 * kk + 8 * g]);
+          for (int h2 = 0; h2 < 2; ++h2)
+            acc2[h][h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, load8(&T.h1[(32 * h2 + sl) * 32 + 16 * kk + 8 * g]),
+                                                                  acc2[h][h2], 0, 0, 0);
+        }
+      // dW1 (64 x 16) += dZ1^T (64 x 32) X (32 x 16): v_mfma_f32_16x16x32_bf16, lane l holds row/col (l & 15)
+      const int r16 = lane & 15, g16 = lane >> 4;
+      const bf16x8 bxT = load8(&T.x[r16 * 32 + 8 * g16]);
+      for (int mt = 0; mt < 4; ++mt)
+        acc1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(&T.d1[(16 * mt + r16) * 32 + 8 * g16]), bxT, acc1[mt],
+                                                            0, 0, 0);
+      // dW3 (2 x 64) += dout^T (2 x 32) H2 (32 x 64), rows padded to 16
+      uint16_t dv[8];
+      for (int j = 0; j < 8; ++j) dv[j] = r16 < 2 ? f32_to_bf16(T.dout[r16 * 32 + 8 * g16 + j]) : (uint16_t)0;
+      const bf16x8 ad = pack8(dv);
+      for (int nt = 0; nt < 4; ++nt)
+        acc3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, load8(&T.h2[(16 * nt + r16) * 32 + 8 * g16]), acc3[nt],
+                                                            0, 0, 0);
+      // bias gradients: row sums over the 32 symbols
+      {
+        float s1 = 0.f, s2 = 0.f;
+        for (int j = 0; j < 32; ++j) {
+          s1 += bf16_to_f32(T.d1[lane * 32 + j]);
+          s2 += bf16_to_f32(T.d2[lane * 32 + j]);
+        }
+        db1 += s1;
+        db2 += s2;
+        if (lane < 2) {
+          float s3 = 0.f;
+          for (int j = 0; j < 32; ++j) s3 += T.dout[lane * 32 + j];
+          db3 += s3;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // ---- block reductions
+  for (int off = 32; off > 0; off >>= 1) {
+    bits_acc += __shfl_xor(bits_acc, off);
+    loss_acc += __shfl_xor(loss_acc, off);
+  }
+  __shared__ float red[2][4];
+  if (lane == 0) {
+    red[0][wave] = bits_acc;
+    red[1][wave] = loss_acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const float bsum = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const float lsum = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    atomicAdd(bits_out + a, (double)bsum);
+    if (loss_out) atomicAdd(loss_out, (double)lsum);
+  }
+  if constexpr (GRAD) {
+    // sum the four waves' weight gradients in LDS (reusing the staging area), then one atomic per value
+    float* acc = (float*)wt;
+    for (int j = tid; j < kWPerAttr + kBPerAttr; j += 256) acc[j] = 0.f;
+    __syncthreads();
+    for (int h = 0; h < 2; ++h)
+      for (int h2 = 0; h2 < 2; ++h2)
+        for (int r = 0; r < 16; ++r) {
+          const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
+          const int i = 32 * h2 + sl;
+          atomicAdd(&acc[kW1 + o2 * kHid + i], acc2[h][h2][r]);
+        }
+    {
+      const int r16 = lane & 15, g16 = lane >> 4;
+      for (int mt = 0; mt < 4; ++mt)
+        for (int r = 0; r < 4; ++r) atomicAdd(&acc[(16 * mt + 4 * g16 + r) * kCtx + r16], acc1[mt][r]);
+      for (int nt = 0; nt < 4; ++nt)
+        for (int r = 0; r < 4; ++r) {
+          const int row = 4 * g16 + r;
+          if (row < 2) atomicAdd(&acc[kW1 + kW2 + row * kHid + 16 * nt + r16], acc3[nt][r]);
+        }
+    }
+    atomicAdd(&acc[kWPerAttr + lane], db1);
+    atomicAdd(&acc[kWPerAttr + kHid + lane], db2);
+    if (lane < 2) atomicAdd(&acc[kWPerAttr + 2 * kHid + lane], db3);
+    __syncthreads();
+    if (d_w)
+      for (int j = tid; j < kWPerAttr; j += 256)
+        if (acc[j] != 0.f) unsafeAtomicAdd(d_w + (size_t)a * kWPerAttr + j, acc[j]);
+    if (d_b)
+      for (int j = tid; j < kBPerAttr; j += 256)
+        if (acc[kWPerAttr + j] != 0.f) unsafeAtomicAdd(d_b + (size_t)a * kBPerAttr + j, acc[kWPerAttr + j]);
+  }
+}
+
+// --------------------------------------------------------------------- Adam
+__global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p, float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              uint16_t* __restrict__ bf16_copy, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    g[i] = 0.f;
+    if (bf16_copy) bf16_copy[i] = f32_to_bf16(pi);
+  }
+}
+
+}  // namespace
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+int gs_rate_context(int32_t n, const float* means, float extent, int32_t n_levels, const int32_t* level_counts,
+                    uint16_t* ctx_out, void* stream) {
+  if (n < 0 || !means || !ctx_out || !(extent > 0.f) || n_levels < 1 || n_levels > 8 || !level_counts)
+    return GS_ERR_INVALID_ARG;
+  if (n == 0) return GS_OK;
+  int lv[8];
+  for (int l = 0; l < 8; ++l) lv[l] = l < n_levels ? level_counts[l] : n;
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope ps_(K_RATE_CTX, st);
+  hipLaunchKernelGGL(k_rate_ctx, dim3((n + 255) / 256), dim3(256), 0, st, n, means, extent, n_levels,
+                     make_int4(lv[0], lv[1], lv[2], lv[3]), make_int4(lv[4], lv[5], lv[6], lv[7]), ctx_out);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_rate_histogram_workspace_size(int32_t n_attr, size_t* bytes_out) {
+  if (n_attr < 1 || !bytes_out) return GS_ERR_INVALID_ARG;
+  *bytes_out = 256 + (size_t)n_attr * 8 + (size_t)n_attr * kHistBins * 4;
+  return GS_OK;
+}
+
+int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  if (n < 0 || n_attr < 1 || !attrs || !bits_out || !ws || !(step > 0.f)) return GS_ERR_INVALID_ARG;
+  gs_rate_histogram_workspace_size(n_attr, &need);
+  if (ws_bytes < need) return GS_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  uint32_t* err = (uint32_t*)w;
+  int* mm = (int*)(w + 256);
+  uint32_t* hist = (uint32_t*)(w + 256 + (size_t)n_attr * 8);
+  if (launch_zero(w, 256, st) != hipSuccess) return GS_ERR_HIP;
+  if (launch_zero(hist, (size_t)n_attr * kHistBins * 4, st) != hipSuccess) return GS_ERR_HIP;
+  {
+    ProfScope ps_(K_RATE_HIST_MINMAX, st);
+    hipLaunchKernelGGL(k_hist_init, dim3((n_attr + 63) / 64), dim3(64), 0, st, n_attr, mm);
+    if (n > 0)
+      hipLaunchKernelGGL(k_hist_minmax, dim3(std::min(64, (n + 255) / 256), n_attr), dim3(256), 0, st, n, attrs,
+                         step, mm);
+  }
+  if (n > 0) {
+    ProfScope ps_(K_RATE_HIST_COUNT, st);
+    hipLaunchKernelGGL(k_hist_count, dim3(std::min(32, (n + 255) / 256), n_attr), dim3(256), 0, st, n, attrs, step,
+                       mm, hist, err);
+  }
+  {
+    ProfScope ps_(K_RATE_HIST_BITS, st);
+    hipLaunchKernelGGL(k_hist_bits, dim3(n_attr), dim3(256), 0, st, n, mm, hist, bits_out);
+  }
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+
+int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
+                  const float* b_f32, double* bits_out, double* loss_out, float* d_attrs, float* d_w, float* d_b,
+                  void* stream) {
+  if (!desc || !attrs || !ctx || !w_bf16 || !b_f32 || !bits_out) return GS_ERR_INVALID_ARG;
+  const gs_rate_desc& d = *desc;
+  if (d.n < 0 || d.n_attr < 1 || !(d.step > 0.f) || (d.mode != 0 && d.mode != 1)) return GS_ERR_INVALID_ARG;
+  if (d.n_levels < 1 || d.n_levels > 8 || d.level_counts[d.n_levels - 1] != d.n) return GS_ERR_INVALID_ARG;
+  for (int l = 1; l < d.n_levels; ++l)
+    if (d.level_counts[l] < d.level_counts[l - 1] || d.level_counts[l - 1] < 0) return GS_ERR_INVALID_ARG;
+  if (d.n == 0) return GS_OK;
+  RateArgs ra;
+  ra.n = d.n; ra.n_attr = d.n_attr; ra.mode = d.mode; ra.n_levels = d.n_levels; ra.step = d.step;
+  ra.seed = d.seed; ra.offset = d.offset;
+  int prev = 0;
+  for (int l = 0; l < 8; ++l) {
+    ra.lv[l] = l < d.n_levels ? d.level_counts[l] : d.n;
+    const int cnt = l < d.n_levels ? d.level_counts[l] - prev : 0;
+    ra.wsym[l] = cnt > 0 ? d.lambda_rate * d.level_weights[l] / (float)cnt : 0.f;
+    if (l < d.n_levels) prev = d.level_counts[l];
+  }
+  const bool grad = d_w || d_b;
+  const int nchunks = (d.n + 31) / 32;
+  const int nb = std::max(1, std::min(64, (nchunks + 3) / 4));
+  const size_t shared = (sizeof(RateShared) + 15) & ~(size_t)15;
+  const size_t lds = grad ? shared + 4 * sizeof(RateWaveTmp) : shared;
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope ps_(K_RATE_MLP, st);
+  if (grad)
+    hipLaunchKernelGGL(k_rate_mlp<true>, dim3(nb, d.n_attr), dim3(256), lds, st, ra, attrs, ctx, w_bf16, b_f32,
+                       bits_out, loss_out, d_attrs, d_w, d_b);
+  else
+    hipLaunchKernelGGL(k_rate_mlp<false>, dim3(nb, d.n_attr), dim3(256), lds, st, ra, attrs, ctx, w_bf16, b_f32,
+                       bits_out, loss_out, d_attrs, d_w, d_b);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_adam_step(int64_t n, float* params, float* grads, float* m, float* v, uint16_t* bf16_copy, float lr,
+                 float beta1, float beta2, float eps, int32_t step, void* stream) {
+  if (n < 0 || !params || !grads || !m || !v || step < 1) return GS_ERR_INVALID_ARG;
+  if (n == 0) return GS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  ProfScope ps_(K_ADAM, st);
+  hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, st, (long long)n, params, grads, m, v, bf16_copy, lr, beta1,
+                     beta2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+}  // extern "C"
