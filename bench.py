@@ -79,7 +79,7 @@ def read_traffic(kernel):
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(w, target_s=15.0):
+def cpu_baseline(w, target_s=25.0):
     """The FP64 oracle (as it stands) on a band of rows of view 0, all six layers, forward +
     analytic backward of the same layer-weighted L1 loss; scaled to ms per view."""
     import numpy as np
@@ -103,16 +103,19 @@ def cpu_baseline(w, target_s=15.0):
         oracle.backward(st, w.params, cams, d.reshape(1, len(w.level_counts), 3, w.height, w.width))
         return time.perf_counter() - t0
 
-    rows = 4
-    t = run(rows)
-    if t < target_s / 3:
-        rows = int(min(w.height, max(rows + 1, rows * (target_s / max(t, 1e-3)))))
-        t = run(rows)
-    ms_per_view = 1e3 * t * (w.height / rows)
-    return {"value": ms_per_view, "unit": "ms/view", "cores": os.cpu_count(), "kind": "oracle",
-            "sample": f"view 0, rows {rows}/{w.height} ({rows * w.width} pixels) x 6 layers, forward + analytic "
-                      f"backward of the layer-weighted L1, FP64 C++/OpenMP; {t:.1f} s measured, scaled by "
-                      f"{w.height / rows:.2f} to one view"}
+    # two band sizes: the per-view cost is fitted as fixed (projection of all Gaussians) + per row
+    r1 = 8
+    t1 = run(r1)
+    r2 = int(min(w.height, max(2 * r1, r1 * target_s / max(t1, 1e-3))))
+    t2 = run(r2)
+    per_row = (t2 - t1) / (r2 - r1) if r2 > r1 else t2 / r2
+    fixed = max(0.0, t1 - per_row * r1)
+    full_s = fixed + per_row * w.height if per_row > 0 else t2 * w.height / r2
+    return {"value": 1e3 * full_s, "unit": "ms/view", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"view 0 of the 24, all 6 layers, forward + analytic backward of the layer-weighted L1 "
+                      f"(FP64 C++/OpenMP) on two bands of {r1} and {r2} of the {w.height} rows "
+                      f"({t1:.1f} s + {t2:.1f} s); per-view time = fixed {fixed:.2f} s + {per_row:.3f} s/row x "
+                      f"{w.height} rows"}
 
 
 def main():
@@ -125,6 +128,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=300_000)
     ap.add_argument("--views", type=int, default=24)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -281,6 +286,14 @@ def main():
                            "speedup_batched": ms_pv / ms_step}
         log(f"[bench] per-view {ms_pv:.2f} ms/step, batched speedup {ms_pv / ms_step:.2f}x")
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w)
