@@ -118,6 +118,56 @@ def cpu_baseline(w, target_s=25.0):
                       f"{w.height} rows"}
 
 
+MLP_FLOP_FWD = 2 * (16 * 64 + 64 * 64 + 64 * 2)                  # per symbol
+MLP_FLOP_BWD = 2 * (128 + 128 + 64 * 64 + 64 * 64 + 64 * 16)       # weight and hidden gradients per symbol
+BF16_PEAK_FLOPS = 2.5e15
+
+
+def bench_rate(torch, dev, L, steps, n=1_000_000):
+    """Learned rate at 1M Gaussians x 56 attributes: train-mode forward + backward of the
+    per-attribute MLP (BF16 MFMA) and the histogram judge, timed with HIP events per kernel."""
+    import ctypes
+
+    import synth
+    from paper_2509_17513_amd import _lib
+    from paper_2509_17513_amd.train import RateModel, context, histogram_bits
+    p_host = synth.cube_scene(n, 5, 3)
+    p = torch.from_numpy(p_host).to(dev)
+    lv = synth.nested_levels(n)
+    lw = synth.paper_level_weights(6)
+    rm = RateModel(56, dev, seed=5, attrs_host=p_host[3:59])
+    ctx = context(p, 1.0, lv)
+    da = torch.zeros((56, n), dtype=torch.float32, device=dev)
+    attrs = ctypes.c_void_p(p.data_ptr() + 4 * 3 * n)
+
+    def one():
+        rm.reset()
+        rm.run(attrs, n, ctx, 1, lv, lw, 1e-3, seed=1, offset=0, d_attrs_ptr=ctypes.c_void_p(da.data_ptr()))
+
+    one()
+    histogram_bits(p[3:59])
+    torch.cuda.synchronize()
+    L.gs_profile_enable(1)
+    for _ in range(steps):
+        one()
+    hb = histogram_bits(p[3:59])
+    torch.cuda.synchronize()
+    L.gs_profile_enable(0)
+    nk = 32
+    tot = (ctypes.c_double * nk)()
+    cnt = (ctypes.c_int32 * nk)()
+    _lib.check(L.gs_profile_collect(nk, tot, cnt), "gs_profile_collect")
+    times = {L.gs_kernel_name(k).decode(): tot[k] / cnt[k] for k in range(nk) if cnt[k]}
+    ms = times.get("rate_mlp", float("nan"))
+    flop = n * 56 * (MLP_FLOP_FWD + MLP_FLOP_BWD)
+    hist_ms = sum(v for k, v in times.items() if k.startswith("rate_hist"))
+    return {"workload": "rate_1000000x56_train_fwd_bwd", "mlp_ms": ms, "mlp_flop": flop,
+            "mlp_tflops": flop / (ms * 1e-3) / 1e12, "mfma_frac": flop / (ms * 1e-3) / BF16_PEAK_FLOPS,
+            "histogram_ms": hist_ms, "histogram_GB/s": n * 56 * 4 * 2 / (hist_ms * 1e-3) / 1e9,
+            "mlp_bits": float(rm.bits.sum().item()), "hist_bits": float(hb.sum().item()),
+            "kernels_ms": times}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +178,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=300_000)
     ap.add_argument("--views", type=int, default=24)
+    ap.add_argument("--no-rate", action="store_true", help="skip the learned-rate measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -190,7 +241,32 @@ def main():
         if cnt[k]:
             kernels[L.gs_kernel_name(k).decode()] = {"ms_total": tot[k], "launches": cnt[k],
                                                      "ms_per_launch": tot[k] / cnt[k]}
-    ms_step = 1e3 * (t1 - t0) / args.steps
+    ms_step_eager = 1e3 * (t1 - t0) / args.steps
+
+    def capture(fn):
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        with torch.cuda.graph(g):
+            fn()
+        return g
+
+    def time_graph(g, steps):
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps
+
+    graph = capture(step)
+    ms_step_graph = time_graph(graph, args.steps)
+    ms_step = min(ms_step_eager, ms_step_graph)
+    log(f"[bench] batched eager {ms_step_eager:.3f} ms/step, graph replay {ms_step_graph:.3f} ms/step")
     stats = _lib.GsStats()
     _lib.check(L.gs_workspace_stats(ctypes.c_void_p(ws.buf.data_ptr()),
                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
@@ -243,7 +319,8 @@ def main():
 
     out = {
         "metric": METRIC, "value": ms_step / B, "unit": "ms/view", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": False, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": ms_step, "ms_per_step_eager": ms_step_eager,
+        "ms_per_step_graph": ms_step_graph, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "gaussians": w.n, "views": B, "width": w.width, "height": w.height,
                    "sh_degree": w.sh_degree, "levels": list(w.level_counts), "pairs": pairs,
@@ -281,11 +358,17 @@ def main():
         for _ in range(args.per_view_steps):
             step_pv()
         torch.cuda.synchronize()
-        ms_pv = 1e3 * (time.perf_counter() - t0) / args.per_view_steps
-        out["per_view"] = {"ms_per_step": ms_pv, "ms_per_view": ms_pv / B, "launch_sequences": B * len(lvl) * 2,
+        ms_pv_eager = 1e3 * (time.perf_counter() - t0) / args.per_view_steps
+        ms_pv_graph = time_graph(capture(step_pv), args.per_view_steps)
+        ms_pv = min(ms_pv_eager, ms_pv_graph)
+        out["per_view"] = {"ms_per_step": ms_pv, "ms_per_view": ms_pv / B, "ms_per_step_eager": ms_pv_eager,
+                           "ms_per_step_graph": ms_pv_graph, "launch_sequences": B * len(lvl) * 2,
                            "speedup_batched": ms_pv / ms_step}
-        log(f"[bench] per-view {ms_pv:.2f} ms/step, batched speedup {ms_pv / ms_step:.2f}x")
+        log(f"[bench] per-view eager {ms_pv_eager:.2f}, graph {ms_pv_graph:.2f} ms/step; batched speedup "
+            f"{ms_pv / ms_step:.2f}x")
 
+    if not args.no_rate:
+        out["rate"] = bench_rate(torch, dev, L, args.steps)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -175,8 +175,11 @@ int gs_rate_context(int32_t n, const float* means, float extent, int32_t n_level
  *  b_f32   [n_attr][130]: b1 [64], b2 [64], b3 [2]
  *  bits_out[n_attr] float64, accumulated (+=) with the unweighted bits per attribute
  *  loss_out[1] float64 (+= L) or NULL
+ *  sym_bits[n_attr][n] float32 bits of every symbol (overwritten) or NULL
  *  d_attrs [n_attr][n] (+= dL/dy, mode 1 only) or NULL
- *  d_w, d_b same layouts as the weights (+= dL/dweights) or NULL. No workspace. */
+ *  d_w, d_b same layouts as the weights (+=) or NULL: the gradient of the maximum-likelihood
+ *          fit of the entropy model, L_fit = fit_scale sum_i sum_a bits_{a,i} (the entropy model
+ *          is fitted to the attributes whatever lambda_rate is). No workspace. */
 typedef struct {
   int32_t n, n_attr;
   float step;
@@ -186,10 +189,11 @@ typedef struct {
   int32_t level_counts[8];
   float level_weights[8];
   float lambda_rate;
+  float fit_scale;
 } gs_rate_desc;
 int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
-                  const float* b_f32, double* bits_out, double* loss_out, float* d_attrs, float* d_w, float* d_b,
-                  void* stream);
+                  const float* b_f32, double* bits_out, double* loss_out, float* sym_bits, float* d_attrs, float* d_w,
+                  float* d_b, void* stream);
 
 /* Empirical-histogram rate (the judge of the learned rate): per attribute
  * bits = -sum_i log2(count(k_i) / n) = n H over its symbol histogram, in FP64.
@@ -205,6 +209,10 @@ int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step,
  * updated parameters (the MFMA copy of the MLP weights). */
 int gs_adam_step(int64_t n, float* params, float* grads, float* m, float* v, uint16_t* bf16_copy, float lr,
                  float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* Zero-fills bytes (a multiple of 4) of device memory with a kernel (no memset node, so it is
+ * safe inside captured graphs). */
+int gs_zero(void* p, size_t bytes, void* stream);
 
 /* Per-kernel timing. While enabled, every kernel launch of the library is
  * bracketed by HIP events recorded on its launch stream (do not enable it

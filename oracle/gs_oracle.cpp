@@ -292,7 +292,7 @@ bool project(const T* p, const oc_settings& s, const Cam& k, Proj<T>& out) {
   double mid = 0.5 * (out.s2d[0] + out.s2d[2]);
   double lmax = mid + std::sqrt(std::max(0.0, 0.25 * (out.s2d[0] - out.s2d[2]) * (out.s2d[0] - out.s2d[2]) + out.s2d[1] * out.s2d[1]));
   double o = val(out.o);
-  out.radius = (255.0 * o >= 1.0) ? std::sqrt(2.0 * std::log(255.0 * o)) * std::sqrt(lmax) : 0.0;
+  out.radius = (o >= s.alpha_min) ? std::sqrt(2.0 * std::log(o / s.alpha_min)) * std::sqrt(lmax) : 0.0;
   return true;
 }
 
@@ -343,7 +343,7 @@ std::vector<Rec> project_view(const Scene& sc, int b) {
       compose_frame(s, n, sc.P.data(), res, f, i, p);
       Proj<double> pr;
       if (!project(p, s, k, pr)) continue;
-      if (!(255.0 * pr.o >= 1.0)) continue;  // can never reach alpha_min
+      if (!(pr.o >= s.alpha_min)) continue;  // can never reach alpha_min
       Rec r;
       r.idx = i; r.key = key;
       r.mx = pr.mx; r.my = pr.my; r.A = pr.A; r.B = pr.B; r.C = pr.C; r.o = pr.o;

@@ -198,11 +198,12 @@ def unpack(w_bf16_bits, b_f32, a, weights_f64=None):
 
 
 def rate_model(attrs, ctx, w_bf16_bits, b_f32, step, mode=0, seed=0, offset=0, sym_w=None, emulate_bf16=True,
-               want_grad=True, weights_f64=None):
+               want_grad=True, weights_f64=None, fit_scale=None):
     """Learned rate. attrs [A][N] float32, ctx [16][N] (BF16 values as float64).
     Returns dict: bits [A] (unweighted per-attribute totals), loss (sum_i w_i sum_a bits),
     d_attrs [A][N] (train mode: dloss/dy through the additive noise), d_w [A][W_PER_ATTR],
-    d_b [A][B_PER_ATTR], m, b [A][N]."""
+    d_b [A][B_PER_ATTR] (gradients of fit_scale * sum_i sum_a bits, the maximum-likelihood fit of
+    the entropy model; of the loss itself when fit_scale is None), m, b [A][N]."""
     attrs = np.asarray(attrs, np.float32).astype(np.float64)
     A, N = attrs.shape
     q = float(np.float32(step))
@@ -234,7 +235,8 @@ def rate_model(attrs, ctx, w_bf16_bits, b_f32, step, mode=0, seed=0, offset=0, s
         g_y = sym_w * dy
         if mode == 1:
             out["d_attrs"][a] = g_y
-        do = np.stack([-g_y, sym_w * dbb * sigmoid(o[:, 1])], axis=1)  # [N][2]
+        fw = sym_w if fit_scale is None else np.full(N, float(np.float32(fit_scale)))
+        do = np.stack([-fw * dy, fw * dbb * sigmoid(o[:, 1])], axis=1)  # [N][2]
         dW3 = do.T @ h2
         dh2 = do @ W3
         dz2 = dh2 * gelu_grad(z2)

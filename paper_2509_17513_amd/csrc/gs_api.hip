@@ -128,7 +128,7 @@ hipEvent_t prof_event() {
 const char* kKernelNames[K_COUNT] = {
     "compose_fwd", "project_fwd", "radix_hist", "radix_scan", "radix_scatter", "bin_count", "bin_chunk_scan",
     "tile_ranges", "bin_emit", "raster_fwd", "zero", "raster_bwd", "project_bwd", "compose_bwd", "rate_ctx",
-    "rate_mlp", "rate_hist_minmax", "rate_hist_count", "rate_hist_bits", "adam"};
+    "rate_mlp", "rate_hist_minmax", "rate_hist_count", "rate_hist_bits", "adam", "bin_gather"};
 }  // namespace
 
 int prof_begin(int id, hipStream_t st) {
@@ -165,12 +165,13 @@ Layout make_layout(const RenderDims& d) {
   lo.keys1 = take(Bn * 4);
   lo.vals1 = take(Bn * 4);
   lo.sort_hist = take((size_t)d.B * 256 * d.n_sort_chunks * 4);
+  lo.bin_rec = take(Bn * 32);
   lo.bin_hist = take((size_t)d.B * d.n_bin_chunks * d.T * 4);
   lo.tile_tot = take((size_t)d.B * d.T * 4);
   lo.ranges = take((size_t)d.B * d.T * 8);
   lo.t_final = take((size_t)d.B * d.L * HW * 4);
   lo.n_last = take((size_t)d.B * d.L * HW * 4);
-  lo.grad2d = take(Bn * 9 * 4);
+  lo.grad2d = take(Bn * kGradStride * 4);
   lo.composed = take((size_t)d.F * d.Rc * d.n * 4);
   lo.d_composed = take((size_t)d.F * d.Rc * d.n * 4);
   // the pair list is last, so every other offset is independent of its capacity
@@ -290,7 +291,7 @@ int gs_render_backward(const gs_settings* s, int32_t n, const float* params, int
     }
     return GS_OK;
   }
-  if ((e = launch_zero(w + lo.grad2d, (size_t)d.B * d.n * 9 * 4, st)) != hipSuccess) return fail_hip(e, "zero");
+  if ((e = launch_zero(w + lo.grad2d, (size_t)d.B * d.n * kGradStride * 4, st)) != hipSuccess) return fail_hip(e, "zero");
   if (d.Rc > 0 && (e = launch_zero(w + lo.d_composed, (size_t)d.F * d.Rc * d.n * 4, st)) != hipSuccess)
     return fail_hip(e, "zero");
   if ((e = launch_raster_bwd(d, w, lo, image, d_image, target, loss_out, st)) != hipSuccess)
@@ -351,6 +352,13 @@ const char* gs_error_string(int code) {
 }
 
 const char* gs_last_error(void) { return g_last_error.c_str(); }
+
+int gs_zero(void* p, size_t bytes, void* stream) {
+  if (!p && bytes) return fail_arg("NULL buffer");
+  if (bytes % 4) return fail_arg("bytes must be a multiple of 4");
+  hipError_t e = launch_zero(p, bytes, (hipStream_t)stream);
+  return e == hipSuccess ? GS_OK : fail_hip(e, "zero");
+}
 
 int gs_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof_mu);

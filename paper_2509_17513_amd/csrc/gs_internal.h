@@ -16,6 +16,8 @@ constexpr int kSortChunk = kSortThreads * kSortItems;  // keys per radix block
 constexpr int kBinChunk = 1024;      // depth-sorted Gaussians per binning wave
 constexpr int kMaxTilesPerView = 16384;
 constexpr int kMaxLevels = 8;
+constexpr int kGradStride = 16;      // floats per (view, Gaussian) gradient record (9 used, 64-byte aligned)
+constexpr int kGradLds = 10;         // LDS row stride of the per-entry gradient sums
 
 // Status word at the start of the workspace.
 struct Status {
@@ -42,7 +44,7 @@ struct RenderDims {
 
 // Byte offsets inside the workspace.
 struct Layout {
-  size_t status, records, rects, keys0, vals0, keys1, vals1, sort_hist, bin_hist, tile_tot, ranges, lists, t_final,
+  size_t status, records, rects, keys0, vals0, keys1, vals1, sort_hist, bin_rec, bin_hist, tile_tot, ranges, lists, t_final,
       n_last, grad2d, composed, d_composed, total;
 };
 

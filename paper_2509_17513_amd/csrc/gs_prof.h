@@ -26,6 +26,7 @@ enum KernelId {
   K_RATE_HIST_COUNT,
   K_RATE_HIST_BITS,
   K_ADAM,
+  K_BIN_GATHER,
   K_COUNT
 };
 

@@ -173,6 +173,7 @@ struct RateArgs {
   unsigned long long seed, offset;
   int lv[8];
   float wsym[8];  // per-symbol loss weight of each layer: lambda_rate lambda^l / |G^l|
+  float wfit;     // per-symbol weight of the maximum-likelihood fit of the MLP weights
 };
 
 __device__ __forceinline__ bf16x8 pack8(const uint16_t* h) {
@@ -258,8 +259,9 @@ template <bool GRAD>
 __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __restrict__ attrs,
                                                   const uint16_t* __restrict__ ctx, const uint16_t* __restrict__ W,
                                                   const float* __restrict__ Bv, double* __restrict__ bits_out,
-                                                  double* __restrict__ loss_out, float* __restrict__ d_attrs,
-                                                  float* __restrict__ d_w, float* __restrict__ d_b) {
+                                                  double* __restrict__ loss_out, float* __restrict__ sym_bits,
+                                                  float* __restrict__ d_attrs, float* __restrict__ d_w,
+                                                  float* __restrict__ d_b) {
   extern __shared__ __align__(16) char smem[];
   RateShared& sh = *(RateShared*)smem;
   RateWaveTmp* wt = (RateWaveTmp*)(smem + ((sizeof(RateShared) + 15) & ~(size_t)15));
@@ -379,13 +381,14 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
       if (g == 0) {
         bits_acc += bits;
         loss_acc += wsym * bits;
+        if (sym_bits) sym_bits[(size_t)a * n + sidx] = bits;
       }
       if (ra.mode == 1 && d_attrs && g == 0) d_attrs[(size_t)a * n + sidx] += wsym * dby;
     }
     if constexpr (GRAD) {
-      const float dout0 = valid ? -wsym * dby : 0.f;
+      const float dout0 = valid ? -ra.wfit * dby : 0.f;
       const float sig1 = 1.f / (1.f + expf(-o1));
-      const float dout1 = valid ? wsym * dbb * sig1 : 0.f;
+      const float dout1 = valid ? ra.wfit * dbb * sig1 : 0.f;
       // dZ2 = (W3^T dout) * GELU'(Z2)
       uint16_t d2b[32];
       for (int h = 0; h < 2; ++h)
@@ -595,8 +598,8 @@ int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step,
 
 
 int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
-                  const float* b_f32, double* bits_out, double* loss_out, float* d_attrs, float* d_w, float* d_b,
-                  void* stream) {
+                  const float* b_f32, double* bits_out, double* loss_out, float* sym_bits, float* d_attrs, float* d_w,
+                  float* d_b, void* stream) {
   if (!desc || !attrs || !ctx || !w_bf16 || !b_f32 || !bits_out) return GS_ERR_INVALID_ARG;
   const gs_rate_desc& d = *desc;
   if (d.n < 0 || d.n_attr < 1 || !(d.step > 0.f) || (d.mode != 0 && d.mode != 1)) return GS_ERR_INVALID_ARG;
@@ -607,6 +610,7 @@ int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* 
   RateArgs ra;
   ra.n = d.n; ra.n_attr = d.n_attr; ra.mode = d.mode; ra.n_levels = d.n_levels; ra.step = d.step;
   ra.seed = d.seed; ra.offset = d.offset;
+  ra.wfit = d.fit_scale;
   int prev = 0;
   for (int l = 0; l < 8; ++l) {
     ra.lv[l] = l < d.n_levels ? d.level_counts[l] : d.n;
@@ -623,10 +627,10 @@ int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* 
   ProfScope ps_(K_RATE_MLP, st);
   if (grad)
     hipLaunchKernelGGL(k_rate_mlp<true>, dim3(nb, d.n_attr), dim3(256), lds, st, ra, attrs, ctx, w_bf16, b_f32,
-                       bits_out, loss_out, d_attrs, d_w, d_b);
+                       bits_out, loss_out, sym_bits, d_attrs, d_w, d_b);
   else
     hipLaunchKernelGGL(k_rate_mlp<false>, dim3(nb, d.n_attr), dim3(256), lds, st, ra, attrs, ctx, w_bf16, b_f32,
-                       bits_out, loss_out, d_attrs, d_w, d_b);
+                       bits_out, loss_out, sym_bits, d_attrs, d_w, d_b);
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 

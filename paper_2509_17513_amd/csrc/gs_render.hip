@@ -249,7 +249,7 @@ __device__ __forceinline__ void load_frame(const RenderDims& d, const float* __r
 
 struct FrameGeom {
   float R[9], s2[3], Sig[6];  // Sigma: xx, xy, xz, yy, yz, zz
-  float o, rf;                // opacity, sqrt(2 ln(255 o))
+  float o, rf;                // opacity, sqrt(2 ln(o / alpha_min))
   float qinv;                 // 1 / |q|
   float qn[4];
   bool valid;
@@ -274,9 +274,14 @@ __device__ __forceinline__ FrameGeom frame_geom(const GaussFrame<DEG>& g) {
   fg.Sig[0] = sig(0, 0); fg.Sig[1] = sig(0, 1); fg.Sig[2] = sig(0, 2);
   fg.Sig[3] = sig(1, 1); fg.Sig[4] = sig(1, 2); fg.Sig[5] = sig(2, 2);
   fg.o = 1.0f / (1.0f + expf(-g.logit));
-  fg.valid = fg.valid && (255.0f * fg.o >= 1.0f);
-  fg.rf = fg.valid ? sqrtf(2.0f * logf(255.0f * fg.o)) : 0.f;
   return fg;
+}
+
+// Opacity cull and footprint factor: a Gaussian reaches alpha_min only where
+// its quadratic form is <= 2 ln(o / alpha_min).
+__device__ __forceinline__ void frame_footprint(FrameGeom& fg, float alpha_min) {
+  fg.valid = fg.valid && (fg.o >= alpha_min);
+  fg.rf = fg.valid ? sqrtf(2.0f * logf(fg.o / alpha_min)) : 0.f;
 }
 
 // View-level projection of one Gaussian.
@@ -372,7 +377,8 @@ __global__ __launch_bounds__(256) void k_project_fwd(RenderDims d, const float* 
   GaussFrame<DEG> g;
   for (int f = 0; f < d.F; ++f) {
     load_frame<DEG>(d, P, comp, d.Rc ? f : -1, i, g);
-    const FrameGeom fg = frame_geom<DEG>(g);
+    FrameGeom fg = frame_geom<DEG>(g);
+    frame_footprint(fg, d.alpha_min);
     for (int v = 0; v < d.V; ++v) {
       const int b = f * d.V + v;
       const gs_camera cam = cams[b];
@@ -422,7 +428,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(RenderDims d, const float* 
   for (int c = 0; c < 3 * K; ++c) t_sh[c] = 0.f;
   for (int f = 0; f < d.F; ++f) {
     load_frame<DEG>(d, P, comp, d.Rc ? f : -1, i, g);
-    const FrameGeom fg = frame_geom<DEG>(g);
+    FrameGeom fg = frame_geom<DEG>(g);
+    frame_footprint(fg, d.alpha_min);
     if (!fg.valid) continue;
     float Gs[6] = {0, 0, 0, 0, 0, 0};  // (G + G^T) of dL/dSigma: xx, xy, xz, yy, yz, zz
     float dmu[3] = {0, 0, 0}, dlg = 0.f;
@@ -432,11 +439,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(RenderDims d, const float* 
     for (int v = 0; v < d.V; ++v) {
       const int b = f * d.V + v;
       float gr[9];
-      bool any = false;
-      for (int c = 0; c < 9; ++c) {
-        gr[c] = g2d[((size_t)b * 9 + c) * n + i];
-        any = any || (gr[c] != 0.f);
+      {
+        const float4* gp = (const float4*)(g2d + ((size_t)b * n + i) * kGradStride);
+        const float4 g0 = gp[0], g1 = gp[1];
+        const float g8 = g2d[((size_t)b * n + i) * kGradStride + 8];
+        gr[0] = g0.x; gr[1] = g0.y; gr[2] = g0.z; gr[3] = g0.w;
+        gr[4] = g1.x; gr[5] = g1.y; gr[6] = g1.z; gr[7] = g1.w; gr[8] = g8;
       }
+      bool any = false;
+      for (int c = 0; c < 9; ++c) any = any || (gr[c] != 0.f);
       if (!any) continue;
       const gs_camera cam = cams[b];
       const ViewProj vp = view_proj(d, cam, g.mu, fg);
@@ -684,16 +695,45 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RenderDims d, co
 }
 
 // ============================================================ binning
+// Binning record of one depth-sorted (frame-view, Gaussian): mean2D, conic,
+// the alpha_min threshold of its quadratic form and its tile rectangle,
+// gathered once after the sort so that the count and emit passes read it
+// sequentially.
+__global__ __launch_bounds__(256) void k_bin_gather(RenderDims d, const uint32_t* __restrict__ skeys,
+                                                    const uint32_t* __restrict__ svals,
+                                                    const uint2* __restrict__ rects, const float4* __restrict__ rec,
+                                                    float4* __restrict__ brec) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (k >= d.n) return;
+  const size_t seg = (size_t)b * d.n;
+  float4 o0 = make_float4(0.f, 0.f, 1.f, 0.f), o1 = make_float4(1.f, -1.f, 0.f, 0.f);
+  if (skeys[seg + k] != 0xFFFFFFFFu) {
+    const uint32_t i = svals[seg + k];
+    const float4 r0 = rec[3 * (seg + i)], r1 = rec[3 * (seg + i) + 1];
+    const uint2 rc = rects[seg + i];
+    // quadratic-form threshold of alpha >= alpha_min, with a relative margin of 1e-3
+    const float tau = 2.f * (logf(r1.y) - logf(d.alpha_min)) * 1.001f + 1e-3f;
+    o0 = r0;
+    o1 = make_float4(r1.x, tau, __uint_as_float(rc.x), __uint_as_float(rc.y));
+  }
+  brec[2 * (seg + k)] = o0;
+  brec[2 * (seg + k) + 1] = o1;
+}
+
 // Each wave walks kBinChunk depth-sorted Gaussians of one frame-view in order;
 // its 64 lanes cover the tiles of one Gaussian at a time, so the per-tile
 // counters in LDS see the Gaussians in depth order (a stable counting sort).
-__device__ __forceinline__ void rect_unpack(uint2 r, int& x0, int& x1, int& y0, int& y1) {
-  x0 = r.x & 0xFFFF; x1 = r.x >> 16; y0 = r.y & 0xFFFF; y1 = r.y >> 16;
-}
-
+// A tile of the bounding rectangle is kept only if the ellipse
+// q(p) = (p - m)^T [[A, B], [B, C]] (p - m) <= tau reaches one of its pixel
+// centres: per tile row, the exact x-extent of the ellipse over the row's band
+// of pixel-centre heights is compared with the tile's pixel-centre columns.
+// The extent's right end is a concave function of the height with its maximum
+// at the ellipse's rightmost point, so it is evaluated at that height clamped
+// to the band (and symmetrically for the left end).
 template <bool EMIT>
 __global__ __launch_bounds__(64) void k_bin(RenderDims d, const uint32_t* __restrict__ skeys,
-                                            const uint32_t* __restrict__ svals, const uint2* __restrict__ rects,
+                                            const uint32_t* __restrict__ svals, const float4* __restrict__ brec,
                                             uint32_t* __restrict__ bhist, const uint2* __restrict__ ranges,
                                             uint32_t* __restrict__ lists) {
   extern __shared__ uint32_t cnt[];
@@ -709,30 +749,55 @@ __global__ __launch_bounds__(64) void k_bin(RenderDims d, const uint32_t* __rest
   for (int base = start; base < end; base += 64) {
     const int e = base + lane;
     uint32_t idx = 0;
-    uint2 rc = make_uint2(1u, 0u);  // empty: x0 = 1 > x1 = 0
+    float4 q0 = make_float4(0.f, 0.f, 1.f, 0.f), q1 = make_float4(1.f, -1.f, 0.f, 0.f);
     bool ok = false;
     if (e < end) {
       ok = skeys[seg + e] != 0xFFFFFFFFu;
       if (ok) {
         idx = svals[seg + e];
-        rc = rects[seg + idx];
+        q0 = brec[2 * (seg + e)];
+        q1 = brec[2 * (seg + e) + 1];
       }
     }
     const unsigned long long live = __ballot(ok);
     if (live == 0ull) break;  // culled keys sort last
     const int nlive = 64 - __clzll(live);  // keys are sorted, so live lanes are a prefix
     for (int j = 0; j < nlive; ++j) {
-      const uint32_t gi = __shfl(idx, j);
-      uint2 r;
-      r.x = __shfl(rc.x, j);
-      r.y = __shfl(rc.y, j);
-      int x0, x1, y0, y1;
-      rect_unpack(r, x0, x1, y0, y1);
+      const uint32_t gi = __builtin_amdgcn_readlane(idx, j);
+      const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.x), j));
+      const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.y), j));
+      const float A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.z), j));
+      const float B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.w), j));
+      const float C = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.x), j));
+      const float tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.y), j));
+      const uint32_t rx = __builtin_amdgcn_readlane(__float_as_uint(q1.z), j);
+      const uint32_t ry = __builtin_amdgcn_readlane(__float_as_uint(q1.w), j);
+      const int x0 = rx & 0xFFFF, x1 = rx >> 16, y0 = ry & 0xFFFF, y1 = ry >> 16;
       const int w = x1 - x0 + 1, h = y1 - y0 + 1;
       const int total = w * h;
+      // per-Gaussian constants of the extent computation
+      const float det = A * C - B * B;
+      const float iA = 1.f / A;
+      const float dxm = sqrtf(fmaxf(tau * C / det, 0.f));  // half-width of the ellipse
+      const float dyr = -B * dxm / C;                      // height offset of its rightmost point
+      const float dym = sqrtf(fmaxf(A * tau / det, 0.f));  // half-height
+      const float iw = 1.f / (float)w;
       for (int l = lane; l < total; l += 64) {
-        const int ly = l / w;
-        const int tile = (y0 + ly) * d.TX + x0 + (l - ly * w);
+        int ly = (int)((float)l * iw);
+        int lx = l - ly * w;
+        if (lx < 0) { --ly; lx += w; } else if (lx >= w) { ++ly; lx -= w; }
+        const int tx = x0 + lx, ty = y0 + ly;
+        const float Y0 = (float)(ty * kTile) + 0.5f - my;
+        const float Y1 = (float)(min(ty * kTile + kTile, d.H) - 1) + 0.5f - my;
+        const float lo = fmaxf(Y0, -dym), hi = fminf(Y1, dym);
+        if (!(lo <= hi)) continue;
+        const float dr = fminf(fmaxf(dyr, lo), hi), dl = fminf(fmaxf(-dyr, lo), hi);
+        const float xr = (-B * dr + sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
+        const float xl = (-B * dl - sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
+        const float X0 = (float)(tx * kTile) + 0.5f - mx;
+        const float X1 = (float)(min(tx * kTile + kTile, d.W) - 1) + 0.5f - mx;
+        if (X0 > xr || X1 < xl) continue;
+        const int tile = ty * d.TX + tx;
         if (EMIT) {
           const uint32_t pos = cnt[tile];
           if (pos < d.capacity) lists[pos] = gi;
@@ -841,6 +906,32 @@ __device__ __forceinline__ void flush_counters(uint32_t evals, uint32_t contribs
   }
 }
 
+// Smallest layer a Gaussian of index gi belongs to (layers are nested prefixes).
+__device__ __forceinline__ uint32_t first_layer(const RenderDims& d, uint32_t gi) {
+  uint32_t l = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxLevels - 1; ++q) l += (q < d.L - 1 && gi >= (uint32_t)d.lv[q]) ? 1u : 0u;
+  return l;
+}
+
+// Block-wide stable compaction of one candidate per thread: returns the slot of
+// this thread's candidate (if `keep`) and the number kept in *total.
+__device__ __forceinline__ int compact_slot(bool keep, uint32_t* s_wcnt, int* total) {
+  const int t = threadIdx.x, w = t >> 6;
+  const unsigned long long m = __ballot(keep);
+  if ((t & 63) == 0) s_wcnt[w] = (uint32_t)__popcll(m);
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < kTilePix / 64; ++q) {
+    const int c = (int)s_wcnt[q];
+    off += q < w ? c : 0;
+    tot += c;
+  }
+  *total = tot;
+  return off + (int)popc_below(m);
+}
+
 template <int MAXL>
 __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
@@ -851,8 +942,10 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
   TileCtx c;
   if (!tile_ctx(d, ranges, c)) return;
   __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
-  __shared__ float4 s_b[kTilePix];  // conic A, B, C
-  __shared__ float4 s_c[kTilePix];  // r, g, b
+  __shared__ float4 s_b[kTilePix];  // conic A, B, C, first layer bits
+  __shared__ float4 s_c[kTilePix];  // r, g, b, list position bits
+  __shared__ uint32_t s_wcnt[kTilePix / 64];
+  __shared__ uint32_t s_hi;
   const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
   float Tr[MAXL], Cr[MAXL], Cg[MAXL], Cb[MAXL];
   uint32_t last[MAXL];
@@ -864,23 +957,31 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
   const int t = threadIdx.x;
   uint32_t n_eval = 0, n_contrib = 0;
   for (uint32_t base = c.range.x; base < c.range.y; base += kTilePix) {
-    if (__syncthreads_count(alive != 0u) == 0) break;
+    // entries of index >= every pixel's highest open layer bound are useless to the whole tile
+    if (t == 0) s_hi = 0;
+    __syncthreads();
+    if (nlhi) atomicMax(&s_hi, nlhi);
+    __syncthreads();
+    const uint32_t hib = s_hi;
+    if (hib == 0) break;
     const uint32_t k = base + t;
-    if (k < c.range.y) {
-      const uint32_t gi = lists[k];
+    uint32_t gi = 0xFFFFFFFFu;
+    if (k < c.range.y) gi = lists[k];
+    int cnt;
+    const int slot = compact_slot(gi < hib, s_wcnt, &cnt);
+    if (gi < hib) {
       const float4* r = rec + 3 * (recbase + gi);
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      s_a[t] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
-      s_b[t] = make_float4(r0.z, r0.w, r1.x, 0.f);
-      s_c[t] = make_float4(r1.z, r1.w, r2.x, 0.f);
+      s_a[slot] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
+      s_b[slot] = make_float4(r0.z, r0.w, r1.x, __uint_as_float(first_layer(d, gi)));
+      s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k - c.range.x + 1));
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kTilePix, c.range.y - base);
     if (alive) {
       for (int j = 0; j < cnt; ++j) {
         const float4 a = s_a[j];
-        const uint32_t gi = __float_as_uint(a.w);
-        if (gi >= nlhi) continue;
+        const uint32_t g = __float_as_uint(a.w);
+        if (g >= nlhi) continue;
         const float4 cb = s_b[j];
         const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
         ++n_eval;
@@ -888,9 +989,10 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
         const float al = fminf(d.alpha_max, ev.ga);
         const float oma = 1.f - al;
         const float4 col = s_c[j];
+        const uint32_t lmin = __float_as_uint(cb.w);
 #pragma unroll
         for (int l = 0; l < MAXL; ++l) {
-          if (!((alive >> l) & 1u) || gi >= (uint32_t)d.lv[l]) continue;
+          if ((uint32_t)l < lmin || !((alive >> l) & 1u)) continue;
           const float Tn = Tr[l] * oma;
           if (Tn < d.t_stop) {
             alive &= ~(1u << l);
@@ -901,12 +1003,13 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
           Cg[l] = fmaf(col.y, wgt, Cg[l]);
           Cb[l] = fmaf(col.z, wgt, Cb[l]);
           Tr[l] = Tn;
-          last[l] = base + j + 1 - c.range.x;
+          last[l] = __float_as_uint(col.w);
           ++n_contrib;
         }
         if (!alive) break;
         nlhi = (uint32_t)d.lv[31 - __clz(alive)];
       }
+      if (!alive) nlhi = 0;
     }
   }
   flush_counters(n_eval, n_contrib, &st->fwd_evals, &st->fwd_contribs);
@@ -939,20 +1042,23 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   if (st->overflow) return;
   TileCtx c;
   if (!tile_ctx(d, ranges, c)) return;
-  __shared__ float4 s_a[kTilePix];
-  __shared__ float4 s_b[kTilePix];
-  __shared__ float4 s_c[kTilePix];
-  __shared__ uint32_t s_kmax;
+  __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
+  __shared__ float4 s_b[kTilePix];  // conic A, B, C, first layer bits
+  __shared__ float4 s_c[kTilePix];  // r, g, b, list position bits
+  __shared__ float s_g[kTilePix][kGradLds];  // per-entry gradient sums of the four waves
+  __shared__ uint32_t s_wcnt[kTilePix / 64];
+  __shared__ uint32_t s_lmax[kMaxLevels];
   __shared__ float s_loss;
   const int t = threadIdx.x;
-  if (t == 0) { s_kmax = 0; s_loss = 0.f; }
+  if (t < kMaxLevels) s_lmax[t] = 0;
+  if (t == 0) s_loss = 0.f;
+  for (int v = 0; v < kGradLds; ++v) s_g[t][v] = 0.f;
   __syncthreads();
   const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
   const size_t HW = (size_t)d.W * d.H;
   const size_t pix = (size_t)c.py * d.W + c.px;
   float Tr[MAXL], wr[MAXL], wg[MAXL], wb[MAXL], Sr[MAXL], Sg[MAXL], Sb[MAXL];
   uint32_t last[MAXL];
-  uint32_t kmax = 0;
   float loss = 0.f;
   const float inv3hw = 1.0f / (3.0f * (float)HW);
 #pragma unroll
@@ -974,7 +1080,7 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
         }
       }
       wr[l] = w3[0]; wg[l] = w3[1]; wb[l] = w3[2];
-      kmax = max(kmax, last[l]);
+      if (last[l]) atomicMax(&s_lmax[l], last[l]);
     }
     Sr[l] = Tr[l] * d.bg[0]; Sg[l] = Tr[l] * d.bg[1]; Sb[l] = Tr[l] * d.bg[2];
   }
@@ -982,48 +1088,64 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
     loss = wave_sum(loss);
     if ((t & 63) == 0) atomicAdd(&s_loss, loss);
   }
-  atomicMax(&s_kmax, kmax);
   __syncthreads();
   if (loss_out && t == 0) unsafeAtomicAdd(loss_out, s_loss);
-  const uint32_t ktop = s_kmax;
+  uint32_t lmax[MAXL];
+  uint32_t ktop = 0;
+#pragma unroll
+  for (int l = 0; l < MAXL; ++l) {
+    lmax[l] = l < d.L ? s_lmax[l] : 0u;
+    ktop = max(ktop, lmax[l]);
+  }
   const size_t recbase = (size_t)c.b * d.n;
   const int lane = t & 63;
   uint32_t n_eval = 0, n_contrib = 0;
+  const int vid = (lane >> 3) & 7;  // value a lane holds after the reduce-scatter
   for (int top = (int)ktop; top > 0; top -= kTilePix) {
     const int lo = max(0, top - kTilePix);
-    const int cnt = top - lo;
     __syncthreads();
-    if (t < cnt) {
-      const uint32_t gi = lists[c.range.x + lo + t];
+    // stage the entries some pixel of the tile still needs (position before that layer's last
+    // contributor, index inside the layer), keeping their order
+    const uint32_t k = (uint32_t)(lo + t);
+    uint32_t gi = 0xFFFFFFFFu;
+    bool need = false;
+    if ((int)k < top) {
+      gi = lists[c.range.x + k];
+#pragma unroll
+      for (int l = 0; l < MAXL; ++l) need = need || (k < lmax[l] && gi < (uint32_t)d.lv[l]);
+    }
+    int cnt;
+    const int slot = compact_slot(need, s_wcnt, &cnt);
+    if (need) {
       const float4* r = rec + 3 * (recbase + gi);
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      s_a[t] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
-      s_b[t] = make_float4(r0.z, r0.w, r1.x, 0.f);
-      s_c[t] = make_float4(r1.z, r1.w, r2.x, 0.f);
+      s_a[slot] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
+      s_b[slot] = make_float4(r0.z, r0.w, r1.x, __uint_as_float(first_layer(d, gi)));
+      s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k));
     }
     __syncthreads();
     for (int j = cnt - 1; j >= 0; --j) {
-      const uint32_t k = (uint32_t)(lo + j);
       const float4 a = s_a[j];
-      const uint32_t gi = __float_as_uint(a.w);
+      const float4 col = s_c[j];
+      const uint32_t kk = __float_as_uint(col.w);
+      const float4 cb = s_b[j];
+      const uint32_t lmin = __float_as_uint(cb.w);
       bool cand = false;
 #pragma unroll
-      for (int l = 0; l < MAXL; ++l) cand = cand || (k < last[l] && gi < (uint32_t)d.lv[l]);
+      for (int l = 0; l < MAXL; ++l) cand = cand || ((uint32_t)l >= lmin && kk < last[l]);
       float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
       bool contrib = false;
       if (cand) {
-        const float4 cb = s_b[j];
         const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
         ++n_eval;
         if (ev.ga >= d.alpha_min) {
           const float al = fminf(d.alpha_max, ev.ga);
           const float oma = 1.f - al;
           const float ioma = 1.0f / oma;
-          const float4 col = s_c[j];
           float dal = 0.f;
 #pragma unroll
           for (int l = 0; l < MAXL; ++l) {
-            if (!(k < last[l] && gi < (uint32_t)d.lv[l])) continue;
+            if (!((uint32_t)l >= lmin && kk < last[l])) continue;
             const float Tb = Tr[l] * ioma;  // transmittance in front of this Gaussian
             const float wT = al * Tb;
             g[6] = fmaf(wr[l], wT, g[6]);
@@ -1050,13 +1172,55 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
         }
       }
       if (__ballot(contrib) != 0ull) {
+        // reduce-scatter of values 0..7 over the wave (each step halves the values a lane keeps),
+        // then a plain reduction of the last value and of value 8
+        float v8 = g[8];
+        {
+          const bool hi = lane & 32;
 #pragma unroll
-        for (int m = 0; m < 9; ++m) g[m] = wave_sum(g[m]);
-        if (lane == 0) {
-          float* dst = g2d + (size_t)c.b * 9 * d.n + gi;
+          for (int q = 0; q < 4; ++q) {
+            const float send = hi ? g[q] : g[q + 4];
+            const float keep = hi ? g[q + 4] : g[q];
+            g[q] = keep + __shfl_xor(send, 32);
+          }
+          v8 += __shfl_xor(v8, 32);
+        }
+        {
+          const bool hi = lane & 16;
 #pragma unroll
-          for (int m = 0; m < 9; ++m)
-            if (g[m] != 0.f) unsafeAtomicAdd(dst + (size_t)m * d.n, g[m]);
+          for (int q = 0; q < 2; ++q) {
+            const float send = hi ? g[q] : g[q + 2];
+            const float keep = hi ? g[q + 2] : g[q];
+            g[q] = keep + __shfl_xor(send, 16);
+          }
+          v8 += __shfl_xor(v8, 16);
+        }
+        {
+          const bool hi = lane & 8;
+          const float send = hi ? g[0] : g[1];
+          const float keep = hi ? g[1] : g[0];
+          g[0] = keep + __shfl_xor(send, 8);
+          v8 += __shfl_xor(v8, 8);
+        }
+#pragma unroll
+        for (int off = 4; off > 0; off >>= 1) {
+          g[0] += __shfl_xor(g[0], off);
+          v8 += __shfl_xor(v8, off);
+        }
+        if ((lane & 7) == 0 && g[0] != 0.f) atomicAdd(&s_g[j][vid], g[0]);
+        if (lane == 0 && v8 != 0.f) atomicAdd(&s_g[j][8], v8);
+      }
+    }
+    __syncthreads();
+    if (t < cnt) {
+      const uint32_t g_i = __float_as_uint(s_a[t].w);
+      float* dst = g2d + (recbase + g_i) * kGradStride;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) {
+        const float x = s_g[t][v];
+        if (x != 0.f) {
+          unsafeAtomicAdd(dst + v, x);
+          s_g[t][v] = 0.f;
         }
       }
     }
@@ -1167,6 +1331,8 @@ hipError_t launch_sort(const RenderDims& d, char* ws, const Layout& lo, uint32_t
 hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t* svals, char* ws, const Layout& lo,
                       hipStream_t st) {
   const uint2* rects = (const uint2*)(ws + lo.rects);
+  const float4* rec = (const float4*)(ws + lo.records);
+  float4* brec = (float4*)(ws + lo.bin_rec);
   uint32_t* bhist = (uint32_t*)(ws + lo.bin_hist);
   uint2* ranges = (uint2*)(ws + lo.ranges);
   uint32_t* lists = (uint32_t*)(ws + lo.lists);
@@ -1174,11 +1340,14 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   Status* status = (Status*)(ws + lo.status);
   dim3 grid(d.n_bin_chunks, d.B);
   const size_t lds = (size_t)d.T * sizeof(uint32_t);
-  if (d.n_bin_chunks > 0)
-    {
-      ProfScope ps_(K_BIN_COUNT, st);
-      hipLaunchKernelGGL(k_bin<false>, grid, dim3(64), lds, st, d, skeys, svals, rects, bhist, ranges, lists);
-    }
+  if (d.n_bin_chunks > 0) {
+    ProfScope ps_(K_BIN_GATHER, st);
+    hipLaunchKernelGGL(k_bin_gather, dim3((d.n + 255) / 256, d.B), dim3(256), 0, st, d, skeys, svals, rects, rec, brec);
+  }
+  if (d.n_bin_chunks > 0) {
+    ProfScope ps_(K_BIN_COUNT, st);
+    hipLaunchKernelGGL(k_bin<false>, grid, dim3(64), lds, st, d, skeys, svals, brec, bhist, ranges, lists);
+  }
   {
     ProfScope ps_(K_BIN_CHUNK_SCAN, st);
     hipLaunchKernelGGL(k_bin_chunk_scan, dim3((d.B * d.T + 255) / 256), dim3(256), 0, st, d, bhist, tot);
@@ -1187,11 +1356,10 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
     ProfScope ps_(K_TILE_RANGES, st);
     hipLaunchKernelGGL(k_tile_ranges, dim3(1), dim3(1024), 0, st, d, tot, ranges, status);
   }
-  if (d.n_bin_chunks > 0)
-    {
-      ProfScope ps_(K_BIN_EMIT, st);
-      hipLaunchKernelGGL(k_bin<true>, grid, dim3(64), lds, st, d, skeys, svals, rects, bhist, ranges, lists);
-    }
+  if (d.n_bin_chunks > 0) {
+    ProfScope ps_(K_BIN_EMIT, st);
+    hipLaunchKernelGGL(k_bin<true>, grid, dim3(64), lds, st, d, skeys, svals, brec, bhist, ranges, lists);
+  }
   return hipGetLastError();
 }
 

@@ -1,0 +1,256 @@
+"""Joint training of Gaussians and the learned rate model, on the library's kernels.
+
+One step (every compute step is a C-ABI call into libgs4d.so; torch only holds memory):
+  forward render of all views and layers -> fused layer-weighted L1 backward into d_params
+  -> context features -> learned rate in training mode (uniform-noise quantisation; the rate
+  gradient lands directly in the attribute rows of d_params, the maximum-likelihood fit of the
+  entropy model in d_w, d_b) -> Adam on the parameter groups and on the MLP (FP32 masters with
+  BF16 copies for the MFMA).
+
+This is the keyframe objective of Sec. 3.3: sum_l lambda^l (L1^l + lambda_rate R^l) with the
+D-SSIM weight 0 and the learned Laplace model as the differentiable rate.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+from .render import RenderSettings, Workspace, render_backward, render_forward
+
+W_PER_ATTR = 16 * 64 + 64 * 64 + 2 * 64
+B_PER_ATTR = 64 + 64 + 2
+CTX_DIM = 16
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _s(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _off(t, elems):
+    """Pointer elems float32 elements into t."""
+    return ctypes.c_void_p(t.data_ptr() + 4 * elems)
+
+
+def zero(t):
+    check(lib().gs_zero(_p(t), t.numel() * t.element_size(), _s(t.device)), "gs_zero")
+
+
+class Adam:
+    """Adam state of one float32 device tensor; slices of it can be stepped with their own rate."""
+
+    def __init__(self, param: torch.Tensor, betas=(0.9, 0.999), eps=1e-15):
+        self.p = param
+        self.m = torch.zeros_like(param)
+        self.v = torch.zeros_like(param)
+        self.b1, self.b2 = betas
+        self.eps = eps
+
+    def step(self, grad: torch.Tensor, lr: float, t: int, start: int = 0, count: int | None = None,
+             bf16_copy: torch.Tensor | None = None):
+        count = self.p.numel() - start if count is None else count
+        cp = None if bf16_copy is None else ctypes.c_void_p(bf16_copy.data_ptr() + 2 * start)
+        check(lib().gs_adam_step(count, _off(self.p, start), _off(grad, start), _off(self.m, start),
+                                 _off(self.v, start), cp, ctypes.c_float(lr), ctypes.c_float(self.b1),
+                                 ctypes.c_float(self.b2), ctypes.c_float(self.eps), t, _s(self.p.device)),
+              "gs_adam_step")
+
+
+def _bf16_bits(x: np.ndarray) -> np.ndarray:
+    """float64 -> BF16 bit patterns, round to nearest even (host-side initialisation only)."""
+    u = x.astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+class RateModel:
+    """Per-attribute Laplace MLP (16 -> 64 -> 64 -> 2): FP32 masters, BF16 copies, Adam state."""
+
+    def __init__(self, n_attr: int, device, seed: int = 0, attrs_host: np.ndarray | None = None,
+                 step: float = 1.0 / 64):
+        rng = np.random.default_rng(seed)
+        w = np.zeros((n_attr, W_PER_ATTR))
+        w[:, :1024] = rng.standard_normal((n_attr, 1024)) * 0.25
+        w[:, 1024:5120] = rng.standard_normal((n_attr, 4096)) * 0.125
+        w[:, 5120:] = rng.standard_normal((n_attr, 128)) * 0.0125
+        b = np.zeros((n_attr, B_PER_ATTR), np.float32)
+        if attrs_host is not None:
+            a64 = attrs_host.astype(np.float64)
+            mu = a64.mean(axis=1)
+            mad = np.abs(a64 - mu[:, None]).mean(axis=1)
+            b[:, 128] = mu
+            target = np.maximum(mad - step / 16, step / 4)
+            b[:, 129] = np.log(np.expm1(target))
+        self.n_attr, self.step_size = n_attr, step
+        self.w = torch.from_numpy(w.astype(np.float32)).to(device)
+        self.w16 = torch.from_numpy(_bf16_bits(w).view(np.int16)).to(device)
+        self.b = torch.from_numpy(b).to(device)
+        self.dw = torch.zeros_like(self.w)
+        self.db = torch.zeros_like(self.b)
+        self.opt_w = Adam(self.w)
+        self.opt_b = Adam(self.b)
+        self.bits = torch.zeros(n_attr, dtype=torch.float64, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        self.t = 0
+
+    def desc(self, n, mode, level_counts, level_weights, lambda_rate, seed=0, offset=0, fit_scale=None):
+        d = _lib.GsRateDesc()
+        d.n, d.n_attr, d.step, d.mode, d.seed, d.offset = n, self.n_attr, self.step_size, mode, seed, offset
+        d.n_levels = len(level_counts)
+        for i, v in enumerate(level_counts):
+            d.level_counts[i] = int(v)
+            d.level_weights[i] = float(level_weights[i])
+        d.lambda_rate = lambda_rate
+        d.fit_scale = (1.0 / max(n, 1)) if fit_scale is None else fit_scale
+        return d
+
+    def run(self, attrs_ptr, n, ctx, mode, level_counts, level_weights, lambda_rate=0.0, seed=0, offset=0,
+            d_attrs_ptr=None, grads=True, sym_bits=None):
+        """Accumulates bits / loss (and gradients) of one pass; zero them first with reset()."""
+        d = self.desc(n, mode, level_counts, level_weights, lambda_rate, seed, offset)
+        check(lib().gs_rate_model(ctypes.byref(d), attrs_ptr, _p(ctx), _p(self.w16), _p(self.b), _p(self.bits),
+                                  _p(self.loss), _p(sym_bits), d_attrs_ptr, _p(self.dw) if grads else None,
+                                  _p(self.db) if grads else None, _s(self.w.device)), "gs_rate_model")
+
+    def reset(self):
+        zero(self.bits)
+        zero(self.loss)
+
+    def adam(self, lr: float):
+        self.t += 1
+        self.opt_w.step(self.dw, lr, self.t, bf16_copy=self.w16)
+        self.opt_b.step(self.db, lr, self.t)
+
+
+def context(params: torch.Tensor, extent: float, level_counts, out: torch.Tensor | None = None):
+    n = params.shape[1]
+    if out is None:
+        out = torch.zeros((n, CTX_DIM), dtype=torch.int16, device=params.device)
+    lv = (ctypes.c_int32 * len(level_counts))(*[int(v) for v in level_counts])
+    check(lib().gs_rate_context(n, _p(params), ctypes.c_float(extent), len(level_counts), lv, _p(out),
+                                _s(params.device)), "gs_rate_context")
+    return out
+
+
+def histogram_bits(attrs: torch.Tensor, step: float = 1.0 / 64, ws: torch.Tensor | None = None):
+    """Per-attribute empirical-histogram rate (float64 bits) of attrs [A][n] (synchronises)."""
+    A, n = attrs.shape
+    sz = ctypes.c_size_t()
+    check(lib().gs_rate_histogram_workspace_size(A, ctypes.byref(sz)), "gs_rate_histogram_workspace_size")
+    if ws is None or ws.numel() < sz.value:
+        ws = torch.zeros(sz.value, dtype=torch.uint8, device=attrs.device)
+    bits = torch.zeros(A, dtype=torch.float64, device=attrs.device)
+    check(lib().gs_rate_histogram(n, A, _p(attrs), ctypes.c_float(step), _p(bits), _p(ws), ws.numel(),
+                                  _s(attrs.device)), "gs_rate_histogram")
+    return bits
+
+
+@dataclasses.dataclass
+class LearningRates:
+    """Per-group Adam rates of the Gaussian parameters (3DGS-style) and of the rate MLP."""
+    mean: float = 1.6e-4
+    log_scale: float = 5e-3
+    quat: float = 1e-3
+    logit: float = 5e-2
+    sh_dc: float = 2.5e-3
+    sh_rest: float = 2.5e-3 / 20
+    mlp: float = 2e-3
+
+
+class JointTrainer:
+    """Keyframe training with layer-weighted L1 and the learned rate on all views and layers at once."""
+
+    def __init__(self, params: torch.Tensor, cams: torch.Tensor, targets: torch.Tensor, settings: RenderSettings,
+                 rate: RateModel | None, lambda_rate: float = 0.0, extent: float = 1.0,
+                 lrs: LearningRates | None = None, seed: int = 0):
+        self.p, self.cams, self.tgt, self.st = params, cams, targets, settings
+        self.n = params.shape[1]
+        self.rate, self.lam, self.extent = rate, lambda_rate, extent
+        self.lrs = lrs or LearningRates()
+        self.dp = torch.zeros_like(params)
+        self.opt = Adam(params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        self.ctx = torch.zeros((self.n, CTX_DIM), dtype=torch.int16, device=params.device)
+        self.t = 0
+        self.seed = seed
+        self.img, self.ws = render_forward(settings, params, cams)  # sizes the workspace
+        self.levels = list(settings.level_counts) if settings.level_counts else [self.n]
+        self.level_w = list(settings.level_weights) if settings.level_weights else [1.0] * len(self.levels)
+
+    def step(self, check_overflow: bool = False):
+        n = self.n
+        zero(self.loss)
+        render_forward(self.st, self.p, self.cams, ws=self.ws, image=self.img, check_overflow=check_overflow)
+        render_backward(self.st, self.p, self.cams, self.ws, image=self.img, target=self.tgt, d_params=self.dp,
+                        loss=self.loss)
+        if self.rate is not None:
+            self.rate.reset()
+            context(self.p, self.extent, self.levels, self.ctx)
+            A = self.rate.n_attr
+            self.rate.run(_off(self.p, 3 * n), n, self.ctx, 1, self.levels, self.level_w, self.lam,
+                          seed=self.seed, offset=self.t * A * n,
+                          d_attrs_ptr=_off(self.dp, 3 * n) if self.lam > 0 else None)
+            self.rate.adam(self.lrs.mlp)
+        self.t += 1
+        K = self.p.shape[0] - 11
+        lr = self.lrs
+        for lo, hi, r in ((0, 3, lr.mean), (3, 6, lr.log_scale), (6, 10, lr.quat), (10, 11, lr.logit),
+                          (11, 14, lr.sh_dc), (14, 11 + K, lr.sh_rest)):
+            if hi > lo:
+                self.opt.step(self.dp, r, self.t, start=lo * n, count=(hi - lo) * n)
+
+    def eval_rate(self):
+        """(MLP bits per attribute in evaluation mode, histogram bits per attribute), float64 numpy."""
+        n = self.n
+        A = self.rate.n_attr
+        self.rate.reset()
+        context(self.p, self.extent, self.levels, self.ctx)
+        self.rate.run(_off(self.p, 3 * n), n, self.ctx, 0, self.levels, self.level_w, self.lam, grads=False)
+        attrs = self.p[3:3 + A]
+        hb = histogram_bits(attrs, self.rate.step_size)
+        torch.cuda.synchronize()
+        return self.rate.bits.cpu().numpy(), hb.cpu().numpy()
+
+
+def laplace_fit_bits(attrs: np.ndarray, step: float) -> np.ndarray:
+    """Context-free baseline: per-attribute Laplace with the maximum-likelihood location (median)
+    and scale (mean absolute deviation), bits of the rint-quantised symbols (host, float64)."""
+    out = np.zeros(attrs.shape[0])
+    for a in range(attrs.shape[0]):
+        y = np.rint(attrs[a].astype(np.float64) / step) * step
+        m = np.median(y)
+        b = max(np.abs(y - m).mean(), step / 16)
+        t = np.abs(y - m)
+        h = step / 2
+        with np.errstate(divide="ignore", over="ignore"):
+            far = math.log(0.5) - (t - h) / b + math.log(-math.expm1(-step / b))
+            near = np.log(np.maximum(1 - 0.5 * np.exp(-(h + t) / b) - 0.5 * np.exp(-(h - t) / b), 1e-300))
+        lp = np.maximum(np.where(t >= h, far, near), math.log(1e-9))
+        out[a] = -lp.sum() / math.log(2)
+    return out
+
+
+def gaussian_fit_bits(attrs: np.ndarray, step: float) -> np.ndarray:
+    """The paper's residual entropy model (Sec. 3.3, inter-frame stage): a Gaussian with the
+    attribute's mean and variance, bits of the rint-quantised symbols (host, float64)."""
+    from math import erf, sqrt
+    out = np.zeros(attrs.shape[0])
+    verf = np.vectorize(erf)
+    for a in range(attrs.shape[0]):
+        y = np.rint(attrs[a].astype(np.float64) / step) * step
+        mu, sd = y.mean(), max(y.std(), step / 16)
+        ks, cnt = np.unique(y, return_counts=True)
+        hi = 0.5 * (1 + verf((ks + step / 2 - mu) / (sd * sqrt(2))))
+        lo = 0.5 * (1 + verf((ks - step / 2 - mu) / (sd * sqrt(2))))
+        P = np.maximum(hi - lo, 1e-9)
+        out[a] = -(cnt * np.log2(P)).sum()
+    return out

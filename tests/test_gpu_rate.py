@@ -36,7 +36,7 @@ def _attrs(n, seed=61):
     return np.ascontiguousarray(p[3:]), np.ascontiguousarray(p[0:3])
 
 
-def _desc(n, A, mode, lv=None, lw=None, lam=1.0, seed=0, offset=0):
+def _desc(n, A, mode, lv=None, lw=None, lam=1.0, seed=0, offset=0, fit=None):
     L = _lib()
     d = L.GsRateDesc()
     d.n, d.n_attr, d.step, d.mode, d.seed, d.offset = n, A, Q, mode, seed, offset
@@ -47,6 +47,7 @@ def _desc(n, A, mode, lv=None, lw=None, lam=1.0, seed=0, offset=0):
         d.level_counts[i] = v
         d.level_weights[i] = lw[i]
     d.lambda_rate = lam
+    d.fit_scale = 1.0 / n if fit is None else fit
     return d
 
 
@@ -115,8 +116,8 @@ def _gpu_mlp(attrs, ctx, wbits, bf, lv, lw, mode, lam, seed=0, offset=0, grad=Tr
     db = torch.zeros((A, rate.B_PER_ATTR), dtype=torch.float32, device=dev) if grad else None
     d = _desc(n, A, mode, lv, lw, lam, seed, offset)
     P = lambda t: None if t is None else _p(t)  # noqa: E731
-    L.check(L.lib().gs_rate_model(ctypes.byref(d), _p(a), _p(c), _p(w), _p(b), _p(bits), _p(loss), P(da), P(dw),
-                                  P(db), _stream()), "gs_rate_model")
+    L.check(L.lib().gs_rate_model(ctypes.byref(d), _p(a), _p(c), _p(w), _p(b), _p(bits), _p(loss), None, P(da),
+                                  P(dw), P(db), _stream()), "gs_rate_model")
     torch.cuda.synchronize()
     out = {"bits": bits.cpu().numpy(), "loss": float(loss.item())}
     if da is not None:
@@ -148,7 +149,7 @@ def test_mlp_train_gradients_match_oracle():
     lam = 3.0
     g = _gpu_mlp(attrs, ctx, wbits, bf, lv, lw, 1, lam, seed=99, offset=12345)
     ref = rate.rate_model(attrs, ctx, wbits, bf, Q, mode=1, seed=99, offset=12345,
-                          sym_w=rate.symbol_weights(n, lv, lw, lam))
+                          sym_w=rate.symbol_weights(n, lv, lw, lam), fit_scale=1.0 / n)
     np.testing.assert_allclose(g["bits"], ref["bits"], rtol=1e-3)
     assert abs(g["loss"] - ref["loss"]) <= 1e-3 * abs(ref["loss"])
     da, rda = g["d_attrs"], ref["d_attrs"]
