@@ -84,7 +84,11 @@ int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap
   d.TX = (d.W + kTile - 1) / kTile;
   d.TY = (d.H + kTile - 1) / kTile;
   d.T = d.TX * d.TY;
-  if (d.T > kMaxTilesPerView) return fail_arg("image has more than 16384 tiles");
+  if (d.TX > kMaxTilesX) {
+    g_last_error = "images wider than 2048 pixels are not implemented";
+    return GS_ERR_UNSUPPORTED;
+  }
+  if (d.TY > 4096) return fail_arg("image taller than 65536 pixels");
   if ((int64_t)d.B * n > (int64_t)1 << 31) return fail_arg("n_frames * n_views * n too large");
   d.deg = s->sh_degree; d.K = K; d.C = C; d.L = s->n_levels; d.Rc = s->res_channels;
   for (int l = 0; l < kMaxLevels; ++l) {
@@ -96,7 +100,9 @@ int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap
   for (int c = 0; c < 3; ++c) d.bg[c] = s->bg[c];
   d.n_sort_chunks = (n + kSortChunk - 1) / kSortChunk;
   d.n_bin_chunks = (n + kBinChunk - 1) / kBinChunk;
+  d.n_row_segs = (n + kRowSeg - 1) / kRowSeg;
   d.capacity = (unsigned long long)cap;
+  d.row_capacity = d.capacity / 2;
   return GS_OK;
 }
 
@@ -128,7 +134,7 @@ hipEvent_t prof_event() {
 const char* kKernelNames[K_COUNT] = {
     "compose_fwd", "project_fwd", "radix_hist", "radix_scan", "radix_scatter", "bin_count", "bin_chunk_scan",
     "tile_ranges", "bin_emit", "raster_fwd", "zero", "raster_bwd", "project_bwd", "compose_bwd", "rate_ctx",
-    "rate_mlp", "rate_hist_minmax", "rate_hist_count", "rate_hist_bits", "adam", "bin_gather"};
+    "rate_mlp", "rate_hist_minmax", "rate_hist_count", "rate_hist_bits", "adam", "bin_gather", "row_count", "row_emit"};
 }  // namespace
 
 int prof_begin(int id, hipStream_t st) {
@@ -165,8 +171,11 @@ Layout make_layout(const RenderDims& d) {
   lo.keys1 = take(Bn * 4);
   lo.vals1 = take(Bn * 4);
   lo.sort_hist = take((size_t)d.B * 256 * d.n_sort_chunks * 4);
-  lo.bin_rec = take(Bn * 32);
-  lo.bin_hist = take((size_t)d.B * d.n_bin_chunks * d.T * 4);
+  lo.bin_rec = take(Bn * 48);
+  lo.bin_hist = take((size_t)d.B * d.n_bin_chunks * d.TY * 4);
+  lo.row_tot = take((size_t)d.B * d.TY * 4);
+  lo.row_ranges = take((size_t)d.B * d.TY * 8);
+  lo.tile_hist = take((size_t)d.B * d.TY * d.n_row_segs * d.TX * 4);
   lo.tile_tot = take((size_t)d.B * d.T * 4);
   lo.ranges = take((size_t)d.B * d.T * 8);
   lo.t_final = take((size_t)d.B * d.L * HW * 4);
@@ -174,10 +183,24 @@ Layout make_layout(const RenderDims& d) {
   lo.grad2d = take(Bn * kGradStride * 4);
   lo.composed = take((size_t)d.F * d.Rc * d.n * 4);
   lo.d_composed = take((size_t)d.F * d.Rc * d.n * 4);
-  // the pair list is last, so every other offset is independent of its capacity
+  // the pair lists are last, so every other offset is independent of their capacity
   lo.lists = take((size_t)d.capacity * 4);
+  lo.row_lists = take((size_t)d.row_capacity * 8);
   lo.total = off;
   return lo;
+}
+
+// The largest pair capacity whose layout fits in ws_bytes (4 bytes of tile list and 4 bytes of
+// row list, half as many 8-byte entries, per unit of capacity).
+void set_capacity(RenderDims& d, const Layout& lo0, size_t ws_bytes) {
+  unsigned long long cap = std::min<unsigned long long>((ws_bytes - lo0.total) / 8, 0xFFFFFFFFull);
+  for (;;) {
+    d.capacity = cap;
+    d.row_capacity = cap / 2;
+    const size_t tot = make_layout(d).total;
+    if (tot <= ws_bytes || cap == 0) break;
+    cap -= std::min<unsigned long long>(cap, (tot - ws_bytes + 7) / 8);
+  }
 }
 
 }  // namespace gs
@@ -236,7 +259,7 @@ int gs_render_forward(const gs_settings* s, int32_t n, const float* params, int3
     g_last_error = "workspace too small";
     return GS_ERR_WORKSPACE;
   }
-  d.capacity = std::min<unsigned long long>((ws_bytes - lo0.total) / 4, 0xFFFFFFFFull);
+  set_capacity(d, lo0, ws_bytes);
   const Layout lo = make_layout(d);
   if ((rc = check_device())) return rc;
   hipStream_t st = (hipStream_t)stream;
@@ -276,7 +299,7 @@ int gs_render_backward(const gs_settings* s, int32_t n, const float* params, int
     g_last_error = "workspace too small";
     return GS_ERR_WORKSPACE;
   }
-  d.capacity = std::min<unsigned long long>((ws_bytes - lo0.total) / 4, 0xFFFFFFFFull);
+  set_capacity(d, lo0, ws_bytes);
   const Layout lo = make_layout(d);
   if ((rc = check_device())) return rc;
   hipStream_t st = (hipStream_t)stream;

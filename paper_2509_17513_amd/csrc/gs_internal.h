@@ -13,7 +13,9 @@ constexpr int kTilePix = kTile * kTile;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortChunk = kSortThreads * kSortItems;  // keys per radix block
-constexpr int kBinChunk = 1024;      // depth-sorted Gaussians per binning wave
+constexpr int kBinChunk = 1024;      // depth-sorted Gaussians per row-binning wave
+constexpr int kRowSeg = 2048;        // row-list entries per tile-binning wave
+constexpr int kMaxTilesX = 128;      // tile columns one tile-binning wave covers (two per lane)
 constexpr int kMaxTilesPerView = 16384;
 constexpr int kMaxLevels = 8;
 constexpr int kGradStride = 16;      // floats per (view, Gaussian) gradient record (9 used, 64-byte aligned)
@@ -38,14 +40,15 @@ struct RenderDims {
   float lw[kMaxLevels];
   float near_plane, dilation, alpha_min, alpha_max, t_stop;
   float bg[3];
-  int n_sort_chunks, n_bin_chunks;
-  unsigned long long capacity;
+  int n_sort_chunks, n_bin_chunks, n_row_segs;
+  unsigned long long capacity;      // (tile, Gaussian) pairs
+  unsigned long long row_capacity;  // (tile row, Gaussian) pairs
 };
 
 // Byte offsets inside the workspace.
 struct Layout {
-  size_t status, records, rects, keys0, vals0, keys1, vals1, sort_hist, bin_rec, bin_hist, tile_tot, ranges, lists, t_final,
-      n_last, grad2d, composed, d_composed, total;
+  size_t status, records, rects, keys0, vals0, keys1, vals1, sort_hist, bin_rec, bin_hist, row_tot, row_ranges,
+      tile_hist, tile_tot, ranges, t_final, n_last, grad2d, composed, d_composed, lists, row_lists, total;
 };
 
 Layout make_layout(const RenderDims& d);

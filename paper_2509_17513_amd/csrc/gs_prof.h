@@ -27,6 +27,8 @@ enum KernelId {
   K_RATE_HIST_BITS,
   K_ADAM,
   K_BIN_GATHER,
+  K_ROW_COUNT,
+  K_ROW_EMIT,
   K_COUNT
 };
 

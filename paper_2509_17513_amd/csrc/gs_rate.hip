@@ -192,13 +192,19 @@ __device__ __forceinline__ bf16x8 load4x2(const uint16_t* p0, const uint16_t* p1
   return __builtin_bit_cast(bf16x8, make_uint4(a.x, a.y, b.x, b.y));
 }
 
+// tanh(u) = 1 - 2 / (1 + e^{2u}) with the hardware exp2 and reciprocal (absolute error ~1e-7,
+// far below the BF16 rounding that follows).
+__device__ __forceinline__ float tanh_fast(float u) {
+  const float e = __builtin_amdgcn_exp2f(u * 2.8853900817779268f);  // e^{2u}
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
+}
 __device__ __forceinline__ float gelu_f(float x) {
   const float c = 0.7978845608028654f;
-  return 0.5f * x * (1.f + tanhf(c * (x + 0.044715f * x * x * x)));
+  return 0.5f * x * (1.f + tanh_fast(c * (x + 0.044715f * x * x * x)));
 }
 __device__ __forceinline__ float gelu_grad_f(float x) {
   const float c = 0.7978845608028654f;
-  const float th = tanhf(c * (x + 0.044715f * x * x * x));
+  const float th = tanh_fast(c * (x + 0.044715f * x * x * x));
   return 0.5f * (1.f + th) + 0.5f * x * (1.f - th * th) * c * (1.f + 3.f * 0.044715f * x * x);
 }
 
@@ -295,63 +301,78 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
   f32x4 acc1[4], acc3[4];
   float db1 = 0.f, db2 = 0.f, db3 = 0.f;
   if constexpr (GRAD) {
+#pragma unroll
     for (int u = 0; u < 2; ++u)
+#pragma unroll
       for (int v = 0; v < 2; ++v)
+#pragma unroll
         for (int r = 0; r < 16; ++r) acc2[u][v][r] = 0.f;
+#pragma unroll
     for (int u = 0; u < 4; ++u)
+#pragma unroll
       for (int r = 0; r < 4; ++r) { acc1[u][r] = 0.f; acc3[u][r] = 0.f; }
   }
   RateWaveTmp& T = wt[wave];
+  const f32x16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
   for (int it = 0; it < iters; ++it) {
+    // Weights, biases and operand fragments are re-read from LDS every chunk rather than held in
+    // registers across the loop (holding all of them would exceed the register file).
+    asm volatile("" ::: "memory");
     const int chunk = (it * gridDim.x + blockIdx.x) * 4 + wave;
     const int sidx = chunk * 32 + sl;
     const bool valid = sidx < n;
     // ---- layer 1: Z1^T (64 x 32) = W1 (64 x 16) X^T (16 x 32)
-    bf16x8 bx;
-    if (valid) bx = load8(ctx + (size_t)sidx * kCtx + 8 * g);
-    else bx = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+    const bf16x8 bx = valid ? load8(ctx + (size_t)sidx * kCtx + 8 * g)
+                            : __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
     f32x16 c1[2];
-    for (int h = 0; h < 2; ++h) {
-      f32x16 z;
-      for (int r = 0; r < 16; ++r) z[r] = 0.f;
-      c1[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(&sh.w1[(32 * h + sl) * kCtx + 8 * g]), bx, z, 0, 0, 0);
-    }
-    float z1[32];
-    uint16_t h1b[32];
+#pragma unroll
     for (int h = 0; h < 2; ++h)
+      c1[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(&sh.w1[(32 * h + sl) * kCtx + 8 * g]), bx, zero16, 0, 0,
+                                                      0);
+    // bias + GELU + BF16, packed straight into the B operand of layer 2
+    uint32_t b2[4][4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b2[ks][j] = 0u;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int o = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float zz = c1[h][r] + sh.b1[o];
-        z1[16 * h + r] = zz;
-        h1b[16 * h + r] = f32_to_bf16(gelu_f(zz));
+        const uint16_t hb = f32_to_bf16(gelu_f(c1[h][r] + sh.b1[o]));
+        if constexpr (GRAD) T.h1[o * 32 + sl] = hb;
+        const int ks = 2 * h + (r >> 3), jj = r & 7;
+        b2[ks][jj >> 1] |= (uint32_t)hb << (16 * (jj & 1));
       }
     // ---- layer 2: Z2^T (64 x 32) = W2 (64 x 64) H1^T (64 x 32), K in 4 steps of 16
     f32x16 c2[2];
+#pragma unroll
     for (int h2 = 0; h2 < 2; ++h2) {
-      for (int r = 0; r < 16; ++r) c2[h2][r] = 0.f;
+      c2[h2] = zero16;
+#pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const uint16_t* row = &sh.w2[(32 * h2 + sl) * kHid + 16 * ks + 4 * g];
-        c2[h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load4x2(row, row + 8), pack8(&h1b[8 * ks]), c2[h2], 0, 0, 0);
+        c2[h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            load4x2(row, row + 8), __builtin_bit_cast(bf16x8, make_uint4(b2[ks][0], b2[ks][1], b2[ks][2], b2[ks][3])),
+            c2[h2], 0, 0, 0);
       }
     }
-    float z2[32], h2f[32];
-    uint16_t h2b[32];
+    // ---- bias + GELU; layer 3 (2 outputs) on the VALU, each lane holds half the hidden units
+    float o0 = 0.f, o1 = 0.f;
+#pragma unroll
     for (int h = 0; h < 2; ++h)
+#pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
         const float zz = c2[h][r] + sh.b2[o2];
-        z2[16 * h + r] = zz;
-        h2b[16 * h + r] = f32_to_bf16(gelu_f(zz));
-        h2f[16 * h + r] = bf16_to_f32(h2b[16 * h + r]);
-      }
-    // ---- layer 3 (2 outputs) on the VALU: each lane holds half of the hidden units of its symbol
-    float o0 = 0.f, o1 = 0.f;
-    for (int h = 0; h < 2; ++h)
-      for (int r = 0; r < 16; ++r) {
-        const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
-        o0 = fmaf(sh.w3[o2], h2f[16 * h + r], o0);
-        o1 = fmaf(sh.w3[kHid + o2], h2f[16 * h + r], o1);
+        c2[h][r] = zz;  // keep Z2 for the backward
+        const uint16_t hb = f32_to_bf16(gelu_f(zz));
+        if constexpr (GRAD) T.h2[o2 * 32 + sl] = hb;
+        const float hf = bf16_to_f32(hb);
+        o0 = fmaf(sh.w3[o2], hf, o0);
+        o1 = fmaf(sh.w3[kHid + o2], hf, o1);
       }
     o0 += __shfl_xor(o0, 32);
     o1 += __shfl_xor(o1, 32);
@@ -361,9 +382,10 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
     const float m = o0;
     const float sp = fmaxf(o1, 0.f) + log1pf(expf(-fabsf(o1)));
     const float bsc = sp + q * (1.f / 16.f);
-    float yh = 0.f, bits = 0.f, dby = 0.f, dbb = 0.f, wsym = 0.f;
+    float bits = 0.f, dby = 0.f, dbb = 0.f, wsym = 0.f;
     if (valid) {
       const float y = ya[sidx];
+      float yh;
       if (ra.mode == 0) {
         yh = rintf(y / q) * q;
       } else {
@@ -382,45 +404,58 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
         bits_acc += bits;
         loss_acc += wsym * bits;
         if (sym_bits) sym_bits[(size_t)a * n + sidx] = bits;
+        if (ra.mode == 1 && d_attrs) d_attrs[(size_t)a * n + sidx] += wsym * dby;
       }
-      if (ra.mode == 1 && d_attrs && g == 0) d_attrs[(size_t)a * n + sidx] += wsym * dby;
     }
     if constexpr (GRAD) {
       const float dout0 = valid ? -ra.wfit * dby : 0.f;
       const float sig1 = 1.f / (1.f + expf(-o1));
       const float dout1 = valid ? ra.wfit * dbb * sig1 : 0.f;
-      // dZ2 = (W3^T dout) * GELU'(Z2)
-      uint16_t d2b[32];
+      // dZ2 = (W3^T dout) * GELU'(Z2), packed into the B operand of dH1^T = W2^T dZ2^T
+      uint32_t bd[4][4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bd[ks][j] = 0u;
+#pragma unroll
       for (int h = 0; h < 2; ++h)
+#pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
           const float dh = dout0 * sh.w3[o2] + dout1 * sh.w3[kHid + o2];
-          d2b[16 * h + r] = f32_to_bf16(dh * gelu_grad_f(z2[16 * h + r]));
+          const uint16_t db = f32_to_bf16(dh * gelu_grad_f(c2[h][r]));
+          T.d2[o2 * 32 + sl] = db;
+          const int ks = 2 * h + (r >> 3), jj = r & 7;
+          bd[ks][jj >> 1] |= (uint32_t)db << (16 * (jj & 1));
         }
-      // dH1^T (64 x 32) = W2^T (64 x 64) dZ2^T (64 x 32)
       f32x16 c3[2];
+#pragma unroll
       for (int hi = 0; hi < 2; ++hi) {
-        for (int r = 0; r < 16; ++r) c3[hi][r] = 0.f;
+        c3[hi] = zero16;
+#pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const uint16_t* row = &sh.w2t[(32 * hi + sl) * kHid + 16 * ks + 4 * g];
-          c3[hi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load4x2(row, row + 8), pack8(&d2b[8 * ks]), c3[hi], 0, 0, 0);
+          c3[hi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              load4x2(row, row + 8),
+              __builtin_bit_cast(bf16x8, make_uint4(bd[ks][0], bd[ks][1], bd[ks][2], bd[ks][3])), c3[hi], 0, 0, 0);
         }
       }
-      uint16_t d1b[32];
+      // layer-1 pre-activations again (two MFMAs) for GELU'(Z1)
+#pragma unroll
       for (int h = 0; h < 2; ++h)
-        for (int r = 0; r < 16; ++r) d1b[16 * h + r] = f32_to_bf16(c3[h][r] * gelu_grad_f(z1[16 * h + r]));
-      // transposed staging (symbols contiguous) for the contractions over symbols
+        c1[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(&sh.w1[(32 * h + sl) * kCtx + 8 * g]), bx, zero16, 0,
+                                                        0, 0);
+#pragma unroll
       for (int h = 0; h < 2; ++h)
+#pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int u = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
-          T.h1[u * 32 + sl] = h1b[16 * h + r];
-          T.h2[u * 32 + sl] = h2b[16 * h + r];
-          T.d2[u * 32 + sl] = d2b[16 * h + r];
-          T.d1[u * 32 + sl] = d1b[16 * h + r];
+          T.d1[u * 32 + sl] = f32_to_bf16(c3[h][r] * gelu_grad_f(c1[h][r] + sh.b1[u]));
         }
       {
         const uint4 xv = __builtin_bit_cast(uint4, bx);
         const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
         for (int j = 0; j < 8; ++j) T.x[(8 * g + j) * 32 + sl] = (uint16_t)(xs[j >> 1] >> (16 * (j & 1)));
       }
       if (g == 0) {
@@ -429,32 +464,50 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
       }
       __syncthreads();
       // dW2 (64 x 64) += dZ2^T (64 x 32 symbols) H1 (32 x 64)
+#pragma unroll
       for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
         for (int h = 0; h < 2; ++h) {
           const bf16x8 av = load8(&T.d2[(32 * h + sl) * 32 + 16 * kk + 8 * g]);
+#pragma unroll
           for (int h2 = 0; h2 < 2; ++h2)
-            acc2[h][h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, load8(&T.h1[(32 * h2 + sl) * 32 + 16 * kk + 8 * g]),
-                                                                  acc2[h][h2], 0, 0, 0);
+            acc2[h][h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                av, load8(&T.h1[(32 * h2 + sl) * 32 + 16 * kk + 8 * g]), acc2[h][h2], 0, 0, 0);
         }
       // dW1 (64 x 16) += dZ1^T (64 x 32) X (32 x 16): v_mfma_f32_16x16x32_bf16, lane l holds row/col (l & 15)
       const int r16 = lane & 15, g16 = lane >> 4;
       const bf16x8 bxT = load8(&T.x[r16 * 32 + 8 * g16]);
+#pragma unroll
       for (int mt = 0; mt < 4; ++mt)
-        acc1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(&T.d1[(16 * mt + r16) * 32 + 8 * g16]), bxT, acc1[mt],
-                                                            0, 0, 0);
+        acc1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(&T.d1[(16 * mt + r16) * 32 + 8 * g16]), bxT,
+                                                            acc1[mt], 0, 0, 0);
       // dW3 (2 x 64) += dout^T (2 x 32) H2 (32 x 64), rows padded to 16
-      uint16_t dv[8];
-      for (int j = 0; j < 8; ++j) dv[j] = r16 < 2 ? f32_to_bf16(T.dout[r16 * 32 + 8 * g16 + j]) : (uint16_t)0;
-      const bf16x8 ad = pack8(dv);
+      uint32_t dv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float lo = r16 < 2 ? T.dout[r16 * 32 + 8 * g16 + 2 * j] : 0.f;
+        const float hi = r16 < 2 ? T.dout[r16 * 32 + 8 * g16 + 2 * j + 1] : 0.f;
+        dv[j] = (uint32_t)f32_to_bf16(lo) | ((uint32_t)f32_to_bf16(hi) << 16);
+      }
+      const bf16x8 ad = __builtin_bit_cast(bf16x8, make_uint4(dv[0], dv[1], dv[2], dv[3]));
+#pragma unroll
       for (int nt = 0; nt < 4; ++nt)
         acc3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, load8(&T.h2[(16 * nt + r16) * 32 + 8 * g16]), acc3[nt],
                                                             0, 0, 0);
       // bias gradients: row sums over the 32 symbols
       {
         float s1 = 0.f, s2 = 0.f;
-        for (int j = 0; j < 32; ++j) {
-          s1 += bf16_to_f32(T.d1[lane * 32 + j]);
-          s2 += bf16_to_f32(T.d2[lane * 32 + j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint4 v1 = *(const uint4*)&T.d1[lane * 32 + 8 * j];
+          const uint4 v2 = *(const uint4*)&T.d2[lane * 32 + 8 * j];
+          const uint32_t w1s[4] = {v1.x, v1.y, v1.z, v1.w};
+          const uint32_t w2s[4] = {v2.x, v2.y, v2.z, v2.w};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            s1 += __uint_as_float(w1s[k] << 16) + __uint_as_float(w1s[k] & 0xFFFF0000u);
+            s2 += __uint_as_float(w2s[k] << 16) + __uint_as_float(w2s[k] & 0xFFFF0000u);
+          }
         }
         db1 += s1;
         db2 += s2;
@@ -468,6 +521,7 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
     }
   }
   // ---- block reductions
+#pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     bits_acc += __shfl_xor(bits_acc, off);
     loss_acc += __shfl_xor(loss_acc, off);
@@ -489,8 +543,11 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
     float* acc = (float*)wt;
     for (int j = tid; j < kWPerAttr + kBPerAttr; j += 256) acc[j] = 0.f;
     __syncthreads();
+#pragma unroll
     for (int h = 0; h < 2; ++h)
+#pragma unroll
       for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
           const int i = 32 * h2 + sl;
@@ -498,9 +555,13 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
         }
     {
       const int r16 = lane & 15, g16 = lane >> 4;
+#pragma unroll
       for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
         for (int r = 0; r < 4; ++r) atomicAdd(&acc[(16 * mt + 4 * g16 + r) * kCtx + r16], acc1[mt][r]);
+#pragma unroll
       for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 4 * g16 + r;
           if (row < 2) atomicAdd(&acc[kW1 + kW2 + row * kHid + 16 * nt + r16], acc3[nt][r]);

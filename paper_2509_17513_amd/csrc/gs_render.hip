@@ -707,41 +707,66 @@ __global__ __launch_bounds__(256) void k_bin_gather(RenderDims d, const uint32_t
   const int b = blockIdx.y;
   if (k >= d.n) return;
   const size_t seg = (size_t)b * d.n;
-  float4 o0 = make_float4(0.f, 0.f, 1.f, 0.f), o1 = make_float4(1.f, -1.f, 0.f, 0.f);
+  float4 o0 = make_float4(0.f, 0.f, 1.f, 0.f), o1 = make_float4(1.f, 1.f, 0.f, 0.f);
+  float4 o2 = make_float4(-1.f, 0.f, 0.f, 0.f);
   if (skeys[seg + k] != 0xFFFFFFFFu) {
     const uint32_t i = svals[seg + k];
     const float4 r0 = rec[3 * (seg + i)], r1 = rec[3 * (seg + i) + 1];
     const uint2 rc = rects[seg + i];
     // quadratic-form threshold of alpha >= alpha_min, with a relative margin of 1e-3
     const float tau = 2.f * (logf(r1.y) - logf(d.alpha_min)) * 1.001f + 1e-3f;
+    const float A = r0.z, B = r0.w, C = r1.x;
+    const float det = A * C - B * B;
+    const float dxm = sqrtf(fmaxf(tau * C / det, 0.f));  // half-width of the ellipse
     o0 = r0;
-    o1 = make_float4(r1.x, tau, __uint_as_float(rc.x), __uint_as_float(rc.y));
+    o1 = make_float4(det, 1.f / A, -B * dxm / C, sqrtf(fmaxf(A * tau / det, 0.f)));
+    o2 = make_float4(tau, 0.f, __uint_as_float(rc.x), __uint_as_float(rc.y));
   }
-  brec[2 * (seg + k)] = o0;
-  brec[2 * (seg + k) + 1] = o1;
+  brec[3 * (seg + k)] = o0;
+  brec[3 * (seg + k) + 1] = o1;
+  brec[3 * (seg + k) + 2] = o2;
 }
 
-// Each wave walks kBinChunk depth-sorted Gaussians of one frame-view in order;
-// its 64 lanes cover the tiles of one Gaussian at a time, so the per-tile
-// counters in LDS see the Gaussians in depth order (a stable counting sort).
-// A tile of the bounding rectangle is kept only if the ellipse
-// q(p) = (p - m)^T [[A, B], [B, C]] (p - m) <= tau reaches one of its pixel
-// centres: per tile row, the exact x-extent of the ellipse over the row's band
-// of pixel-centre heights is compared with the tile's pixel-centre columns.
-// The extent's right end is a concave function of the height with its maximum
-// at the ellipse's rightmost point, so it is evaluated at that height clamped
-// to the band (and symmetrically for the left end).
+// Tile columns of tile row ty whose pixel centres the ellipse
+// q(p) = (p - m)^T [[A, B], [B, C]] (p - m) <= tau reaches, intersected with
+// [x0, x1]; false if none. The ellipse's exact x-extent over the row's band of
+// pixel-centre heights is used: its right end is a concave function of the
+// height with the maximum at the ellipse's rightmost point, so it is evaluated
+// at that height clamped to the band (and symmetrically for the left end).
+struct EllipseRows {
+  float mx, my, A, B, det, iA, tau, dyr, dym;  // dyr: height of the rightmost point; dym: half-height
+  __device__ __forceinline__ bool row(const RenderDims& d, int ty, int x0, int x1, int& txl, int& txh) const {
+    const float Y0 = (float)(ty * kTile) + 0.5f - my;
+    const float Y1 = (float)(min(ty * kTile + kTile, d.H) - 1) + 0.5f - my;
+    const float lo = fmaxf(Y0, -dym), hi = fminf(Y1, dym);
+    if (!(lo <= hi)) return false;
+    const float dr = fminf(fmaxf(dyr, lo), hi), dl = fminf(fmaxf(-dyr, lo), hi);
+    const float xr = mx + (-B * dr + sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
+    const float xl = mx + (-B * dl - sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
+    // tile tx has pixel centres 16 tx + 0.5 .. 16 tx + 15.5 (clipped to the image)
+    const float fl = fminf(fmaxf(ceilf((xl - 15.5f) * (1.f / kTile)), -1.f), (float)d.TX);
+    const float fh = fminf(fmaxf(floorf((xr - 0.5f) * (1.f / kTile)), -1.f), (float)d.TX);
+    txl = max(x0, (int)fl);
+    txh = min(x1, (int)fh);
+    return txl <= txh;
+  }
+};
+
+// Level 1: rows. Each wave walks kBinChunk depth-sorted Gaussians of one
+// frame-view in order; its lanes cover one Gaussian's tile rows at a time, so
+// the per-row counters in LDS see the Gaussians in depth order (a stable
+// counting sort). An entry is (Gaussian index, tile-column range in the row).
 template <bool EMIT>
-__global__ __launch_bounds__(64) void k_bin(RenderDims d, const uint32_t* __restrict__ skeys,
-                                            const uint32_t* __restrict__ svals, const float4* __restrict__ brec,
-                                            uint32_t* __restrict__ bhist, const uint2* __restrict__ ranges,
-                                            uint32_t* __restrict__ lists) {
+__global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __restrict__ skeys,
+                                                const uint32_t* __restrict__ svals, const float4* __restrict__ brec,
+                                                uint32_t* __restrict__ hist, const uint2* __restrict__ row_ranges,
+                                                uint2* __restrict__ row_lists) {
   extern __shared__ uint32_t cnt[];
   const int lane = threadIdx.x;
   const int b = blockIdx.y, chunk = blockIdx.x;
-  const int T = d.T;
-  uint32_t* bh = bhist + ((size_t)b * d.n_bin_chunks + chunk) * T;
-  for (int t = lane; t < T; t += 64) cnt[t] = EMIT ? ranges[(size_t)b * T + t].x + bh[t] : 0u;
+  const int TY = d.TY;
+  uint32_t* bh = hist + ((size_t)b * d.n_bin_chunks + chunk) * TY;
+  for (int t = lane; t < TY; t += 64) cnt[t] = EMIT ? row_ranges[(size_t)b * TY + t].x + bh[t] : 0u;
   __syncthreads();
   const size_t seg = (size_t)b * d.n;
   const int start = chunk * kBinChunk;
@@ -749,14 +774,16 @@ __global__ __launch_bounds__(64) void k_bin(RenderDims d, const uint32_t* __rest
   for (int base = start; base < end; base += 64) {
     const int e = base + lane;
     uint32_t idx = 0;
-    float4 q0 = make_float4(0.f, 0.f, 1.f, 0.f), q1 = make_float4(1.f, -1.f, 0.f, 0.f);
+    float4 q0 = make_float4(0.f, 0.f, 1.f, 0.f), q1 = make_float4(1.f, 1.f, 0.f, 0.f);
+    float4 q2 = make_float4(-1.f, 0.f, 0.f, 0.f);
     bool ok = false;
     if (e < end) {
       ok = skeys[seg + e] != 0xFFFFFFFFu;
       if (ok) {
         idx = svals[seg + e];
-        q0 = brec[2 * (seg + e)];
-        q1 = brec[2 * (seg + e) + 1];
+        q0 = brec[3 * (seg + e)];
+        q1 = brec[3 * (seg + e) + 1];
+        q2 = brec[3 * (seg + e) + 2];
       }
     }
     const unsigned long long live = __ballot(ok);
@@ -764,82 +791,164 @@ __global__ __launch_bounds__(64) void k_bin(RenderDims d, const uint32_t* __rest
     const int nlive = 64 - __clzll(live);  // keys are sorted, so live lanes are a prefix
     for (int j = 0; j < nlive; ++j) {
       const uint32_t gi = __builtin_amdgcn_readlane(idx, j);
-      const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.x), j));
-      const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.y), j));
-      const float A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.z), j));
-      const float B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.w), j));
-      const float C = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.x), j));
-      const float tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.y), j));
-      const uint32_t rx = __builtin_amdgcn_readlane(__float_as_uint(q1.z), j);
-      const uint32_t ry = __builtin_amdgcn_readlane(__float_as_uint(q1.w), j);
+      EllipseRows el;
+      el.mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.x), j));
+      el.my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.y), j));
+      el.A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.z), j));
+      el.B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.w), j));
+      el.det = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.x), j));
+      el.iA = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.y), j));
+      el.dyr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.z), j));
+      el.dym = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.w), j));
+      el.tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.x), j));
+      const uint32_t rx = __builtin_amdgcn_readlane(__float_as_uint(q2.z), j);
+      const uint32_t ry = __builtin_amdgcn_readlane(__float_as_uint(q2.w), j);
       const int x0 = rx & 0xFFFF, x1 = rx >> 16, y0 = ry & 0xFFFF, y1 = ry >> 16;
-      const int w = x1 - x0 + 1, h = y1 - y0 + 1;
-      const int total = w * h;
-      // per-Gaussian constants of the extent computation
-      const float det = A * C - B * B;
-      const float iA = 1.f / A;
-      const float dxm = sqrtf(fmaxf(tau * C / det, 0.f));  // half-width of the ellipse
-      const float dyr = -B * dxm / C;                      // height offset of its rightmost point
-      const float dym = sqrtf(fmaxf(A * tau / det, 0.f));  // half-height
-      const float iw = 1.f / (float)w;
-      for (int l = lane; l < total; l += 64) {
-        int ly = (int)((float)l * iw);
-        int lx = l - ly * w;
-        if (lx < 0) { --ly; lx += w; } else if (lx >= w) { ++ly; lx -= w; }
-        const int tx = x0 + lx, ty = y0 + ly;
-        const float Y0 = (float)(ty * kTile) + 0.5f - my;
-        const float Y1 = (float)(min(ty * kTile + kTile, d.H) - 1) + 0.5f - my;
-        const float lo = fmaxf(Y0, -dym), hi = fminf(Y1, dym);
-        if (!(lo <= hi)) continue;
-        const float dr = fminf(fmaxf(dyr, lo), hi), dl = fminf(fmaxf(-dyr, lo), hi);
-        const float xr = (-B * dr + sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
-        const float xl = (-B * dl - sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
-        const float X0 = (float)(tx * kTile) + 0.5f - mx;
-        const float X1 = (float)(min(tx * kTile + kTile, d.W) - 1) + 0.5f - mx;
-        if (X0 > xr || X1 < xl) continue;
-        const int tile = ty * d.TX + tx;
+      for (int ty = y0 + lane; ty <= y1; ty += 64) {
+        int txl, txh;
+        if (!el.row(d, ty, x0, x1, txl, txh)) continue;
         if (EMIT) {
-          const uint32_t pos = cnt[tile];
-          if (pos < d.capacity) lists[pos] = gi;
-          cnt[tile] = pos + 1;
+          const uint32_t pos = cnt[ty];
+          if (pos < d.row_capacity) row_lists[pos] = make_uint2(gi, (uint32_t)txl | ((uint32_t)txh << 16));
+          cnt[ty] = pos + 1;
         } else {
-          cnt[tile] += 1u;
+          cnt[ty] += 1u;
         }
       }
     }
   }
   __syncthreads();
   if (!EMIT)
-    for (int t = lane; t < T; t += 64) bh[t] = cnt[t];
+    for (int t = lane; t < TY; t += 64) bh[t] = cnt[t];
 }
 
-// Per (frame-view, tile): exclusive prefix over chunks, total count.
-__global__ __launch_bounds__(256) void k_bin_chunk_scan(RenderDims d, uint32_t* __restrict__ bhist,
-                                                        uint32_t* __restrict__ tot) {
+// Level 2: tiles of one row. One wave takes a segment of kRowSeg entries of a
+// (frame-view, row) list; lane l owns tile columns l and l + 64 and appends, in
+// list (= depth) order, every entry whose column range covers them, so each
+// lane writes its own tile list sequentially.
+template <bool EMIT>
+__global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __restrict__ st,
+                                                 const uint2* __restrict__ row_ranges,
+                                                 const uint2* __restrict__ row_lists, uint32_t* __restrict__ hist,
+                                                 const uint2* __restrict__ ranges, uint32_t* __restrict__ lists) {
+  // emit: each lane gathers up to kWc entries of each of its two tiles in LDS and writes them
+  // out as one contiguous run that ends on a kWc-entry boundary of the list
+  constexpr int kWc = 16;
+  __shared__ __align__(16) uint32_t wbuf[2][64][kWc];
+  if (st->overflow & 2u) return;
+  const int lane = threadIdx.x;
+  const int s = blockIdx.x, ty = blockIdx.y, b = blockIdx.z;
+  const uint2 rr = row_ranges[(size_t)b * d.TY + ty];
+  const uint32_t start = rr.x + (uint32_t)s * kRowSeg;
+  if (start >= rr.y) return;
+  const uint32_t end = min(start + (uint32_t)kRowSeg, rr.y);
+  const int tx0 = lane, tx1 = lane + 64;
+  uint32_t* hb = hist + (((size_t)b * d.TY + ty) * d.n_row_segs + s) * d.TX;
+  uint32_t c0 = 0, c1 = 0;   // next list position (emit) or count
+  uint32_t n0 = 0, n1 = 0;   // buffered entries (emit)
+  if (EMIT) {
+    if (tx0 < d.TX) c0 = ranges[(size_t)b * d.T + ty * d.TX + tx0].x + hb[tx0];
+    if (tx1 < d.TX) c1 = ranges[(size_t)b * d.T + ty * d.TX + tx1].x + hb[tx1];
+  }
+  auto flush = [&](int q, uint32_t& c, uint32_t& nb) {
+    if (nb == kWc && c + kWc <= d.capacity) {  // a whole aligned run: four 16-byte stores
+      const uint4* src = (const uint4*)wbuf[q][lane];
+      uint4* dst = (uint4*)(lists + c);
+#pragma unroll
+      for (int v = 0; v < kWc / 4; ++v) dst[v] = src[v];
+    } else {
+      for (uint32_t k = 0; k < nb; ++k)
+        if (c + k < d.capacity) lists[c + k] = wbuf[q][lane][k];
+    }
+    c += nb;
+    nb = 0;
+  };
+  for (uint32_t base = start; base < end; base += 64) {
+    const uint32_t e = base + lane;
+    const uint2 ent = e < end ? row_lists[e] : make_uint2(0u, 1u);
+    const int nin = (int)min(64u, end - base);
+    for (int j = 0; j < nin; ++j) {
+      const uint32_t gi = __builtin_amdgcn_readlane(ent.x, j);
+      const uint32_t rg = __builtin_amdgcn_readlane(ent.y, j);
+      const int txl = (int)(rg & 0xFFFF), txh = (int)(rg >> 16);
+      if (tx0 >= txl && tx0 <= txh) {
+        if (EMIT) {
+          wbuf[0][lane][n0++] = gi;
+          if (((c0 + n0) & (kWc - 1)) == 0) flush(0, c0, n0);
+        } else {
+          ++c0;
+        }
+      }
+      if (tx1 >= txl && tx1 <= txh) {
+        if (EMIT) {
+          wbuf[1][lane][n1++] = gi;
+          if (((c1 + n1) & (kWc - 1)) == 0) flush(1, c1, n1);
+        } else {
+          ++c1;
+        }
+      }
+    }
+  }
+  if (EMIT) {
+    flush(0, c0, n0);
+    flush(1, c1, n1);
+  } else {
+    if (tx0 < d.TX) hb[tx0] = c0;
+    if (tx1 < d.TX) hb[tx1] = c1;
+  }
+}
+
+// Per (frame-view, bin): exclusive prefix over the chunks of level 1 (bins = rows).
+__global__ __launch_bounds__(256) void k_chunk_scan(int nbins_total, int nbins, int nchunks,
+                                                    uint32_t* __restrict__ hist, uint32_t* __restrict__ tot) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= d.B * d.T) return;
-  const int b = g / d.T, t = g - b * d.T;
+  if (g >= nbins_total) return;
+  const int b = g / nbins, t = g - b * nbins;
   uint32_t run = 0;
-  for (int c = 0; c < d.n_bin_chunks; ++c) {
-    const size_t o = ((size_t)b * d.n_bin_chunks + c) * d.T + t;
-    const uint32_t v = bhist[o];
-    bhist[o] = run;
+  for (int c = 0; c < nchunks; ++c) {
+    const size_t o = ((size_t)b * nchunks + c) * nbins + t;
+    const uint32_t v = hist[o];
+    hist[o] = run;
     run += v;
   }
   tot[g] = run;
 }
 
-// Exclusive scan over all (frame-view, tile) totals -> list ranges; flags overflow.
-__global__ __launch_bounds__(1024) void k_tile_ranges(RenderDims d, const uint32_t* __restrict__ tot,
-                                                      uint2* __restrict__ ranges, Status* __restrict__ st) {
+// Per (frame-view, tile): exclusive prefix over the level-2 segments of its row.
+__global__ __launch_bounds__(256) void k_seg_scan(RenderDims d, const Status* __restrict__ st,
+                                                  const uint2* __restrict__ row_ranges, uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ tot) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.B * d.T) return;
+  const int b = g / d.T, tile = g - b * d.T;
+  const int ty = tile / d.TX, tx = tile - ty * d.TX;
+  uint32_t run = 0;
+  if (!(st->overflow & 2u)) {
+    const uint2 rr = row_ranges[(size_t)b * d.TY + ty];
+    const int nseg = (int)((rr.y - rr.x + kRowSeg - 1) / kRowSeg);
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+      const size_t o = (((size_t)b * d.TY + ty) * d.n_row_segs + sgi) * d.TX + tx;
+      const uint32_t v = hist[o];
+      hist[o] = run;
+      run += v;
+    }
+  }
+  tot[g] = run;
+}
+
+// Exclusive scan of `count` totals into [start, end) ranges. level 0 (rows):
+// flags overflow bit 2 if the row pairs exceed their capacity; level 1 (tiles):
+// flags bit 1 for the tile pairs and records the pairs needed.
+__global__ __launch_bounds__(1024) void k_scan_ranges(int count, int level, unsigned long long cap,
+                                                      const uint32_t* __restrict__ tot, uint2* __restrict__ ranges,
+                                                      Status* __restrict__ st) {
   __shared__ unsigned long long part[1024];
   const int t = threadIdx.x;
-  const int total = d.B * d.T;
-  const int per = (total + 1023) / 1024;
-  const int lo = t * per, hi = min(lo + per, total);
-  unsigned long long s = 0;
-  for (int j = lo; j < hi; ++j) s += tot[j];
-  part[t] = s;
+  const int per = (count + 1023) / 1024;
+  const int lo = t * per, hi = min(lo + per, count);
+  unsigned long long sum = 0;
+  for (int j = lo; j < hi; ++j) sum += tot[j];
+  part[t] = sum;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
     unsigned long long v = t >= off ? part[t - off] : 0ull;
@@ -847,7 +956,7 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(RenderDims d, const uint32
     part[t] += v;
     __syncthreads();
   }
-  unsigned long long run = part[t] - s;
+  unsigned long long run = part[t] - sum;
   for (int j = lo; j < hi; ++j) {
     const uint32_t v = tot[j];
     const unsigned long long e = run + v;
@@ -855,10 +964,16 @@ __global__ __launch_bounds__(1024) void k_tile_ranges(RenderDims d, const uint32
     run = e;
   }
   if (t == 1023) {
-    st->needed_pairs = part[1023];
-    st->overflow = part[1023] > d.capacity ? 1u : 0u;
-    st->fwd_evals = 0;
-    st->fwd_contribs = 0;
+    const unsigned long long total = part[1023];
+    if (level == 0) {
+      st->overflow = total > cap ? 2u : 0u;
+      st->needed_pairs = 2ull * total;  // a lower bound of the tile pairs while the rows overflow
+      st->fwd_evals = 0;
+      st->fwd_contribs = 0;
+    } else if (!(st->overflow & 2u)) {
+      st->overflow = total > cap ? 1u : 0u;
+      st->needed_pairs = max(total, st->needed_pairs);
+    }
   }
 }
 
@@ -1333,32 +1448,50 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   const uint2* rects = (const uint2*)(ws + lo.rects);
   const float4* rec = (const float4*)(ws + lo.records);
   float4* brec = (float4*)(ws + lo.bin_rec);
-  uint32_t* bhist = (uint32_t*)(ws + lo.bin_hist);
+  uint32_t* rhist = (uint32_t*)(ws + lo.bin_hist);
+  uint32_t* rtot = (uint32_t*)(ws + lo.row_tot);
+  uint2* rranges = (uint2*)(ws + lo.row_ranges);
+  uint2* rlists = (uint2*)(ws + lo.row_lists);
+  uint32_t* thist = (uint32_t*)(ws + lo.tile_hist);
   uint2* ranges = (uint2*)(ws + lo.ranges);
   uint32_t* lists = (uint32_t*)(ws + lo.lists);
   uint32_t* tot = (uint32_t*)(ws + lo.tile_tot);
   Status* status = (Status*)(ws + lo.status);
-  dim3 grid(d.n_bin_chunks, d.B);
-  const size_t lds = (size_t)d.T * sizeof(uint32_t);
+  dim3 grid1(d.n_bin_chunks, d.B);
+  const size_t lds1 = (size_t)d.TY * sizeof(uint32_t);
+  dim3 grid2(d.n_row_segs, d.TY, d.B);
   if (d.n_bin_chunks > 0) {
-    ProfScope ps_(K_BIN_GATHER, st);
-    hipLaunchKernelGGL(k_bin_gather, dim3((d.n + 255) / 256, d.B), dim3(256), 0, st, d, skeys, svals, rects, rec, brec);
-  }
-  if (d.n_bin_chunks > 0) {
-    ProfScope ps_(K_BIN_COUNT, st);
-    hipLaunchKernelGGL(k_bin<false>, grid, dim3(64), lds, st, d, skeys, svals, brec, bhist, ranges, lists);
+    {
+      ProfScope ps_(K_BIN_GATHER, st);
+      hipLaunchKernelGGL(k_bin_gather, dim3((d.n + 255) / 256, d.B), dim3(256), 0, st, d, skeys, svals, rects, rec,
+                         brec);
+    }
+    ProfScope ps_(K_ROW_COUNT, st);
+    hipLaunchKernelGGL(k_row_bin<false>, grid1, dim3(64), lds1, st, d, skeys, svals, brec, rhist, rranges, rlists);
   }
   {
     ProfScope ps_(K_BIN_CHUNK_SCAN, st);
-    hipLaunchKernelGGL(k_bin_chunk_scan, dim3((d.B * d.T + 255) / 256), dim3(256), 0, st, d, bhist, tot);
+    hipLaunchKernelGGL(k_chunk_scan, dim3((d.B * d.TY + 255) / 256), dim3(256), 0, st, d.B * d.TY, d.TY,
+                       d.n_bin_chunks, rhist, rtot);
+    hipLaunchKernelGGL(k_scan_ranges, dim3(1), dim3(1024), 0, st, d.B * d.TY, 0, d.row_capacity, rtot, rranges,
+                       status);
+  }
+  if (d.n_bin_chunks > 0) {
+    ProfScope ps_(K_ROW_EMIT, st);
+    hipLaunchKernelGGL(k_row_bin<true>, grid1, dim3(64), lds1, st, d, skeys, svals, brec, rhist, rranges, rlists);
+  }
+  if (d.n_row_segs > 0) {
+    ProfScope ps_(K_BIN_COUNT, st);
+    hipLaunchKernelGGL(k_tile_bin<false>, grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges, lists);
   }
   {
     ProfScope ps_(K_TILE_RANGES, st);
-    hipLaunchKernelGGL(k_tile_ranges, dim3(1), dim3(1024), 0, st, d, tot, ranges, status);
+    hipLaunchKernelGGL(k_seg_scan, dim3((d.B * d.T + 255) / 256), dim3(256), 0, st, d, status, rranges, thist, tot);
+    hipLaunchKernelGGL(k_scan_ranges, dim3(1), dim3(1024), 0, st, d.B * d.T, 1, d.capacity, tot, ranges, status);
   }
-  if (d.n_bin_chunks > 0) {
+  if (d.n_row_segs > 0) {
     ProfScope ps_(K_BIN_EMIT, st);
-    hipLaunchKernelGGL(k_bin<true>, grid, dim3(64), lds, st, d, skeys, svals, brec, bhist, ranges, lists);
+    hipLaunchKernelGGL(k_tile_bin<true>, grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges, lists);
   }
   return hipGetLastError();
 }

@@ -42,10 +42,10 @@ def test_workspace_size_and_validation(L):
     s = _settings(1000)
     assert L.gs_workspace_size(ctypes.byref(s), 1000, 1, 2, 10000, ctypes.byref(sz)) == 0
     assert sz.value > 10000 * 4
-    # bigger capacity -> exactly 4 bytes per pair more (after 256-byte alignment)
+    # bigger capacity -> 8 bytes per pair more (tile list 4 B + row list 4 B, after 256-byte alignment)
     sz2 = ctypes.c_size_t()
     assert L.gs_workspace_size(ctypes.byref(s), 1000, 1, 2, 10000 + 64 * 10, ctypes.byref(sz2)) == 0
-    assert sz2.value - sz.value == 2560
+    assert sz2.value - sz.value == 5120
     bad = [
         (_settings(1000), -1, 1, 1, 10),
         (_settings(1000), 1000, 0, 1, 10),
@@ -91,6 +91,6 @@ def test_workspace_layout_regions_are_disjoint(L):
     assert L.gs_workspace_describe(ctypes.byref(s), 5000, 2, 3, 123456, ctypes.byref(lo)) == 0
     offs = [lo.status, lo.records, lo.rects, lo.keys, lo.vals, lo.ranges, lo.t_final, lo.n_last, lo.grad2d,
             lo.lists]
+    assert lo.lists + 4 * 123456 + 8 * (123456 // 2) <= lo.total
     assert offs == sorted(offs) and len(set(offs)) == len(offs)
-    assert lo.lists + 4 * 123456 <= lo.total
     assert lo.tiles_x == 13 and lo.tiles_y == 8

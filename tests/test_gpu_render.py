@@ -130,10 +130,15 @@ def test_overflow_reports_needed_pairs_and_retry_matches():
     ok, needed = ws.status()
     assert not ok and needed > 100
     assert torch.all(img0 == -7.0)  # an overflowing forward leaves the image untouched
-    ws.allocate(needed)
-    img1, _ = render_forward(st, p, c, 1, None, ws, check_overflow=False)
-    ok, needed2 = ws.status()
-    assert ok and needed2 == needed
+    for _ in range(3):  # the row lists may overflow first; their needed count is a lower bound
+        ws.allocate(needed)
+        img1, _ = render_forward(st, p, c, 1, None, ws, check_overflow=False)
+        ok, needed2 = ws.status()
+        if ok:
+            break
+        assert needed2 > needed
+        needed = needed2
+    assert ok
     img2, _, _ = _gpu_forward(w)
     assert torch.equal(img1, img2)
 
