@@ -168,6 +168,74 @@ def bench_rate(torch, dev, L, steps, n=1_000_000):
             "kernels_ms": times}
 
 
+def bench_group(torch, dev, steps):
+    """4D group: 150k keyframe Gaussians + 10 residual frames x 8 ring views at 960x540, the 80
+    forward + fused-L1 backward renders in one call, replayed from a captured graph."""
+    import synth
+    from paper_2509_17513_amd import RenderSettings, Workspace, render_backward, render_forward
+    w = synth.config_group()
+    st = RenderSettings(w.width, w.height, w.sh_degree, tuple(w.level_counts), tuple(w.level_weights),
+                        res_channels=w.residuals.shape[1])
+    p, c, r, tgt = (torch.from_numpy(a).to(dev) for a in (w.params, w.cams, w.residuals, w.target))
+    B = w.cams.shape[0]
+    img, ws = render_forward(st, p, c, w.n_frames, r, ws=Workspace(st, w.n, w.n_frames, B // w.n_frames, dev,
+                                                                    pair_capacity=30 * w.n * B))
+    dp, dr = torch.zeros_like(p), torch.zeros_like(r)
+
+    def step():
+        render_forward(st, p, c, w.n_frames, r, ws=ws, image=img, check_overflow=False)
+        render_backward(st, p, c, ws, w.n_frames, r, image=img, target=tgt, d_params=dp, d_residuals=dr)
+
+    step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(g):
+        step()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"workload": w.name, "renders": B, "ms_per_step": ms, "ms_per_render": ms / B,
+            "pairs": ws.status()[1]}
+
+
+def bench_train(torch, dev, steps, n=1_000_000, views=8):
+    """Joint keyframe training step at the rate-model scale: 1M Gaussians, 8 ring views at 960x540,
+    six nested layers: render forward + fused L1 backward + learned rate (train mode) + Adam."""
+    import synth
+    from paper_2509_17513_amd import RenderSettings, render_forward
+    from paper_2509_17513_amd.train import JointTrainer, RateModel
+    idx = list(range(0, 24, 24 // views))
+    cams = torch.from_numpy(synth.ring_cameras(idx, 24, 4.0, 960, 540)).to(dev)
+    teacher = torch.from_numpy(synth.cube_scene(n, 15, 3)).to(dev)
+    timg, _ = render_forward(RenderSettings(960, 540, 3, (n,), (1.0,)), teacher, cams)
+    targets = timg[0, :, 0].contiguous()
+    del teacher, timg
+    p_host = synth.cube_scene(n, 5, 3)
+    p = torch.from_numpy(p_host).to(dev)
+    lv = synth.nested_levels(n)
+    st = RenderSettings(960, 540, 3, tuple(lv), tuple(synth.paper_level_weights(6)))
+    tr = JointTrainer(p, cams, targets, st, RateModel(56, dev, seed=5, attrs_host=p_host[3:59]),
+                      lambda_rate=1e-3, extent=1.0, seed=5)
+    tr.step(check_overflow=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"workload": f"train_{n}_{views}v_960x540_L6_rate56", "ms_per_step": ms, "ms_per_view": ms / views,
+            "l1": float(tr.loss.item())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +247,7 @@ def main():
     ap.add_argument("--n", type=int, default=300_000)
     ap.add_argument("--views", type=int, default=24)
     ap.add_argument("--no-rate", action="store_true", help="skip the learned-rate measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the group and training-step measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -369,6 +438,13 @@ def main():
 
     if not args.no_rate:
         out["rate"] = bench_rate(torch, dev, L, args.steps)
+    if not args.no_extra:
+        log("[bench] 4D group and joint training step")
+        del ws, img
+        torch.cuda.empty_cache()
+        out["group"] = bench_group(torch, dev, args.steps)
+        torch.cuda.empty_cache()
+        out["train"] = bench_train(torch, dev, args.steps)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
