@@ -108,20 +108,23 @@ __device__ __forceinline__ float cam_y(const gs_camera& c, float x, float y, flo
 }
 
 // Per-pixel Gaussian weight. Forward and backward call this one function on
-// the same inputs, so they take identical float32 decisions.
+// the same inputs, so they take identical float32 decisions. The conic comes
+// pre-scaled to a base-2 exponent: (a2, b2, c2) = -log2(e) (A / 2, B, C / 2), so
+// that G = 2^(a2 dx^2 + b2 dx dy + c2 dy^2) = exp(-q / 2).
 struct AlphaEval {
   float dx, dy, G, ga;  // ga = o * G before the alpha_max clamp
 };
-__device__ __forceinline__ AlphaEval alpha_eval(float px, float py, float mx, float my, float A, float B, float C,
+__device__ __forceinline__ AlphaEval alpha_eval(float px, float py, float mx, float my, float a2, float b2, float c2,
                                                 float o) {
   AlphaEval r;
   r.dx = px - mx;
   r.dy = py - my;
-  const float q = fmaf(A, r.dx * r.dx, fmaf(C, r.dy * r.dy, 2.0f * B * (r.dx * r.dy)));
-  r.G = __builtin_amdgcn_exp2f((-0.5f * q) * kLog2e);
+  const float u = fmaf(a2, r.dx, b2 * r.dy);
+  r.G = __builtin_amdgcn_exp2f(fmaf(u, r.dx, (c2 * r.dy) * r.dy));
   r.ga = o * r.G;
   return r;
 }
+constexpr float kLn2 = 0.6931471805599453f;
 
 // Residual channel r -> parameter channel.
 __device__ __forceinline__ int res_to_param(int r) {
@@ -752,15 +755,32 @@ struct EllipseRows {
   }
 };
 
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+
 // Level 1: rows. Each wave walks kBinChunk depth-sorted Gaussians of one
-// frame-view in order; its lanes cover one Gaussian's tile rows at a time, so
-// the per-row counters in LDS see the Gaussians in depth order (a stable
-// counting sort). An entry is (Gaussian index, tile-column range in the row).
+// frame-view, 64 at a time with one Gaussian per lane. A lane evaluates the
+// first kRowPre tile rows of its Gaussian up front; the wave then visits the
+// tile rows the batch reaches, and per row a ballot ranks the hitting lanes,
+// so the entries of a row keep the depth order of the batch (a stable counting
+// sort; the per-row counters live in LDS). Gaussians taller than kRowPre rows
+// evaluate their further rows inside the row loop. An entry is (Gaussian
+// index, tile-column range in the row).
 template <bool EMIT>
 __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ svals, const float4* __restrict__ brec,
                                                 uint32_t* __restrict__ hist, const uint2* __restrict__ row_ranges,
                                                 uint2* __restrict__ row_lists) {
+  constexpr int kRowPre = 4;
   extern __shared__ uint32_t cnt[];
   const int lane = threadIdx.x;
   const int b = blockIdx.y, chunk = blockIdx.x;
@@ -773,48 +793,61 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
   const int end = min(start + kBinChunk, d.n);
   for (int base = start; base < end; base += 64) {
     const int e = base + lane;
-    uint32_t idx = 0;
-    float4 q0 = make_float4(0.f, 0.f, 1.f, 0.f), q1 = make_float4(1.f, 1.f, 0.f, 0.f);
-    float4 q2 = make_float4(-1.f, 0.f, 0.f, 0.f);
+    uint32_t gi = 0;
     bool ok = false;
+    EllipseRows el{};
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
     if (e < end) {
       ok = skeys[seg + e] != 0xFFFFFFFFu;
       if (ok) {
-        idx = svals[seg + e];
-        q0 = brec[3 * (seg + e)];
-        q1 = brec[3 * (seg + e) + 1];
-        q2 = brec[3 * (seg + e) + 2];
+        gi = svals[seg + e];
+        const float4 q0 = brec[3 * (seg + e)], q1 = brec[3 * (seg + e) + 1], q2 = brec[3 * (seg + e) + 2];
+        el = EllipseRows{q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q2.x, q1.z, q1.w};
+        const uint32_t rx = __float_as_uint(q2.z), ry = __float_as_uint(q2.w);
+        x0 = (int)(rx & 0xFFFF);
+        x1 = (int)(rx >> 16);
+        y0 = (int)(ry & 0xFFFF);
+        y1 = (int)(ry >> 16);
       }
     }
-    const unsigned long long live = __ballot(ok);
-    if (live == 0ull) break;  // culled keys sort last
-    const int nlive = 64 - __clzll(live);  // keys are sorted, so live lanes are a prefix
-    for (int j = 0; j < nlive; ++j) {
-      const uint32_t gi = __builtin_amdgcn_readlane(idx, j);
-      EllipseRows el;
-      el.mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.x), j));
-      el.my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.y), j));
-      el.A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.z), j));
-      el.B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.w), j));
-      el.det = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.x), j));
-      el.iA = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.y), j));
-      el.dyr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.z), j));
-      el.dym = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.w), j));
-      el.tau = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.x), j));
-      const uint32_t rx = __builtin_amdgcn_readlane(__float_as_uint(q2.z), j);
-      const uint32_t ry = __builtin_amdgcn_readlane(__float_as_uint(q2.w), j);
-      const int x0 = rx & 0xFFFF, x1 = rx >> 16, y0 = ry & 0xFFFF, y1 = ry >> 16;
-      for (int ty = y0 + lane; ty <= y1; ty += 64) {
-        int txl, txh;
-        if (!el.row(d, ty, x0, x1, txl, txh)) continue;
-        if (EMIT) {
-          const uint32_t pos = cnt[ty];
-          if (pos < d.row_capacity) row_lists[pos] = make_uint2(gi, (uint32_t)txl | ((uint32_t)txh << 16));
-          cnt[ty] = pos + 1;
-        } else {
-          cnt[ty] += 1u;
+    if (__ballot(ok) == 0ull) break;  // culled keys sort last
+    uint32_t hm = 0, pk[kRowPre];
+#pragma unroll
+    for (int r = 0; r < kRowPre; ++r) {
+      int txl = 0, txh = 0;
+      const bool h = ok && y0 + r <= y1 && el.row(d, y0 + r, x0, x1, txl, txh);
+      hm |= h ? 1u << r : 0u;
+      pk[r] = h ? ((uint32_t)txl | ((uint32_t)txh << 16)) : 0u;
+    }
+    const bool tall = ok && y1 - y0 >= kRowPre;
+    int ylo = hm ? y0 + __builtin_ctz(hm) : 0x7FFFFFFF;
+    int yhi = hm ? y0 + 31 - __builtin_clz(hm) : -1;
+    if (tall) {
+      ylo = min(ylo, y0 + kRowPre);
+      yhi = y1;
+    }
+    const bool any_tall = __ballot(tall) != 0ull;
+    ylo = wave_min_i(ylo);
+    yhi = wave_max_i(yhi);
+    for (int ty = ylo; ty <= yhi; ++ty) {
+      const uint32_t r = (uint32_t)(ty - y0);
+      bool hit = r < (uint32_t)kRowPre && ((hm >> r) & 1u);
+      uint32_t rg = r == 0 ? pk[0] : r == 1 ? pk[1] : r == 2 ? pk[2] : pk[3];
+      if (any_tall) {
+        int txl = 0, txh = 0;
+        if (tall && r >= (uint32_t)kRowPre && ty <= y1 && el.row(d, ty, x0, x1, txl, txh)) {
+          hit = true;
+          rg = (uint32_t)txl | ((uint32_t)txh << 16);
         }
       }
+      const unsigned long long m = __ballot(hit);
+      if (m == 0ull) continue;
+      const uint32_t pos0 = cnt[ty];
+      if (EMIT && hit) {
+        const uint32_t pos = pos0 + popc_below(m);
+        if (pos < d.row_capacity) row_lists[pos] = make_uint2(gi, rg);
+      }
+      if (lane == 0) cnt[ty] = pos0 + (uint32_t)__popcll(m);
     }
   }
   __syncthreads();
@@ -979,7 +1012,7 @@ __global__ __launch_bounds__(1024) void k_scan_ranges(int count, int level, unsi
 
 // ============================================================ rasterization
 struct TileCtx {
-  int b, tile, px, py;
+  int b, tile, px, py, ox, oy;  // ox, oy: pixel origin of the tile
   bool inside;
   uint2 range;
 };
@@ -991,8 +1024,12 @@ __device__ __forceinline__ bool tile_ctx(const RenderDims& d, const uint2* range
   c.b = wid / d.T;
   c.tile = wid - c.b * d.T;
   const int tx = c.tile % d.TX, ty = c.tile / d.TX;
-  c.px = tx * kTile + (threadIdx.x & (kTile - 1));
-  c.py = ty * kTile + (threadIdx.x / kTile);
+  c.ox = tx * kTile;
+  c.oy = ty * kTile;
+  // wave w covers the 8x8 quadrant (w & 1, w >> 1) of the tile, lane l its pixel (l & 7, l >> 3)
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  c.px = tx * kTile + (w & 1) * 8 + (l & 7);
+  c.py = ty * kTile + (w >> 1) * 8 + (l >> 3);
   c.inside = c.px < d.W && c.py < d.H;
   c.range = ranges[(size_t)c.b * d.T + c.tile];
   return true;
@@ -1029,6 +1066,36 @@ __device__ __forceinline__ uint32_t first_layer(const RenderDims& d, uint32_t gi
   return l;
 }
 
+// Quadrants (bit 2 qy + qx) of the 16x16 tile with origin (x0, y0) whose pixel
+// centres the ellipse q(p) <= tau of alpha >= alpha_min may reach. The same
+// exact row-extent test (and margins) as the binning, on 8-pixel bands; a wave
+// skips every entry whose bit for its quadrant is clear.
+__device__ __forceinline__ uint32_t quad_mask(const RenderDims& d, float mx, float my, float A, float B, float C,
+                                              float o, int x0, int y0) {
+  const float tau = 2.f * (logf(o) - logf(d.alpha_min)) * 1.001f + 1e-3f;
+  const float det = A * C - B * B;
+  if (!(tau > 0.f) || !(det > 0.f) || !(A > 0.f) || !(C > 0.f)) return 0xFu;
+  const float iA = 1.f / A;
+  const float dxm = sqrtf(tau * C / det);
+  const float dyr = -B * dxm / C, dym = sqrtf(A * tau / det);
+  uint32_t m = 0;
+#pragma unroll
+  for (int qy = 0; qy < 2; ++qy) {
+    const float Y0 = (float)(y0 + 8 * qy) + 0.5f - my;
+    const float lo = fmaxf(Y0, -dym), hi = fminf(Y0 + 7.f, dym);
+    if (!(lo <= hi)) continue;
+    const float dr = fminf(fmaxf(dyr, lo), hi), dl = fminf(fmaxf(-dyr, lo), hi);
+    const float xr = mx + (-B * dr + sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
+    const float xl = mx + (-B * dl - sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
+#pragma unroll
+    for (int qx = 0; qx < 2; ++qx) {
+      const float X0 = (float)(x0 + 8 * qx) + 0.5f;
+      if (xl <= X0 + 7.f && xr >= X0) m |= 1u << (2 * qy + qx);
+    }
+  }
+  return m;
+}
+
 // Block-wide stable compaction of one candidate per thread: returns the slot of
 // this thread's candidate (if `keep`) and the number kept in *total.
 __device__ __forceinline__ int compact_slot(bool keep, uint32_t* s_wcnt, int* total) {
@@ -1057,10 +1124,11 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
   TileCtx c;
   if (!tile_ctx(d, ranges, c)) return;
   __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
-  __shared__ float4 s_b[kTilePix];  // conic A, B, C, first layer bits
+  __shared__ float4 s_b[kTilePix];  // scaled conic a2, b2, c2, (first layer | quadrant mask << 8) bits
   __shared__ float4 s_c[kTilePix];  // r, g, b, list position bits
   __shared__ uint32_t s_wcnt[kTilePix / 64];
   __shared__ uint32_t s_hi;
+  const uint32_t qbit = __builtin_amdgcn_readfirstlane(1u << (8 + (threadIdx.x >> 6)));
   const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
   float Tr[MAXL], Cr[MAXL], Cg[MAXL], Cb[MAXL];
   uint32_t last[MAXL];
@@ -1087,30 +1155,36 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
     if (gi < hib) {
       const float4* r = rec + 3 * (recbase + gi);
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+      const uint32_t qm = quad_mask(d, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, c.ox, c.oy);
       s_a[slot] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
-      s_b[slot] = make_float4(r0.z, r0.w, r1.x, __uint_as_float(first_layer(d, gi)));
+      s_b[slot] = make_float4(-0.5f * kLog2e * r0.z, -kLog2e * r0.w, -0.5f * kLog2e * r1.x,
+                              __uint_as_float(first_layer(d, gi) | (qm << 8)));
       s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k - c.range.x + 1));
     }
     __syncthreads();
     if (alive) {
       for (int j = 0; j < cnt; ++j) {
+        const float4 cb = s_b[j];
+        const uint32_t meta = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w));
+        if (!(meta & qbit)) continue;  // the ellipse misses this wave's quadrant
         const float4 a = s_a[j];
         const uint32_t g = __float_as_uint(a.w);
         if (g >= nlhi) continue;
-        const float4 cb = s_b[j];
         const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
         ++n_eval;
         if (!(ev.ga >= d.alpha_min)) continue;
         const float al = fminf(d.alpha_max, ev.ga);
         const float oma = 1.f - al;
         const float4 col = s_c[j];
-        const uint32_t lmin = __float_as_uint(cb.w);
+        const uint32_t lmin = meta & 0xFFu;
+        bool died = false;
 #pragma unroll
         for (int l = 0; l < MAXL; ++l) {
           if ((uint32_t)l < lmin || !((alive >> l) & 1u)) continue;
           const float Tn = Tr[l] * oma;
           if (Tn < d.t_stop) {
             alive &= ~(1u << l);
+            died = true;
             continue;
           }
           const float wgt = al * Tr[l];
@@ -1121,8 +1195,14 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
           last[l] = __float_as_uint(col.w);
           ++n_contrib;
         }
-        if (!alive) break;
-        nlhi = (uint32_t)d.lv[31 - __clz(alive)];
+        if (died) {
+          if (!alive) break;
+          uint32_t hb = 0;
+#pragma unroll
+          for (int l = 0; l < MAXL; ++l)
+            if (l < d.L && ((alive >> l) & 1u)) hb = (uint32_t)d.lv[l];
+          nlhi = hb;
+        }
       }
       if (!alive) nlhi = 0;
     }
@@ -1143,6 +1223,58 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
   }
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within each 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within each 16 lanes
+
+// Wave reduction of nine per-lane values. Values 0..7 are reduce-scattered:
+// each halving step pairs two values and exchanges the halves of the wave
+// that keep them (v_permlane32_swap, then v_permlane16_swap across rows, then a
+// row mirror), so that every aligned group of 8 lanes ends with the sum of one
+// value over all 64 lanes, which a butterfly inside the group completes. Value
+// 8 is reduced to every lane. On return g[0] holds the group's value and g[8]
+// value 8.
+__device__ __forceinline__ void reduce_scatter9(float* g, int lane) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(g[q]), __float_as_uint(g[q + 4]), false, false);
+    g[q] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(g[q]), __float_as_uint(g[q + 2]), false, false);
+    g[q] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  {
+    const bool hi = lane & 8;
+    const float send = hi ? g[0] : g[1];
+    const float keep = hi ? g[1] : g[0];
+    g[0] = keep + dpp<kDppMirror>(send);
+  }
+  g[0] += dpp<kDppHalfMirror>(g[0]);
+  g[0] += dpp<kDppXor2>(g[0]);
+  g[0] += dpp<kDppXor1>(g[0]);
+  float v = g[8];
+  v += dpp<kDppHalfMirror>(v);
+  v += dpp<kDppXor2>(v);
+  v += dpp<kDppXor1>(v);
+  v += dpp<kDppMirror>(v);
+  {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  g[8] = v;
+}
+
 template <int MAXL>
 __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
@@ -1158,13 +1290,14 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   TileCtx c;
   if (!tile_ctx(d, ranges, c)) return;
   __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
-  __shared__ float4 s_b[kTilePix];  // conic A, B, C, first layer bits
+  __shared__ float4 s_b[kTilePix];  // scaled conic a2, b2, c2, (first layer | quadrant mask << 8) bits
   __shared__ float4 s_c[kTilePix];  // r, g, b, list position bits
   __shared__ float s_g[kTilePix][kGradLds];  // per-entry gradient sums of the four waves
   __shared__ uint32_t s_wcnt[kTilePix / 64];
   __shared__ uint32_t s_lmax[kMaxLevels];
   __shared__ float s_loss;
   const int t = threadIdx.x;
+  const uint32_t qbit = __builtin_amdgcn_readfirstlane(1u << (8 + (t >> 6)));
   if (t < kMaxLevels) s_lmax[t] = 0;
   if (t == 0) s_loss = 0.f;
   for (int v = 0; v < kGradLds; ++v) s_g[t][v] = 0.f;
@@ -1172,7 +1305,9 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
   const size_t HW = (size_t)d.W * d.H;
   const size_t pix = (size_t)c.py * d.W + c.px;
-  float Tr[MAXL], wr[MAXL], wg[MAXL], wb[MAXL], Sr[MAXL], Sg[MAXL], Sb[MAXL];
+  // Q[l]: the colour composited behind the current entry (background included), weighted by
+  // dL/dC of the layer and summed over the channels; it is all the backward needs of it
+  float Tr[MAXL], wr[MAXL], wg[MAXL], wb[MAXL], Q[MAXL];
   uint32_t last[MAXL];
   float loss = 0.f;
   const float inv3hw = 1.0f / (3.0f * (float)HW);
@@ -1197,7 +1332,7 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       wr[l] = w3[0]; wg[l] = w3[1]; wb[l] = w3[2];
       if (last[l]) atomicMax(&s_lmax[l], last[l]);
     }
-    Sr[l] = Tr[l] * d.bg[0]; Sg[l] = Tr[l] * d.bg[1]; Sb[l] = Tr[l] * d.bg[2];
+    Q[l] = Tr[l] * (wr[l] * d.bg[0] + wg[l] * d.bg[1] + wb[l] * d.bg[2]);
   }
   if (loss_out) {
     loss = wave_sum(loss);
@@ -1215,7 +1350,14 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   const size_t recbase = (size_t)c.b * d.n;
   const int lane = t & 63;
   uint32_t n_eval = 0, n_contrib = 0;
-  const int vid = (lane >> 3) & 7;  // value a lane holds after the reduce-scatter
+  // the value index an aligned 8-lane group holds after reduce_scatter9: reduce the one-hot
+  // pattern g[q] = q (every lane), which leaves 64 * index in each lane
+  int vid;
+  {
+    float pr[9] = {0.f, 1.f, 2.f, 3.f, 4.f, 5.f, 6.f, 7.f, 0.f};
+    reduce_scatter9(pr, lane);
+    vid = (int)(pr[0] * (1.f / 64.f) + 0.5f);
+  }
   for (int top = (int)ktop; top > 0; top -= kTilePix) {
     const int lo = max(0, top - kTilePix);
     __syncthreads();
@@ -1234,96 +1376,69 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
     if (need) {
       const float4* r = rec + 3 * (recbase + gi);
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+      const uint32_t qm = quad_mask(d, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, c.ox, c.oy);
       s_a[slot] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
-      s_b[slot] = make_float4(r0.z, r0.w, r1.x, __uint_as_float(first_layer(d, gi)));
+      s_b[slot] = make_float4(-0.5f * kLog2e * r0.z, -kLog2e * r0.w, -0.5f * kLog2e * r1.x,
+                              __uint_as_float(first_layer(d, gi) | (qm << 8)));
       s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k));
     }
     __syncthreads();
     for (int j = cnt - 1; j >= 0; --j) {
+      const float4 cb = s_b[j];
+      const uint32_t meta = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w));
+      if (!(meta & qbit)) continue;  // the ellipse misses this wave's quadrant
       const float4 a = s_a[j];
       const float4 col = s_c[j];
       const uint32_t kk = __float_as_uint(col.w);
-      const float4 cb = s_b[j];
-      const uint32_t lmin = __float_as_uint(cb.w);
+      const uint32_t lmin = meta & 0xFFu;
       bool cand = false;
 #pragma unroll
       for (int l = 0; l < MAXL; ++l) cand = cand || ((uint32_t)l >= lmin && kk < last[l]);
-      float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (__ballot(cand) == 0ull) continue;
+      // straight-line code from here on (lanes that are not candidates compute and discard),
+      // so that the accumulators below need no copies at control-flow joins
+      const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
+      n_eval += cand ? 1u : 0u;
+      const bool hit = cand && ev.ga >= d.alpha_min;
+      if (__ballot(hit) == 0ull) continue;
+      const float al = fminf(d.alpha_max, ev.ga);
+      const float oma = 1.f - al;
+      const float ioma = __builtin_amdgcn_rcpf(oma);
+      float g[9];
+      g[6] = g[7] = g[8] = 0.f;
+      float dal = 0.f;
       bool contrib = false;
-      if (cand) {
-        const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
-        ++n_eval;
-        if (ev.ga >= d.alpha_min) {
-          const float al = fminf(d.alpha_max, ev.ga);
-          const float oma = 1.f - al;
-          const float ioma = 1.0f / oma;
-          float dal = 0.f;
 #pragma unroll
-          for (int l = 0; l < MAXL; ++l) {
-            if (!((uint32_t)l >= lmin && kk < last[l])) continue;
-            const float Tb = Tr[l] * ioma;  // transmittance in front of this Gaussian
-            const float wT = al * Tb;
-            g[6] = fmaf(wr[l], wT, g[6]);
-            g[7] = fmaf(wg[l], wT, g[7]);
-            g[8] = fmaf(wb[l], wT, g[8]);
-            dal += wr[l] * (col.x * Tb - Sr[l] * ioma) + wg[l] * (col.y * Tb - Sg[l] * ioma) +
-                   wb[l] * (col.z * Tb - Sb[l] * ioma);
-            Sr[l] = fmaf(col.x, wT, Sr[l]);
-            Sg[l] = fmaf(col.y, wT, Sg[l]);
-            Sb[l] = fmaf(col.z, wT, Sb[l]);
-            Tr[l] = Tb;
-            contrib = true;
-            ++n_contrib;
-          }
-          if (contrib && ev.ga <= d.alpha_max) {
-            g[5] = dal * ev.G;
-            const float dp = dal * ev.ga;
-            g[0] = dp * (cb.x * ev.dx + cb.y * ev.dy);
-            g[1] = dp * (cb.y * ev.dx + cb.z * ev.dy);
-            g[2] = -0.5f * dp * ev.dx * ev.dx;
-            g[3] = -dp * ev.dx * ev.dy;
-            g[4] = -0.5f * dp * ev.dy * ev.dy;
-          }
-        }
+      for (int l = 0; l < MAXL; ++l) {
+        if ((uint32_t)l < lmin) continue;  // uniform
+        if (!(hit && kk < last[l])) continue;
+        const float Tb = Tr[l] * ioma;  // transmittance in front of this Gaussian
+        const float wT = al * Tb;
+        g[6] = fmaf(wr[l], wT, g[6]);
+        g[7] = fmaf(wg[l], wT, g[7]);
+        g[8] = fmaf(wb[l], wT, g[8]);
+        const float wc = fmaf(wr[l], col.x, fmaf(wg[l], col.y, wb[l] * col.z));
+        dal = fmaf(Tb, wc, fmaf(-Q[l], ioma, dal));
+        Q[l] = fmaf(wT, wc, Q[l]);
+        Tr[l] = Tb;
+        contrib = true;
+        ++n_contrib;
       }
+      // the clamp at alpha_max has zero derivative; dal is zero without a contribution
+      const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
+      g[5] = dl * ev.G;
+      const float dp = dl * ev.ga;
+      // conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2)
+      const float dpl = -kLn2 * dp;
+      g[0] = dpl * fmaf(2.f * cb.x, ev.dx, cb.y * ev.dy);
+      g[1] = dpl * fmaf(cb.y, ev.dx, 2.f * cb.z * ev.dy);
+      g[2] = -0.5f * dp * ev.dx * ev.dx;
+      g[3] = -dp * ev.dx * ev.dy;
+      g[4] = -0.5f * dp * ev.dy * ev.dy;
       if (__ballot(contrib) != 0ull) {
-        // reduce-scatter of values 0..7 over the wave (each step halves the values a lane keeps),
-        // then a plain reduction of the last value and of value 8
-        float v8 = g[8];
-        {
-          const bool hi = lane & 32;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float send = hi ? g[q] : g[q + 4];
-            const float keep = hi ? g[q + 4] : g[q];
-            g[q] = keep + __shfl_xor(send, 32);
-          }
-          v8 += __shfl_xor(v8, 32);
-        }
-        {
-          const bool hi = lane & 16;
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const float send = hi ? g[q] : g[q + 2];
-            const float keep = hi ? g[q + 2] : g[q];
-            g[q] = keep + __shfl_xor(send, 16);
-          }
-          v8 += __shfl_xor(v8, 16);
-        }
-        {
-          const bool hi = lane & 8;
-          const float send = hi ? g[0] : g[1];
-          const float keep = hi ? g[1] : g[0];
-          g[0] = keep + __shfl_xor(send, 8);
-          v8 += __shfl_xor(v8, 8);
-        }
-#pragma unroll
-        for (int off = 4; off > 0; off >>= 1) {
-          g[0] += __shfl_xor(g[0], off);
-          v8 += __shfl_xor(v8, off);
-        }
+        reduce_scatter9(g, lane);
         if ((lane & 7) == 0 && g[0] != 0.f) atomicAdd(&s_g[j][vid], g[0]);
-        if (lane == 0 && v8 != 0.f) atomicAdd(&s_g[j][8], v8);
+        if (lane == 0 && g[8] != 0.f) atomicAdd(&s_g[j][8], g[8]);
       }
     }
     __syncthreads();
