@@ -856,18 +856,19 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
 }
 
 // Level 2: tiles of one row. One wave takes a segment of kRowSeg entries of a
-// (frame-view, row) list; lane l owns tile columns l and l + 64 and appends, in
-// list (= depth) order, every entry whose column range covers them, so each
-// lane writes its own tile list sequentially.
-template <bool EMIT>
+// (frame-view, row) list; lane l owns tile column l (and l + 64 when the image
+// is wider than 64 tiles, TWO) and appends, in list (= depth) order, every
+// entry whose column range covers it, so each lane writes its own tile list
+// sequentially.
+template <bool EMIT, bool TWO>
 __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __restrict__ st,
                                                  const uint2* __restrict__ row_ranges,
                                                  const uint2* __restrict__ row_lists, uint32_t* __restrict__ hist,
                                                  const uint2* __restrict__ ranges, uint32_t* __restrict__ lists) {
-  // emit: each lane gathers up to kWc entries of each of its two tiles in LDS and writes them
-  // out as one contiguous run that ends on a kWc-entry boundary of the list
+  // emit: each lane gathers up to kWc entries of each of its tiles in LDS and writes them out as
+  // one contiguous run that ends on a kWc-entry boundary of the list
   constexpr int kWc = 16;
-  __shared__ __align__(16) uint32_t wbuf[2][64][kWc];
+  __shared__ __align__(16) uint32_t wbuf[TWO ? 2 : 1][64][kWc];
   if (st->overflow & 2u) return;
   const int lane = threadIdx.x;
   const int s = blockIdx.x, ty = blockIdx.y, b = blockIdx.z;
@@ -912,7 +913,7 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
           ++c0;
         }
       }
-      if (tx1 >= txl && tx1 <= txh) {
+      if (TWO && tx1 >= txl && tx1 <= txh) {
         if (EMIT) {
           wbuf[1][lane][n1++] = gi;
           if (((c1 + n1) & (kWc - 1)) == 0) flush(1, c1, n1);
@@ -924,10 +925,10 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
   }
   if (EMIT) {
     flush(0, c0, n0);
-    flush(1, c1, n1);
+    if (TWO) flush(1, c1, n1);
   } else {
     if (tx0 < d.TX) hb[tx0] = c0;
-    if (tx1 < d.TX) hb[tx1] = c1;
+    if (TWO && tx1 < d.TX) hb[tx1] = c1;
   }
 }
 
@@ -1066,18 +1067,41 @@ __device__ __forceinline__ uint32_t first_layer(const RenderDims& d, uint32_t gi
   return l;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within each 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within each 16 lanes
+
+// Unsigned maximum over the wave, in every lane (all 64 lanes active).
+__device__ __forceinline__ uint32_t wave_max_u(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppXor1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppXor2, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppHalfMirror, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppMirror, 0xF, 0xF, false));
+  const auto r16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = max(r16[0], r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return __builtin_amdgcn_readfirstlane(max(r32[0], r32[1]));
+}
+
 // Quadrants (bit 2 qy + qx) of the 16x16 tile with origin (x0, y0) whose pixel
 // centres the ellipse q(p) <= tau of alpha >= alpha_min may reach. The same
 // exact row-extent test (and margins) as the binning, on 8-pixel bands; a wave
 // skips every entry whose bit for its quadrant is clear.
 __device__ __forceinline__ uint32_t quad_mask(const RenderDims& d, float mx, float my, float A, float B, float C,
                                               float o, int x0, int y0) {
-  const float tau = 2.f * (logf(o) - logf(d.alpha_min)) * 1.001f + 1e-3f;
+  // hardware log / reciprocal / square root: their relative errors (~1e-7) are far inside the
+  // 1e-3 threshold margin and the 0.01-pixel margin
+  const float tau = 2.f * (__logf(o) - __logf(d.alpha_min)) * 1.001f + 1e-3f;
   const float det = A * C - B * B;
   if (!(tau > 0.f) || !(det > 0.f) || !(A > 0.f) || !(C > 0.f)) return 0xFu;
-  const float iA = 1.f / A;
-  const float dxm = sqrtf(tau * C / det);
-  const float dyr = -B * dxm / C, dym = sqrtf(A * tau / det);
+  const float iA = __builtin_amdgcn_rcpf(A), idet = __builtin_amdgcn_rcpf(det);
+  const float dxm = __builtin_amdgcn_sqrtf(tau * C * idet);
+  const float dyr = -B * dxm * __builtin_amdgcn_rcpf(C), dym = __builtin_amdgcn_sqrtf(A * tau * idet);
   uint32_t m = 0;
 #pragma unroll
   for (int qy = 0; qy < 2; ++qy) {
@@ -1085,8 +1109,8 @@ __device__ __forceinline__ uint32_t quad_mask(const RenderDims& d, float mx, flo
     const float lo = fmaxf(Y0, -dym), hi = fminf(Y0 + 7.f, dym);
     if (!(lo <= hi)) continue;
     const float dr = fminf(fmaxf(dyr, lo), hi), dl = fminf(fmaxf(-dyr, lo), hi);
-    const float xr = mx + (-B * dr + sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
-    const float xl = mx + (-B * dl - sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
+    const float xr = mx + (-B * dr + __builtin_amdgcn_sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
+    const float xl = mx + (-B * dl - __builtin_amdgcn_sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
 #pragma unroll
     for (int qx = 0; qx < 2; ++qx) {
       const float X0 = (float)(x0 + 8 * qx) + 0.5f;
@@ -1126,9 +1150,11 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
   __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
   __shared__ float4 s_b[kTilePix];  // scaled conic a2, b2, c2, (first layer | quadrant mask << 8) bits
   __shared__ float4 s_c[kTilePix];  // r, g, b, list position bits
+  __shared__ uint8_t s_idx[kTilePix / 64][kTilePix];  // per wave: the staged entries it needs, in order
   __shared__ uint32_t s_wcnt[kTilePix / 64];
   __shared__ uint32_t s_hi;
-  const uint32_t qbit = __builtin_amdgcn_readfirstlane(1u << (8 + (threadIdx.x >> 6)));
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const uint32_t qbit = 1u << (8 + wv);
   const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
   float Tr[MAXL], Cr[MAXL], Cg[MAXL], Cb[MAXL];
   uint32_t last[MAXL];
@@ -1162,21 +1188,33 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
       s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k - c.range.x + 1));
     }
     __syncthreads();
+    // this wave's list: staged entries whose ellipse reaches its quadrant, below the highest open
+    // layer bound of its own pixels (wave-private LDS, written and read in order by the wave)
+    const uint32_t hw = wave_max_u(nlhi);
+    int cw = 0;
+    if (hw) {
+      for (int q = 0; q < cnt; q += 64) {
+        const int e = q + lane;
+        const bool keep =
+            e < cnt && (__float_as_uint(s_b[e].w) & qbit) && __float_as_uint(s_a[e].w) < hw;
+        const unsigned long long m = __ballot(keep);
+        if (keep) s_idx[wv][cw + (int)popc_below(m)] = (uint8_t)e;
+        cw += (int)__popcll(m);
+      }
+    }
     if (alive) {
-      for (int j = 0; j < cnt; ++j) {
-        const float4 cb = s_b[j];
-        const uint32_t meta = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w));
-        if (!(meta & qbit)) continue;  // the ellipse misses this wave's quadrant
-        const float4 a = s_a[j];
-        const uint32_t g = __float_as_uint(a.w);
-        if (g >= nlhi) continue;
+      for (int j = 0; j < cw; ++j) {
+        const int e = s_idx[wv][j];
+        const float4 a = s_a[e];
+        if (__float_as_uint(a.w) >= nlhi) continue;
+        const float4 cb = s_b[e];
         const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
         ++n_eval;
         if (!(ev.ga >= d.alpha_min)) continue;
         const float al = fminf(d.alpha_max, ev.ga);
         const float oma = 1.f - al;
-        const float4 col = s_c[j];
-        const uint32_t lmin = meta & 0xFFu;
+        const float4 col = s_c[e];
+        const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
         bool died = false;
 #pragma unroll
         for (int l = 0; l < MAXL; ++l) {
@@ -1222,15 +1260,6 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
     n_last[o * HW + pix] = last[l];
   }
 }
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
-constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
-constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within each 8 lanes
-constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within each 16 lanes
 
 // Wave reduction of nine per-lane values. Values 0..7 are reduce-scattered:
 // each halving step pairs two values and exchanges the halves of the wave
@@ -1296,8 +1325,10 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   __shared__ uint32_t s_wcnt[kTilePix / 64];
   __shared__ uint32_t s_lmax[kMaxLevels];
   __shared__ float s_loss;
+  __shared__ uint8_t s_idx[kTilePix / 64][kTilePix];  // per wave: the staged entries it needs, in order
   const int t = threadIdx.x;
-  const uint32_t qbit = __builtin_amdgcn_readfirstlane(1u << (8 + (t >> 6)));
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const uint32_t qbit = 1u << (8 + wv);
   if (t < kMaxLevels) s_lmax[t] = 0;
   if (t == 0) s_loss = 0.f;
   for (int v = 0; v < kGradLds; ++v) s_g[t][v] = 0.f;
@@ -1347,6 +1378,17 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
     lmax[l] = l < d.L ? s_lmax[l] : 0u;
     ktop = max(ktop, lmax[l]);
   }
+  // per wave: lw[m] = the largest last-contributor position over its pixels and the layers l >= m,
+  // so that an entry of first layer m at position kk can matter to the wave only if kk < lw[m]
+  uint32_t lw[MAXL];
+  {
+    uint32_t run = 0;
+#pragma unroll
+    for (int l = MAXL - 1; l >= 0; --l) {
+      run = max(run, wave_max_u(l < d.L ? last[l] : 0u));
+      lw[l] = run;
+    }
+  }
   const size_t recbase = (size_t)c.b * d.n;
   const int lane = t & 63;
   uint32_t n_eval = 0, n_contrib = 0;
@@ -1383,14 +1425,31 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k));
     }
     __syncthreads();
-    for (int j = cnt - 1; j >= 0; --j) {
+    // this wave's list: staged entries whose ellipse reaches its quadrant and that lie before the
+    // last contributor of some layer they belong to, for some pixel of the wave
+    int cw = 0;
+    for (int q = 0; q < cnt; q += 64) {
+      const int e = q + lane;
+      bool keep = false;
+      if (e < cnt) {
+        const uint32_t meta = __float_as_uint(s_b[e].w);
+        const uint32_t lm = meta & 0xFFu;
+        uint32_t lim = 0;
+#pragma unroll
+        for (int l = 0; l < MAXL; ++l) lim = lm == (uint32_t)l ? lw[l] : lim;
+        keep = (meta & qbit) && __float_as_uint(s_c[e].w) < lim;
+      }
+      const unsigned long long m = __ballot(keep);
+      if (keep) s_idx[wv][cw + (int)popc_below(m)] = (uint8_t)e;
+      cw += (int)__popcll(m);
+    }
+    for (int jw = cw - 1; jw >= 0; --jw) {
+      const int j = s_idx[wv][jw];
       const float4 cb = s_b[j];
-      const uint32_t meta = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w));
-      if (!(meta & qbit)) continue;  // the ellipse misses this wave's quadrant
       const float4 a = s_a[j];
       const float4 col = s_c[j];
       const uint32_t kk = __float_as_uint(col.w);
-      const uint32_t lmin = meta & 0xFFu;
+      const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
       bool cand = false;
 #pragma unroll
       for (int l = 0; l < MAXL; ++l) cand = cand || ((uint32_t)l >= lmin && kk < last[l]);
@@ -1597,7 +1656,12 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   }
   if (d.n_row_segs > 0) {
     ProfScope ps_(K_BIN_COUNT, st);
-    hipLaunchKernelGGL(k_tile_bin<false>, grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges, lists);
+    if (d.TX > 64)
+      hipLaunchKernelGGL((k_tile_bin<false, true>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
+                         lists);
+    else
+      hipLaunchKernelGGL((k_tile_bin<false, false>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
+                         lists);
   }
   {
     ProfScope ps_(K_TILE_RANGES, st);
@@ -1606,7 +1670,12 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   }
   if (d.n_row_segs > 0) {
     ProfScope ps_(K_BIN_EMIT, st);
-    hipLaunchKernelGGL(k_tile_bin<true>, grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges, lists);
+    if (d.TX > 64)
+      hipLaunchKernelGGL((k_tile_bin<true, true>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
+                         lists);
+    else
+      hipLaunchKernelGGL((k_tile_bin<true, false>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
+                         lists);
   }
   return hipGetLastError();
 }
