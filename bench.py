@@ -144,6 +144,8 @@ def bench_rate(torch, dev, L, steps, n=1_000_000):
         rm.reset()
         rm.run(attrs, n, ctx, 1, lv, lw, 1e-3, seed=1, offset=0, d_attrs_ptr=ctypes.c_void_p(da.data_ptr()))
 
+    blocks, cand_ms = rm.autotune(attrs, n, ctx, 1, lv, lw, 1e-3, d_attrs_ptr=ctypes.c_void_p(da.data_ptr()))
+    da.zero_()
     one()
     histogram_bits(p[3:59])
     torch.cuda.synchronize()
@@ -165,7 +167,8 @@ def bench_rate(torch, dev, L, steps, n=1_000_000):
             "mlp_tflops": flop / (ms * 1e-3) / 1e12, "mfma_frac": flop / (ms * 1e-3) / BF16_PEAK_FLOPS,
             "histogram_ms": hist_ms, "histogram_GB/s": n * 56 * 4 * 2 / (hist_ms * 1e-3) / 1e9,
             "mlp_bits": float(rm.bits.sum().item()), "hist_bits": float(hb.sum().item()),
-            "kernels_ms": times}
+            "kernels_ms": times, "autotune": {"blocks_per_attr": blocks,
+                                               "candidates": dict(zip((16, 32, 64, 128, 256), cand_ms))}}
 
 
 def bench_group(torch, dev, steps):

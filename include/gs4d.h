@@ -190,10 +190,26 @@ typedef struct {
   float level_weights[8];
   float lambda_rate;
   float fit_scale;
+  int32_t blocks_per_attr; /* launch blocks per attribute; 0 = the library default (64, fewer when
+                              n is small); gs_rate_autotune picks one for a given workload */
 } gs_rate_desc;
 int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
                   const float* b_f32, double* bits_out, double* loss_out, float* sym_bits, float* d_attrs, float* d_w,
                   float* d_b, void* stream);
+
+/* Launch-shape autotuner of gs_rate_model (the rate MLP's only free parameter: how many
+ * blocks share an attribute's symbols; it changes the summation order, not the result).
+ * Runs desc with blocks_per_attr in {16, 32, 64, 128, 256} (clamped to the work available) on
+ * the caller's inputs, once untimed and then 3 times between HIP events on `stream`; a
+ * candidate qualifies if its bits agree with the first candidate's to 1e-5 relative.
+ * Synchronises the stream. bits_scratch [5][n_attr] float64 (overwritten); d_attrs, d_w, d_b
+ * as in gs_rate_model (accumulated into; pass the buffers of the calls being tuned, or NULL, so
+ * that the timed work is the same). *best_blocks receives the fastest qualifying value;
+ * times_ms [5] (or NULL) the mean time of each candidate, or -1 for one that disagreed.
+ * Returns GS_ERR_INVALID_ARG as gs_rate_model does, GS_ERR_HIP on a launch or event error. */
+int gs_rate_autotune(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
+                     const float* b_f32, double* bits_scratch, float* d_attrs, float* d_w, float* d_b, void* stream,
+                     int32_t* best_blocks, float* times_ms);
 
 /* Empirical-histogram rate (the judge of the learned rate): per attribute
  * bits = -sum_i log2(count(k_i) / n) = n H over its symbol histogram, in FP64.

@@ -43,7 +43,7 @@ class GsRateDesc(ctypes.Structure):
         ("n", ctypes.c_int32), ("n_attr", ctypes.c_int32), ("step", ctypes.c_float), ("mode", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("offset", ctypes.c_uint64), ("n_levels", ctypes.c_int32),
         ("level_counts", ctypes.c_int32 * 8), ("level_weights", ctypes.c_float * 8), ("lambda_rate", ctypes.c_float),
-        ("fit_scale", ctypes.c_float),
+        ("fit_scale", ctypes.c_float), ("blocks_per_attr", ctypes.c_int32),
     ]
 
 
@@ -69,6 +69,7 @@ SIGNATURES = {
     "gs_kernel_name": ([I32], ctypes.c_char_p),
     "gs_rate_histogram_workspace_size": ([I32, P], ctypes.c_int),
     "gs_rate_model": ([P, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+    "gs_rate_autotune": ([P, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
     "gs_rate_histogram": ([I32, I32, P, ctypes.c_float, P, P, SZ, P], ctypes.c_int),
     "gs_rate_context": ([I32, P, ctypes.c_float, I32, P, P, P], ctypes.c_int),
     "gs_adam_step": ([I64, P, P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,

@@ -12,6 +12,9 @@
 //   k_adam            Adam update of FP32 masters with an optional BF16 copy
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <vector>
+
 #include <stdint.h>
 
 #include <algorithm>
@@ -33,11 +36,12 @@ constexpr int kBPerAttr = kHid + kHid + 2;
 constexpr float kPFloor = 1e-9f;
 constexpr float kLn2 = 0.69314718055994531f;
 
-__device__ __forceinline__ uint16_t f32_to_bf16(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);  // inf / nan unchanged
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
-  return (uint16_t)(u >> 16);
+// FP32 -> BF16, round to nearest even, on the hardware converter (v_cvt_pk_bf16_f32)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t f32_to_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2(float lo, float hi) {
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -187,25 +191,37 @@ __device__ __forceinline__ bf16x8 pack8(const uint16_t* h) {
 __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {  // 16-byte aligned
   return __builtin_bit_cast(bf16x8, *(const uint4*)p);
 }
+// Eight values of a [o][64] matrix column: rows 0..3 and 8..11 from p (row stride 64).
+__device__ __forceinline__ bf16x8 load_col8(const uint16_t* p) {
+  uint32_t u[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r0 = 2 * j < 4 ? 2 * j : 2 * j + 4;
+    u[j] = (uint32_t)p[r0 * kHid] | ((uint32_t)p[(r0 + 1) * kHid] << 16);
+  }
+  return __builtin_bit_cast(bf16x8, make_uint4(u[0], u[1], u[2], u[3]));
+}
 __device__ __forceinline__ bf16x8 load4x2(const uint16_t* p0, const uint16_t* p1) {  // two 8-byte halves
   const uint2 a = *(const uint2*)p0, b = *(const uint2*)p1;
   return __builtin_bit_cast(bf16x8, make_uint4(a.x, a.y, b.x, b.y));
 }
 
-// tanh(u) = 1 - 2 / (1 + e^{2u}) with the hardware exp2 and reciprocal (absolute error ~1e-7,
-// far below the BF16 rounding that follows).
-__device__ __forceinline__ float tanh_fast(float u) {
-  const float e = __builtin_amdgcn_exp2f(u * 2.8853900817779268f);  // e^{2u}
-  return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
+// tanh-approximated GELU, 0.5 x (1 + tanh(u)) with u = c (x + 0.044715 x^3), c = sqrt(2 / pi),
+// evaluated as x * s with s = 0.5 (1 + tanh(u)) = 1 / (1 + e^{-2u}) on the hardware exp2 and
+// reciprocal (absolute error ~1e-7, far below the BF16 rounding that follows).
+constexpr float kGeluC = 0.7978845608028654f;
+constexpr float kGeluE0 = -2.f * kGeluC * 1.4426950408889634f;  // e^{-2u} = 2^{x (E0 + E1 x^2)}
+constexpr float kGeluE1 = kGeluE0 * 0.044715f;
+__device__ __forceinline__ float gelu_s(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * fmaf(x * x, kGeluE1, kGeluE0));
+  return __builtin_amdgcn_rcpf(1.f + e);
 }
-__device__ __forceinline__ float gelu_f(float x) {
-  const float c = 0.7978845608028654f;
-  return 0.5f * x * (1.f + tanh_fast(c * (x + 0.044715f * x * x * x)));
-}
+__device__ __forceinline__ float gelu_f(float x) { return x * gelu_s(x); }
+// d/dx [x s] = s + x s (1 - s) 2 u', with 2 u' = 2 c (1 + 3 * 0.044715 x^2)
 __device__ __forceinline__ float gelu_grad_f(float x) {
-  const float c = 0.7978845608028654f;
-  const float th = tanh_fast(c * (x + 0.044715f * x * x * x));
-  return 0.5f * (1.f + th) + 0.5f * x * (1.f - th * th) * c * (1.f + 3.f * 0.044715f * x * x);
+  const float s = gelu_s(x);
+  const float du2 = fmaf(x * x, 2.f * kGeluC * 3.f * 0.044715f, 2.f * kGeluC);
+  return fmaf(x * du2, fmaf(-s, s, s), s);
 }
 
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
@@ -248,7 +264,6 @@ __device__ __forceinline__ void laplace_bits(float y, float m, float b, float q,
 struct RateShared {
   uint16_t w1[kHid * kCtx];    // [o][f]
   uint16_t w2[kHid * kHid];    // [o2][i]
-  uint16_t w2t[kHid * kHid];   // [i][o2]
   float w3[2 * kHid];
   float b1[kHid], b2[kHid], b3[2];
 };
@@ -258,11 +273,12 @@ struct RateWaveTmp {           // transposed per-wave staging for the weight gra
   uint16_t d2[kHid * 32];      // [o2][s]
   uint16_t d1[kHid * 32];      // [i][s]
   uint16_t x[kCtx * 32];       // [f][s]
-  float dout[2 * 32];          // [r][s]
+  uint16_t dout[2 * 32];       // [r][s], BF16 (the operand of the layer-3 weight gradient)
 };
 
+// Two waves per SIMD (two blocks per CU): at most 256 registers per lane and 80 KB of LDS per block.
 template <bool GRAD>
-__global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __restrict__ attrs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rate_mlp(RateArgs ra, const float* __restrict__ attrs,
                                                   const uint16_t* __restrict__ ctx, const uint16_t* __restrict__ W,
                                                   const float* __restrict__ Bv, double* __restrict__ bits_out,
                                                   double* __restrict__ loss_out, float* __restrict__ sym_bits,
@@ -280,7 +296,6 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
   for (int j = tid; j < kW2; j += 256) {
     const uint16_t v = Wa[kW1 + j];
     sh.w2[j] = v;
-    sh.w2t[(j & 63) * kHid + (j >> 6)] = v;
   }
   for (int j = tid; j < kW3; j += 256) sh.w3[j] = bf16_to_f32(Wa[kW1 + kW2 + j]);
   if (tid < kHid) {
@@ -297,20 +312,19 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
   const int per_iter = gridDim.x * 4;
   const int iters = (nchunks + per_iter - 1) / per_iter;
   float bits_acc = 0.f, loss_acc = 0.f;
-  f32x16 acc2[2][2];
-  f32x4 acc1[4], acc3[4];
-  float db1 = 0.f, db2 = 0.f, db3 = 0.f;
+  // Weight gradients are split over the block's four waves: wave w accumulates rows 16w..16w+15
+  // of dW2 and dW1 and columns 16w..16w+15 of dW3, over the symbols of all four waves (their
+  // staged activations are read from LDS), so each wave holds 24 accumulators instead of 96.
+  f32x4 acc2[4], acc1, acc3;
+  float db1 = 0.f, db2 = 0.f, db30 = 0.f, db31 = 0.f;
   if constexpr (GRAD) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int r = 0; r < 4; ++r) {
 #pragma unroll
-      for (int v = 0; v < 2; ++v)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc2[u][v][r] = 0.f;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) { acc1[u][r] = 0.f; acc3[u][r] = 0.f; }
+      for (int u = 0; u < 4; ++u) acc2[u][r] = 0.f;
+      acc1[r] = 0.f;
+      acc3[r] = 0.f;
+    }
   }
   RateWaveTmp& T = wt[wave];
   const f32x16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -339,12 +353,14 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int o = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
-        const uint16_t hb = f32_to_bf16(gelu_f(c1[h][r] + sh.b1[o]));
-        if constexpr (GRAD) T.h1[o * 32 + sl] = hb;
-        const int ks = 2 * h + (r >> 3), jj = r & 7;
-        b2[ks][jj >> 1] |= (uint32_t)hb << (16 * (jj & 1));
+      for (int r = 0; r < 16; r += 2) {
+        const int o = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o + 1 for r + 1
+        const uint32_t hp = f32x2_to_bf16x2(gelu_f(c1[h][r] + sh.b1[o]), gelu_f(c1[h][r + 1] + sh.b1[o + 1]));
+        if constexpr (GRAD) {
+          T.h1[o * 32 + sl] = (uint16_t)hp;
+          T.h1[(o + 1) * 32 + sl] = (uint16_t)(hp >> 16);
+        }
+        b2[2 * h + (r >> 3)][(r & 7) >> 1] = hp;
       }
     // ---- layer 2: Z2^T (64 x 32) = W2 (64 x 64) H1^T (64 x 32), K in 4 steps of 16
     f32x16 c2[2];
@@ -364,15 +380,20 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float zz = c2[h][r] + sh.b2[o2];
-        c2[h][r] = zz;  // keep Z2 for the backward
-        const uint16_t hb = f32_to_bf16(gelu_f(zz));
-        if constexpr (GRAD) T.h2[o2 * 32 + sl] = hb;
-        const float hf = bf16_to_f32(hb);
-        o0 = fmaf(sh.w3[o2], hf, o0);
-        o1 = fmaf(sh.w3[kHid + o2], hf, o1);
+      for (int r = 0; r < 16; r += 2) {
+        const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o2 + 1 for r + 1
+        const float z0 = c2[h][r] + sh.b2[o2], z1 = c2[h][r + 1] + sh.b2[o2 + 1];
+        c2[h][r] = z0;  // keep Z2 for the backward
+        c2[h][r + 1] = z1;
+        const uint32_t hp = f32x2_to_bf16x2(gelu_f(z0), gelu_f(z1));
+        if constexpr (GRAD) {
+          T.h2[o2 * 32 + sl] = (uint16_t)hp;
+          T.h2[(o2 + 1) * 32 + sl] = (uint16_t)(hp >> 16);
+        }
+        o0 = fmaf(sh.w3[o2], __uint_as_float(hp << 16), o0);
+        o1 = fmaf(sh.w3[kHid + o2], __uint_as_float(hp << 16), o1);
+        o0 = fmaf(sh.w3[o2 + 1], __uint_as_float(hp & 0xFFFF0000u), o0);
+        o1 = fmaf(sh.w3[kHid + o2 + 1], __uint_as_float(hp & 0xFFFF0000u), o1);
       }
     o0 += __shfl_xor(o0, 32);
     o1 += __shfl_xor(o1, 32);
@@ -420,13 +441,14 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
-          const float dh = dout0 * sh.w3[o2] + dout1 * sh.w3[kHid + o2];
-          const uint16_t db = f32_to_bf16(dh * gelu_grad_f(c2[h][r]));
-          T.d2[o2 * 32 + sl] = db;
-          const int ks = 2 * h + (r >> 3), jj = r & 7;
-          bd[ks][jj >> 1] |= (uint32_t)db << (16 * (jj & 1));
+        for (int r = 0; r < 16; r += 2) {
+          const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o2 + 1 for r + 1
+          const float dh0 = dout0 * sh.w3[o2] + dout1 * sh.w3[kHid + o2];
+          const float dh1 = dout0 * sh.w3[o2 + 1] + dout1 * sh.w3[kHid + o2 + 1];
+          const uint32_t dp = f32x2_to_bf16x2(dh0 * gelu_grad_f(c2[h][r]), dh1 * gelu_grad_f(c2[h][r + 1]));
+          T.d2[o2 * 32 + sl] = (uint16_t)dp;
+          T.d2[(o2 + 1) * 32 + sl] = (uint16_t)(dp >> 16);
+          bd[2 * h + (r >> 3)][(r & 7) >> 1] = dp;
         }
       f32x16 c3[2];
 #pragma unroll
@@ -434,9 +456,10 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
         c3[hi] = zero16;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-          const uint16_t* row = &sh.w2t[(32 * hi + sl) * kHid + 16 * ks + 4 * g];
+          // W2^T rows i, K = o2 in the order 16 ks + 4 g + {0..3, 8..11}: a column of W2
+          const uint16_t* col = &sh.w2[(16 * ks + 4 * g) * kHid + 32 * hi + sl];
           c3[hi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              load4x2(row, row + 8),
+              load_col8(col),
               __builtin_bit_cast(bf16x8, make_uint4(bd[ks][0], bd[ks][1], bd[ks][2], bd[ks][3])), c3[hi], 0, 0, 0);
         }
       }
@@ -448,9 +471,12 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int u = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
-          T.d1[u * 32 + sl] = f32_to_bf16(c3[h][r] * gelu_grad_f(c1[h][r] + sh.b1[u]));
+        for (int r = 0; r < 16; r += 2) {
+          const int u = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // u + 1 for r + 1
+          const uint32_t dp = f32x2_to_bf16x2(c3[h][r] * gelu_grad_f(c1[h][r] + sh.b1[u]),
+                                              c3[h][r + 1] * gelu_grad_f(c1[h][r + 1] + sh.b1[u + 1]));
+          T.d1[u * 32 + sl] = (uint16_t)dp;
+          T.d1[(u + 1) * 32 + sl] = (uint16_t)(dp >> 16);
         }
       {
         const uint4 xv = __builtin_bit_cast(uint4, bx);
@@ -459,42 +485,12 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
         for (int j = 0; j < 8; ++j) T.x[(8 * g + j) * 32 + sl] = (uint16_t)(xs[j >> 1] >> (16 * (j & 1)));
       }
       if (g == 0) {
-        T.dout[sl] = dout0;
-        T.dout[32 + sl] = dout1;
+        T.dout[sl] = f32_to_bf16(dout0);
+        T.dout[32 + sl] = f32_to_bf16(dout1);
+        db30 += dout0;
+        db31 += dout1;
       }
-      __syncthreads();
-      // dW2 (64 x 64) += dZ2^T (64 x 32 symbols) H1 (32 x 64)
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const bf16x8 av = load8(&T.d2[(32 * h + sl) * 32 + 16 * kk + 8 * g]);
-#pragma unroll
-          for (int h2 = 0; h2 < 2; ++h2)
-            acc2[h][h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                av, load8(&T.h1[(32 * h2 + sl) * 32 + 16 * kk + 8 * g]), acc2[h][h2], 0, 0, 0);
-        }
-      // dW1 (64 x 16) += dZ1^T (64 x 32) X (32 x 16): v_mfma_f32_16x16x32_bf16, lane l holds row/col (l & 15)
-      const int r16 = lane & 15, g16 = lane >> 4;
-      const bf16x8 bxT = load8(&T.x[r16 * 32 + 8 * g16]);
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-        acc1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(&T.d1[(16 * mt + r16) * 32 + 8 * g16]), bxT,
-                                                            acc1[mt], 0, 0, 0);
-      // dW3 (2 x 64) += dout^T (2 x 32) H2 (32 x 64), rows padded to 16
-      uint32_t dv[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float lo = r16 < 2 ? T.dout[r16 * 32 + 8 * g16 + 2 * j] : 0.f;
-        const float hi = r16 < 2 ? T.dout[r16 * 32 + 8 * g16 + 2 * j + 1] : 0.f;
-        dv[j] = (uint32_t)f32_to_bf16(lo) | ((uint32_t)f32_to_bf16(hi) << 16);
-      }
-      const bf16x8 ad = __builtin_bit_cast(bf16x8, make_uint4(dv[0], dv[1], dv[2], dv[3]));
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-        acc3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, load8(&T.h2[(16 * nt + r16) * 32 + 8 * g16]), acc3[nt],
-                                                            0, 0, 0);
-      // bias gradients: row sums over the 32 symbols
+      // bias gradients of this wave's symbols: row sums (lane = row) over its 32 symbols
       {
         float s1 = 0.f, s2 = 0.f;
 #pragma unroll
@@ -511,10 +507,29 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
         }
         db1 += s1;
         db2 += s2;
-        if (lane < 2) {
-          float s3 = 0.f;
-          for (int j = 0; j < 32; ++j) s3 += T.dout[lane * 32 + j];
-          db3 += s3;
+      }
+      __syncthreads();
+      // This wave's slices of the weight gradients over the 4 x 32 symbols of the block
+      // (v_mfma_f32_16x16x32_bf16: lane l holds A row / B column l & 15 and K slots 8 (l >> 4) ..).
+      //   dW2 rows 16w.. (16 x 64) += dZ2^T (16 x 32 s) H1 (32 s x 64)
+      //   dW1 rows 16w.. (16 x 16) += dZ1^T (16 x 32 s) X (32 s x 16)
+      //   dW3 columns 16w.. (2 x 16, rows padded to 16) += dout^T (2 x 32 s) H2 (32 s x 16)
+      {
+        const int r16 = lane & 15, g16 = lane >> 4;
+        const int row = 16 * wave + r16;
+#pragma unroll
+        for (int src = 0; src < 4; ++src) {
+          const RateWaveTmp& S = wt[src];
+          const bf16x8 a2 = load8(&S.d2[row * 32 + 8 * g16]);
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt)
+            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, load8(&S.h1[(16 * nt + r16) * 32 + 8 * g16]),
+                                                                acc2[nt], 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(&S.d1[row * 32 + 8 * g16]),
+                                                          load8(&S.x[r16 * 32 + 8 * g16]), acc1, 0, 0, 0);
+          const bf16x8 ad = r16 < 2 ? load8(&S.dout[r16 * 32 + 8 * g16])
+                                    : __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+          acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, load8(&S.h2[row * 32 + 8 * g16]), acc3, 0, 0, 0);
         }
       }
       __syncthreads();
@@ -539,37 +554,33 @@ __global__ __launch_bounds__(256) void k_rate_mlp(RateArgs ra, const float* __re
     if (loss_out) atomicAdd(loss_out, (double)lsum);
   }
   if constexpr (GRAD) {
-    // sum the four waves' weight gradients in LDS (reusing the staging area), then one atomic per value
+    // the waves' slices are disjoint; the bias sums of the four waves are added in LDS (reusing
+    // the staging area), then one atomic per value
     float* acc = (float*)wt;
     for (int j = tid; j < kWPerAttr + kBPerAttr; j += 256) acc[j] = 0.f;
     __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int h2 = 0; h2 < 2; ++h2)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
-          const int i = 32 * h2 + sl;
-          atomicAdd(&acc[kW1 + o2 * kHid + i], acc2[h][h2][r]);
-        }
     {
       const int r16 = lane & 15, g16 = lane >> 4;
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
+      for (int r = 0; r < 4; ++r) {
+        const int o = 16 * wave + 4 * g16 + r;  // output row of this accumulator value
 #pragma unroll
-        for (int r = 0; r < 4; ++r) atomicAdd(&acc[(16 * mt + 4 * g16 + r) * kCtx + r16], acc1[mt][r]);
+        for (int nt = 0; nt < 4; ++nt) acc[kW1 + o * kHid + 16 * nt + r16] = acc2[nt][r];
+        acc[o * kCtx + r16] = acc1[r];
+        if (4 * g16 + r < 2) acc[kW1 + kW2 + (4 * g16 + r) * kHid + 16 * wave + r16] = acc3[r];
+      }
+    }
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 4 * g16 + r;
-          if (row < 2) atomicAdd(&acc[kW1 + kW2 + row * kHid + 16 * nt + r16], acc3[nt][r]);
-        }
+    for (int off = 32; off > 0; off >>= 1) {
+      db30 += __shfl_xor(db30, off);
+      db31 += __shfl_xor(db31, off);
     }
     atomicAdd(&acc[kWPerAttr + lane], db1);
     atomicAdd(&acc[kWPerAttr + kHid + lane], db2);
-    if (lane < 2) atomicAdd(&acc[kWPerAttr + 2 * kHid + lane], db3);
+    if (lane == 0) {
+      atomicAdd(&acc[kWPerAttr + 2 * kHid], db30);
+      atomicAdd(&acc[kWPerAttr + 2 * kHid + 1], db31);
+    }
     __syncthreads();
     if (d_w)
       for (int j = tid; j < kWPerAttr; j += 256)
@@ -681,7 +692,7 @@ int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* 
   }
   const bool grad = d_w || d_b;
   const int nchunks = (d.n + 31) / 32;
-  const int nb = std::max(1, std::min(64, (nchunks + 3) / 4));
+  const int nb = std::max(1, std::min(d.blocks_per_attr > 0 ? d.blocks_per_attr : 64, (nchunks + 3) / 4));
   const size_t shared = (sizeof(RateShared) + 15) & ~(size_t)15;
   const size_t lds = grad ? shared + 4 * sizeof(RateWaveTmp) : shared;
   hipStream_t st = (hipStream_t)stream;
@@ -709,3 +720,58 @@ int gs_adam_step(int64_t n, float* params, float* grads, float* m, float* v, uin
 }
 
 }  // extern "C"
+
+int gs_rate_autotune(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
+                     const float* b_f32, double* bits_scratch, float* d_attrs, float* d_w, float* d_b, void* stream,
+                     int32_t* best_blocks, float* times_ms) {
+  constexpr int kCand = 5;
+  static const int32_t cand[kCand] = {16, 32, 64, 128, 256};
+  if (!desc || !bits_scratch || !best_blocks) return GS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int A = desc->n_attr;
+  if (A < 1) return GS_ERR_INVALID_ARG;
+  std::vector<double> ref(A), got(A);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return GS_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return GS_ERR_HIP;
+  }
+  int rc = GS_OK;
+  float best_t = -1.f;
+  int32_t best = 0;
+  for (int c = 0; c < kCand && rc == GS_OK; ++c) {
+    gs_rate_desc dc = *desc;
+    dc.blocks_per_attr = cand[c];
+    double* bits = bits_scratch + (size_t)c * A;
+    if (hipMemsetAsync(bits, 0, sizeof(double) * A, st) != hipSuccess) { rc = GS_ERR_HIP; break; }
+    rc = gs_rate_model(&dc, attrs, ctx, w_bf16, b_f32, bits, nullptr, nullptr, d_attrs, d_w, d_b, stream);
+    if (rc != GS_OK) break;
+    if (hipMemcpyAsync(got.data(), bits, sizeof(double) * A, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) { rc = GS_ERR_HIP; break; }
+    bool agree = true;
+    if (c == 0) {
+      ref = got;
+    } else {
+      for (int a = 0; a < A; ++a)
+        if (!(std::fabs(got[a] - ref[a]) <= 1e-5 * std::fabs(ref[a]) + 1e-6)) agree = false;
+    }
+    if (hipEventRecord(e0, st) != hipSuccess) { rc = GS_ERR_HIP; break; }
+    for (int r = 0; r < 3 && rc == GS_OK; ++r)
+      rc = gs_rate_model(&dc, attrs, ctx, w_bf16, b_f32, bits, nullptr, nullptr, d_attrs, d_w, d_b, stream);
+    if (rc != GS_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = GS_ERR_HIP; break; }
+    ms /= 3.f;
+    if (times_ms) times_ms[c] = agree ? ms : -1.f;
+    if (agree && (best_t < 0.f || ms < best_t)) {
+      best_t = ms;
+      best = cand[c];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == GS_OK) *best_blocks = best;
+  return rc;
+}

@@ -769,19 +769,20 @@ __device__ __forceinline__ int wave_max_i(int v) {
 
 // Level 1: rows. Each wave walks kBinChunk depth-sorted Gaussians of one
 // frame-view, 64 at a time with one Gaussian per lane. A lane evaluates the
-// first kRowPre tile rows of its Gaussian up front; the wave then visits the
-// tile rows the batch reaches, and per row a ballot ranks the hitting lanes,
-// so the entries of a row keep the depth order of the batch (a stable counting
-// sort; the per-row counters live in LDS). Gaussians taller than kRowPre rows
-// evaluate their further rows inside the row loop. An entry is (Gaussian
-// index, tile-column range in the row).
+// first kRowPre tile rows of its Gaussian up front (column ranges kept in
+// LDS); the wave then visits the tile rows the batch reaches, and per row a
+// ballot ranks the hitting lanes, so the entries of a row keep the depth order
+// of the batch (a stable counting sort; the per-row counters live in LDS).
+// Gaussians taller than kRowPre rows evaluate their further rows inside the
+// row loop. An entry is (Gaussian index, tile-column range in the row).
 template <bool EMIT>
 __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ svals, const float4* __restrict__ brec,
                                                 uint32_t* __restrict__ hist, const uint2* __restrict__ row_ranges,
                                                 uint2* __restrict__ row_lists) {
-  constexpr int kRowPre = 4;
+  constexpr int kRowPre = 8;
   extern __shared__ uint32_t cnt[];
+  __shared__ uint32_t s_pk[64][kRowPre + 1];  // per lane: packed column ranges of its first rows
   const int lane = threadIdx.x;
   const int b = blockIdx.y, chunk = blockIdx.x;
   const int TY = d.TY;
@@ -811,13 +812,13 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
       }
     }
     if (__ballot(ok) == 0ull) break;  // culled keys sort last
-    uint32_t hm = 0, pk[kRowPre];
+    uint32_t hm = 0;
 #pragma unroll
     for (int r = 0; r < kRowPre; ++r) {
       int txl = 0, txh = 0;
       const bool h = ok && y0 + r <= y1 && el.row(d, y0 + r, x0, x1, txl, txh);
       hm |= h ? 1u << r : 0u;
-      pk[r] = h ? ((uint32_t)txl | ((uint32_t)txh << 16)) : 0u;
+      s_pk[lane][r] = (uint32_t)txl | ((uint32_t)txh << 16);
     }
     const bool tall = ok && y1 - y0 >= kRowPre;
     int ylo = hm ? y0 + __builtin_ctz(hm) : 0x7FFFFFFF;
@@ -832,7 +833,7 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
     for (int ty = ylo; ty <= yhi; ++ty) {
       const uint32_t r = (uint32_t)(ty - y0);
       bool hit = r < (uint32_t)kRowPre && ((hm >> r) & 1u);
-      uint32_t rg = r == 0 ? pk[0] : r == 1 ? pk[1] : r == 2 ? pk[2] : pk[3];
+      uint32_t rg = s_pk[lane][min(r, (uint32_t)kRowPre - 1u)];
       if (any_tall) {
         int txl = 0, txh = 0;
         if (tall && r >= (uint32_t)kRowPre && ty <= y1 && el.row(d, ty, x0, x1, txl, txh)) {
@@ -1148,19 +1149,22 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
   TileCtx c;
   if (!tile_ctx(d, ranges, c)) return;
   __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
-  __shared__ float4 s_b[kTilePix];  // scaled conic a2, b2, c2, (first layer | quadrant mask << 8) bits
+  __shared__ float4 s_b[kTilePix];  // scaled conic a2, b2, c2, first layer bits
   __shared__ float4 s_c[kTilePix];  // r, g, b, list position bits
-  __shared__ uint8_t s_idx[kTilePix / 64][kTilePix];  // per wave: the staged entries it needs, in order
   __shared__ uint32_t s_wcnt[kTilePix / 64];
   __shared__ uint32_t s_hi;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const uint32_t qbit = 1u << (8 + wv);
   const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
+  // Tr[l] > 0: open layer and its transmittance; a closed layer keeps -T (its final
+  // transmittance, negated), so that T (1 - alpha) < t_stop rejects it with no extra test
   float Tr[MAXL], Cr[MAXL], Cg[MAXL], Cb[MAXL];
   uint32_t last[MAXL];
-#pragma unroll
-  for (int l = 0; l < MAXL; ++l) { Tr[l] = 1.f; Cr[l] = Cg[l] = Cb[l] = 0.f; last[l] = 0; }
   uint32_t alive = c.inside ? ((1u << d.L) - 1u) : 0u;
+#pragma unroll
+  for (int l = 0; l < MAXL; ++l) {
+    Tr[l] = ((alive >> l) & 1u) ? 1.f : -1.f;
+    Cr[l] = Cg[l] = Cb[l] = 0.f;
+    last[l] = 0;
+  }
   uint32_t nlhi = alive ? (uint32_t)d.lv[d.L - 1] : 0u;
   const size_t recbase = (size_t)c.b * d.n;
   const int t = threadIdx.x;
@@ -1181,48 +1185,37 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
     if (gi < hib) {
       const float4* r = rec + 3 * (recbase + gi);
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      const uint32_t qm = quad_mask(d, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, c.ox, c.oy);
       s_a[slot] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
       s_b[slot] = make_float4(-0.5f * kLog2e * r0.z, -kLog2e * r0.w, -0.5f * kLog2e * r1.x,
-                              __uint_as_float(first_layer(d, gi) | (qm << 8)));
+                              __uint_as_float(first_layer(d, gi)));
       s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k - c.range.x + 1));
     }
     __syncthreads();
-    // this wave's list: staged entries whose ellipse reaches its quadrant, below the highest open
-    // layer bound of its own pixels (wave-private LDS, written and read in order by the wave)
-    const uint32_t hw = wave_max_u(nlhi);
-    int cw = 0;
-    if (hw) {
-      for (int q = 0; q < cnt; q += 64) {
-        const int e = q + lane;
-        const bool keep =
-            e < cnt && (__float_as_uint(s_b[e].w) & qbit) && __float_as_uint(s_a[e].w) < hw;
-        const unsigned long long m = __ballot(keep);
-        if (keep) s_idx[wv][cw + (int)popc_below(m)] = (uint8_t)e;
-        cw += (int)__popcll(m);
-      }
-    }
+    // every wave walks all staged entries: a per-wave quadrant/open-layer list was measured to cost
+    // more (list building, a dependent LDS read per entry) than the evaluations it saves here
     if (alive) {
-      for (int j = 0; j < cw; ++j) {
-        const int e = s_idx[wv][j];
+      for (int e = 0; e < cnt; ++e) {
         const float4 a = s_a[e];
         if (__float_as_uint(a.w) >= nlhi) continue;
         const float4 cb = s_b[e];
         const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
         ++n_eval;
         if (!(ev.ga >= d.alpha_min)) continue;
-        const float al = fminf(d.alpha_max, ev.ga);
+        const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
         const float oma = 1.f - al;
         const float4 col = s_c[e];
         const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
         bool died = false;
 #pragma unroll
         for (int l = 0; l < MAXL; ++l) {
-          if ((uint32_t)l < lmin || !((alive >> l) & 1u)) continue;
+          if ((uint32_t)l < lmin) continue;  // uniform
           const float Tn = Tr[l] * oma;
-          if (Tn < d.t_stop) {
-            alive &= ~(1u << l);
-            died = true;
+          if (!(Tn >= d.t_stop)) {
+            if (Tr[l] > 0.f) {  // this Gaussian would take the layer below the floor: close it
+              Tr[l] = -Tr[l];
+              alive &= ~(1u << l);
+              died = true;
+            }
             continue;
           }
           const float wgt = al * Tr[l];
@@ -1253,10 +1246,11 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
   for (int l = 0; l < MAXL; ++l) {
     if (l >= d.L) break;
     const size_t o = (size_t)c.b * d.L + l;
-    image[(o * 3 + 0) * HW + pix] = fmaf(Tr[l], d.bg[0], Cr[l]);
-    image[(o * 3 + 1) * HW + pix] = fmaf(Tr[l], d.bg[1], Cg[l]);
-    image[(o * 3 + 2) * HW + pix] = fmaf(Tr[l], d.bg[2], Cb[l]);
-    t_final[o * HW + pix] = Tr[l];
+    const float T = fabsf(Tr[l]);
+    image[(o * 3 + 0) * HW + pix] = fmaf(T, d.bg[0], Cr[l]);
+    image[(o * 3 + 1) * HW + pix] = fmaf(T, d.bg[1], Cg[l]);
+    image[(o * 3 + 2) * HW + pix] = fmaf(T, d.bg[2], Cb[l]);
+    t_final[o * HW + pix] = T;
     n_last[o * HW + pix] = last[l];
   }
 }
@@ -1450,17 +1444,16 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       const float4 col = s_c[j];
       const uint32_t kk = __float_as_uint(col.w);
       const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
+      // some lane of the wave is a candidate (the list holds no other entries); straight-line
+      // code from here on (lanes that are not candidates compute and discard), so that the
+      // accumulators below need no copies at control-flow joins
       bool cand = false;
 #pragma unroll
       for (int l = 0; l < MAXL; ++l) cand = cand || ((uint32_t)l >= lmin && kk < last[l]);
-      if (__ballot(cand) == 0ull) continue;
-      // straight-line code from here on (lanes that are not candidates compute and discard),
-      // so that the accumulators below need no copies at control-flow joins
       const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
       n_eval += cand ? 1u : 0u;
       const bool hit = cand && ev.ga >= d.alpha_min;
-      if (__ballot(hit) == 0ull) continue;
-      const float al = fminf(d.alpha_max, ev.ga);
+      const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
       const float oma = 1.f - al;
       const float ioma = __builtin_amdgcn_rcpf(oma);
       float g[9];

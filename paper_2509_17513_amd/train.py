@@ -101,6 +101,7 @@ class RateModel:
         self.bits = torch.zeros(n_attr, dtype=torch.float64, device=device)
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
         self.t = 0
+        self.blocks = 0  # launch blocks per attribute; 0 = library default (see autotune)
 
     def desc(self, n, mode, level_counts, level_weights, lambda_rate, seed=0, offset=0, fit_scale=None):
         d = _lib.GsRateDesc()
@@ -111,6 +112,7 @@ class RateModel:
             d.level_weights[i] = float(level_weights[i])
         d.lambda_rate = lambda_rate
         d.fit_scale = (1.0 / max(n, 1)) if fit_scale is None else fit_scale
+        d.blocks_per_attr = self.blocks
         return d
 
     def run(self, attrs_ptr, n, ctx, mode, level_counts, level_weights, lambda_rate=0.0, seed=0, offset=0,
@@ -120,6 +122,22 @@ class RateModel:
         check(lib().gs_rate_model(ctypes.byref(d), attrs_ptr, _p(ctx), _p(self.w16), _p(self.b), _p(self.bits),
                                   _p(self.loss), _p(sym_bits), d_attrs_ptr, _p(self.dw) if grads else None,
                                   _p(self.db) if grads else None, _s(self.w.device)), "gs_rate_model")
+
+    def autotune(self, attrs_ptr, n, ctx, mode, level_counts, level_weights, lambda_rate=0.0, d_attrs_ptr=None,
+                 grads=True):
+        """Picks the launch shape (blocks per attribute) for this workload with gs_rate_autotune; the
+        gradient buffers used for the timed calls are zeroed afterwards. Returns (blocks, times_ms)."""
+        d = self.desc(n, mode, level_counts, level_weights, lambda_rate)
+        scratch = torch.zeros((5, self.n_attr), dtype=torch.float64, device=self.w.device)
+        best = ctypes.c_int32()
+        times = (ctypes.c_float * 5)()
+        check(lib().gs_rate_autotune(ctypes.byref(d), attrs_ptr, _p(ctx), _p(self.w16), _p(self.b), _p(scratch),
+                                     d_attrs_ptr, _p(self.dw) if grads else None, _p(self.db) if grads else None,
+                                     _s(self.w.device), ctypes.byref(best), times), "gs_rate_autotune")
+        zero(self.dw)
+        zero(self.db)
+        self.blocks = int(best.value)
+        return self.blocks, list(times)
 
     def reset(self):
         zero(self.bits)

@@ -165,6 +165,46 @@ def test_mlp_train_gradients_match_oracle():
             np.testing.assert_allclose(np.linalg.norm(x[a]), np.linalg.norm(r[a]), rtol=2e-2)
 
 
+def test_rate_autotune_picks_an_agreeing_launch_shape():
+    _case("rate autotuner: candidates agree, tuned launch equals the default")
+    L = _lib()
+    n, A = 200_000, 4
+    attrs, ctx, wbits, bf, lv = _mlp_inputs(n, A, 79)
+    lw = [0.5, 0.25, 1.0]
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(attrs).to(dev)
+    c = torch.from_numpy(np.ascontiguousarray(rate.f64_to_bf16_bits(ctx.T))).to(dev)
+    w = torch.from_numpy(wbits.view(np.int16)).to(dev)
+    b = torch.from_numpy(bf.astype(np.float32)).to(dev)
+    scratch = torch.zeros((5, A), dtype=torch.float64, device=dev)
+    da = torch.zeros_like(a)
+    dw = torch.zeros((A, rate.W_PER_ATTR), dtype=torch.float32, device=dev)
+    db = torch.zeros((A, rate.B_PER_ATTR), dtype=torch.float32, device=dev)
+    best = ctypes.c_int32()
+    times = (ctypes.c_float * 5)()
+    d = _desc(n, A, 1, lv, lw, 1.0, seed=5)
+    L.check(L.lib().gs_rate_autotune(ctypes.byref(d), _p(a), _p(c), _p(w), _p(b), _p(scratch), _p(da), _p(dw),
+                                     _p(db), _stream(), ctypes.byref(best), times), "gs_rate_autotune")
+    t = list(times)
+    print(f"best={best.value} times={t}")
+    assert best.value in (16, 32, 64, 128, 256)
+    assert all(x > 0 for x in t)  # every launch shape gives the same bits
+    assert t[(16, 32, 64, 128, 256).index(best.value)] == min(t)
+    sb = scratch.cpu().numpy()
+    np.testing.assert_allclose(sb, np.broadcast_to(sb[0], sb.shape), rtol=1e-5)
+    outs = []
+    for blocks in (0, best.value):
+        bits = torch.zeros(A, dtype=torch.float64, device=dev)
+        gw = torch.zeros_like(dw)
+        d.blocks_per_attr = blocks
+        L.check(L.lib().gs_rate_model(ctypes.byref(d), _p(a), _p(c), _p(w), _p(b), _p(bits), None, None, None,
+                                      _p(gw), None, _stream()), "gs_rate_model")
+        torch.cuda.synchronize()
+        outs.append((bits.cpu().numpy(), gw.cpu().numpy()))
+    np.testing.assert_allclose(outs[1][0], outs[0][0], rtol=1e-5)
+    np.testing.assert_allclose(outs[1][1], outs[0][1], rtol=1e-3, atol=1e-4 * np.abs(outs[0][1]).max())
+
+
 def test_adam_step_matches_reference():
     _case("Adam")
     L = _lib()

@@ -190,6 +190,72 @@ def test_backward_l1_matches_oracle_ring():
     assert bad <= 1e-3 * dp.numel()
 
 
+def _extreme_scene(seed=77, w=100, h=150):
+    """Degenerate and extreme Gaussians around 150 ordinary ones, identity camera, SH 0:
+    behind the camera and on the near plane, off screen, one Gaussian covering the whole image
+    (taller than the rows the binning evaluates up front), sub-pixel ones, needles, and ones
+    straddling the image border."""
+    rng = np.random.default_rng(seed)
+    f = float(w)
+    rows = []
+
+    def add(mu, log_s, q, logit, rgb):
+        rows.append(np.concatenate([mu, log_s, q, [logit], rgb]).astype(np.float32))
+
+    add([0.05, -0.1, 3.0], [np.log(1.2)] * 3, [1, 0, 0, 0], -0.5, [0.6, 0.3, 0.2])  # whole image
+    for z in (-1.0, 0.1, 0.2):  # behind the camera / at the near plane
+        add([0.0, 0.0, z], [np.log(0.3)] * 3, [1, 0, 0, 0], 2.0, [1, 0, 0])
+    for x, y in ((40.0, 0.0), (0.0, -40.0), (-9.0, 9.0)):  # far off screen
+        add([x, y, 3.0], [np.log(0.1)] * 3, [1, 0, 0, 0], 2.0, [0, 1, 0])
+    for _ in range(6):  # sub-pixel
+        add([rng.uniform(-0.4, 0.4), rng.uniform(-0.6, 0.6), rng.uniform(2, 4)], [np.log(0.002)] * 3,
+            [1, 0, 0, 0], 3.0, rng.uniform(0, 1, 3))
+    for ang in (0.3, 1.1, 2.0):  # needles, rotated about the view axis
+        add([rng.uniform(-0.3, 0.3), rng.uniform(-0.5, 0.5), 3.0], [np.log(0.4), np.log(0.004), np.log(0.004)],
+            [np.cos(ang / 2), 0, 0, np.sin(ang / 2)], 1.5, rng.uniform(0, 1, 3))
+    for u, v in ((-3.0, 75.0), (w + 2.0, 20.0), (50.0, -4.0), (30.0, h + 3.0), (-2.0, -2.0)):  # border
+        z = 3.0
+        add([(u - w / 2) * z / f, (v - h / 2) * z / f, z], [np.log(0.05)] * 3, [1, 0, 0, 0], 1.0,
+            rng.uniform(0, 1, 3))
+    base = synth.cube_scene(150, seed, 0)
+    p = np.concatenate([np.stack(rows, axis=1), base[:, :]], axis=1)
+    # push the ordinary ones in front of the identity camera
+    p[2, len(rows):] = 2.0 + 2.0 * (p[2, len(rows):] + 1.0)
+    p = np.ascontiguousarray(p.astype(np.float32))
+    n = p.shape[1]
+    cams = synth.identity_camera(w, h, f)[None]
+    lv, lw = [12, n], [0.5, 1.0]
+    tgt = synth.target_images(1, w, h, seed + 1)
+    return synth.Workload("extreme", p, cams, w, h, 0, lv, lw, target=tgt)
+
+
+def test_degenerate_and_extreme_gaussians_match_oracle():
+    _case("culled, whole-image, sub-pixel, needle and border Gaussians, 100x150, 2 layers: fwd + bwd")
+    from paper_2509_17513_amd import render_backward
+    w = _extreme_scene()
+    img, ws, (p, c, r, st) = _gpu_forward(w)
+    ost = oracle_settings(w)
+    ref = oracle.render(ost, w.params, w.cams, variants=True)
+    bad, amb, excl, err = image_mismatch(_flat(img), ref)
+    print(f"bad={bad} ambiguous={amb} excluded={excl} max_err={err:.3g}")
+    assert bad == 0
+    dimg = l1_dimage(ref, w.target, w.level_weights)
+    dp_ref, _, _ = oracle.backward(ost, w.params, w.cams, dimg)
+    d_image = torch.from_numpy(dimg.astype(np.float32).reshape(img.shape)).to(p.device)
+    dp, _ = render_backward(st, p, c, ws, image=img, d_image=d_image)
+    torch.cuda.synchronize()
+    got = dp.cpu().numpy().astype(np.float64)
+    assert np.all(got[:, 1:7] == 0.0)  # culled Gaussians get no gradient
+    bad, worst = grad_mismatch(got, dp_ref, param_groups(0))
+    print(f"grad bad={bad} of {dp.numel()} worst_ratio={worst:.3g}")
+    for lo, hi in param_groups(0):  # name the values outside the bar
+        r = dp_ref[lo:hi]
+        rms = np.sqrt(np.mean(r ** 2))
+        for ch, i in zip(*np.nonzero(np.abs(got[lo:hi] - r) > 1e-3 * np.abs(r) + 1e-3 * rms)):
+            print(f"  channel {lo + ch} Gaussian {i}: gpu {got[lo + ch, i]:.6g} oracle {r[ch, i]:.6g}")
+    assert bad <= 1e-3 * dp.numel()
+
+
 def test_backward_fused_target_equals_dimage_path():
     _case("fused L1 target gradient == explicit d_image gradient (GPU vs GPU, same image)")
     from paper_2509_17513_amd import render_backward
