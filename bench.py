@@ -14,6 +14,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -123,7 +124,7 @@ MLP_FLOP_BWD = 2 * (128 + 128 + 64 * 64 + 64 * 64 + 64 * 16)       # weight and 
 BF16_PEAK_FLOPS = 2.5e15
 
 
-def bench_rate(torch, dev, L, steps, n=1_000_000):
+def bench_rate(torch, dev, L, steps, n=1_000_000, tune=True):
     """Learned rate at 1M Gaussians x 56 attributes: train-mode forward + backward of the
     per-attribute MLP (BF16 MFMA) and the histogram judge, timed with HIP events per kernel."""
     import ctypes
@@ -144,8 +145,10 @@ def bench_rate(torch, dev, L, steps, n=1_000_000):
         rm.reset()
         rm.run(attrs, n, ctx, 1, lv, lw, 1e-3, seed=1, offset=0, d_attrs_ptr=ctypes.c_void_p(da.data_ptr()))
 
-    blocks, cand_ms = rm.autotune(attrs, n, ctx, 1, lv, lw, 1e-3, d_attrs_ptr=ctypes.c_void_p(da.data_ptr()))
-    da.zero_()
+    blocks, cand_ms = 0, None
+    if tune:
+        blocks, cand_ms = rm.autotune(attrs, n, ctx, 1, lv, lw, 1e-3, d_attrs_ptr=ctypes.c_void_p(da.data_ptr()))
+        da.zero_()
     one()
     histogram_bits(p[3:59])
     torch.cuda.synchronize()
@@ -168,7 +171,7 @@ def bench_rate(torch, dev, L, steps, n=1_000_000):
             "histogram_ms": hist_ms, "histogram_GB/s": n * 56 * 4 * 2 / (hist_ms * 1e-3) / 1e9,
             "mlp_bits": float(rm.bits.sum().item()), "hist_bits": float(hb.sum().item()),
             "kernels_ms": times, "autotune": {"blocks_per_attr": blocks,
-                                               "candidates": dict(zip((16, 32, 64, 128, 256), cand_ms))}}
+                                               "candidates": dict(zip((16, 32, 64, 128, 256), cand_ms or ()))}}
 
 
 def bench_group(torch, dev, steps):
@@ -251,6 +254,8 @@ def main():
     ap.add_argument("--views", type=int, default=24)
     ap.add_argument("--no-rate", action="store_true", help="skip the learned-rate measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the group and training-step measurements")
+    ap.add_argument("--no-autotune", action="store_true", help="no autotuning: default shapes or --shapes")
+    ap.add_argument("--shapes", default="", help="launch shapes bin_chunk,row_seg,wave_layout (with --no-autotune)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -284,6 +289,17 @@ def main():
 
     log("[bench] sizing workspace")
     img, ws = render_forward(st, p, c, ws=Workspace(st, w.n, 1, B, dev, pair_capacity=40 * w.n * B))
+    tune = None
+    if args.shapes:
+        bc, rs, wl = (int(x) for x in args.shapes.split(","))
+        st = dataclasses.replace(st, bin_chunk=bc, row_seg=rs, wave_layout=wl)
+        tune = {"bin_chunk": bc, "row_seg": rs, "wave_layout": wl, "trial_ms": None}
+    if not args.no_autotune:
+        from paper_2509_17513_amd import autotune
+        st, tune_ms = autotune(st, p, c, ws, image=img)
+        tune = {"bin_chunk": st.bin_chunk, "row_seg": st.row_seg, "wave_layout": st.wave_layout,
+                "trial_ms": tune_ms}
+        log(f"[bench] autotuned launch shapes {tune}")
 
     def step():
         render_forward(st, p, c, ws=ws, image=img, check_overflow=False)
@@ -398,6 +414,7 @@ def main():
                    "sh_degree": w.sh_degree, "levels": list(w.level_counts), "pairs": pairs,
                    "loss": "sum_l lambda^l mean L1 vs uniform-noise targets"},
         "roofline": roof,
+        "autotune": tune,
         "step_hbm": step_hbm,
         "hbm_kernels": hbm_kernels,
         "kernels": kernels,
@@ -409,7 +426,8 @@ def main():
         lvl = []
         for li, nl in enumerate(w.level_counts):
             pl = p[:, :nl].contiguous()
-            stl = RenderSettings(w.width, w.height, w.sh_degree, (nl,), (w.level_weights[li],))
+            stl = RenderSettings(w.width, w.height, w.sh_degree, (nl,), (w.level_weights[li],),
+                                 bin_chunk=st.bin_chunk, row_seg=st.row_seg, wave_layout=st.wave_layout)
             imgl, wsl = render_forward(stl, pl, c[0:1].contiguous(),
                                        ws=Workspace(stl, nl, 1, 1, dev, pair_capacity=60 * nl))
             for v in range(B):  # size each layer's workspace for its worst view
@@ -440,7 +458,7 @@ def main():
             f"{ms_pv / ms_step:.2f}x")
 
     if not args.no_rate:
-        out["rate"] = bench_rate(torch, dev, L, args.steps)
+        out["rate"] = bench_rate(torch, dev, L, args.steps, tune=not args.no_autotune)
     if not args.no_extra:
         log("[bench] 4D group and joint training step")
         del ws, img

@@ -68,7 +68,14 @@ typedef struct {
  *                transmittance below t_stop (that Gaussian is not included).
  *  bg            background colour added with the final transmittance.
  *  tile_w/tile_h screen tile in pixels; 0/0 selects 16 x 16, the only shape
- *                this build implements. */
+ *                this build implements.
+ *  bin_chunk, row_seg, wave_layout   launch shapes; every value renders the same
+ *                images bit for bit (gs_autotune_render picks them for a workload):
+ *    bin_chunk   depth-sorted Gaussians per row-binning wave: 0 (= 1024), 512, 1024, 2048
+ *    row_seg     row-list entries per tile-binning wave: 0 (= 2048), 1024, 2048, 4096
+ *    wave_layout pixels of the four waves of a 16 x 16 tile: 0 or 1 = 8 x 8 quadrants,
+ *                2 = 16 x 4 strips
+ *                The workspace size does not depend on them. */
 typedef struct {
   int32_t width, height;
   int32_t sh_degree;
@@ -79,6 +86,7 @@ typedef struct {
   float near_plane, dilation, alpha_min, alpha_max, t_stop;
   float bg[3];
   int32_t tile_w, tile_h;
+  int32_t bin_chunk, row_seg, wave_layout;
 } gs_settings;
 
 /* Bytes of workspace needed for a render of n Gaussians, n_frames frames of
@@ -127,6 +135,23 @@ int gs_render_backward(const gs_settings* s, int32_t n, const float* params, int
                        const float* residuals, int32_t n_views, const gs_camera* cams, const float* image,
                        const float* d_image, const float* target, float* d_params, float* d_residuals,
                        float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Autotuner of the render launch shapes (bin_chunk, row_seg, wave_layout of gs_settings) for
+ * one workload: the a10 step of the hot path, with shapes picked by timed trials that must pass
+ * parity. Starting from *s, it tries the wave layouts, then the binning chunk sizes, then the
+ * row-segment sizes, keeping the best of each before moving on (8 trials). A trial renders the
+ * forward once, requires an image bit-identical to the first trial's (checksum on the device)
+ * and no pair-list overflow, then times two forward + backward passes between HIP events on
+ * `stream` (the backward takes the image itself as dL/dC and accumulates into the scratch
+ * d_params [C][n] and d_residuals [F][R][n] or NULL). Synchronises the stream.
+ * *best receives *s with the three fields set; times_ms[8] (or NULL) each trial's time per
+ * forward + backward, or -1 for a rejected trial. Returns GS_ERR_PAIR_OVERFLOW if the workspace
+ * is too small for the pairs (grow it first: render once and check gs_check_status), and the
+ * errors of gs_render_forward otherwise. */
+int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int32_t n_frames,
+                       const float* residuals, int32_t n_views, const gs_camera* cams, float* image, float* d_params,
+                       float* d_residuals, void* ws, size_t ws_bytes, void* stream, gs_settings* best,
+                       float* times_ms);
 
 /* Synchronises `stream` and reports the status of the last forward on ws:
  * GS_ERR_PAIR_OVERFLOW (and *needed_pairs) if its pair list did not fit. */

@@ -23,6 +23,7 @@ class GsSettings(ctypes.Structure):
         ("res_channels", ctypes.c_int32), ("near_plane", ctypes.c_float), ("dilation", ctypes.c_float),
         ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_stop", ctypes.c_float),
         ("bg", ctypes.c_float * 3), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+        ("bin_chunk", ctypes.c_int32), ("row_seg", ctypes.c_int32), ("wave_layout", ctypes.c_int32),
     ]
 
 
@@ -60,6 +61,7 @@ SIGNATURES = {
     "gs_render_forward": ([P, I32, P, I32, P, I32, P, P, P, SZ, P], ctypes.c_int),
     "gs_render_backward": ([P, I32, P, I32, P, I32, P, P, P, P, P, P, P, P, SZ, P], ctypes.c_int),
     "gs_check_status": ([P, P, P], ctypes.c_int),
+    "gs_autotune_render": ([P, I32, P, I32, P, I32, P, P, P, P, P, SZ, P, P, P], ctypes.c_int),
     "gs_error_string": ([ctypes.c_int], ctypes.c_char_p),
     "gs_last_error": ([], ctypes.c_char_p),
     "gs_workspace_stats": ([P, P, P], ctypes.c_int),

@@ -98,9 +98,19 @@ int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap
   d.near_plane = s->near_plane; d.dilation = s->dilation; d.alpha_min = s->alpha_min;
   d.alpha_max = s->alpha_max; d.t_stop = s->t_stop;
   for (int c = 0; c < 3; ++c) d.bg[c] = s->bg[c];
+  d.bin_chunk = s->bin_chunk == 0 ? kBinChunk : s->bin_chunk;
+  d.row_seg = s->row_seg == 0 ? kRowSeg : s->row_seg;
+  d.wave_layout = s->wave_layout == 0 ? 1 : s->wave_layout;
+  if (d.bin_chunk != 512 && d.bin_chunk != 1024 && d.bin_chunk != 2048)
+    return fail_arg("bin_chunk must be 0, 512, 1024 or 2048");
+  if (d.row_seg != 1024 && d.row_seg != 2048 && d.row_seg != 4096)
+    return fail_arg("row_seg must be 0, 1024, 2048 or 4096");
+  if (d.wave_layout != 1 && d.wave_layout != 2) return fail_arg("wave_layout must be 0, 1 or 2");
   d.n_sort_chunks = (n + kSortChunk - 1) / kSortChunk;
-  d.n_bin_chunks = (n + kBinChunk - 1) / kBinChunk;
-  d.n_row_segs = (n + kRowSeg - 1) / kRowSeg;
+  d.n_bin_chunks = (n + d.bin_chunk - 1) / d.bin_chunk;
+  d.n_row_segs = (n + d.row_seg - 1) / d.row_seg;
+  d.n_bin_chunks_max = (n + kBinChunkMin - 1) / kBinChunkMin;
+  d.n_row_segs_max = (n + kRowSegMin - 1) / kRowSegMin;
   d.capacity = (unsigned long long)cap;
   d.row_capacity = d.capacity / 2;
   return GS_OK;
@@ -172,10 +182,10 @@ Layout make_layout(const RenderDims& d) {
   lo.vals1 = take(Bn * 4);
   lo.sort_hist = take((size_t)d.B * 256 * d.n_sort_chunks * 4);
   lo.bin_rec = take(Bn * 48);
-  lo.bin_hist = take((size_t)d.B * d.n_bin_chunks * d.TY * 4);
+  lo.bin_hist = take((size_t)d.B * d.n_bin_chunks_max * d.TY * 4);
   lo.row_tot = take((size_t)d.B * d.TY * 4);
   lo.row_ranges = take((size_t)d.B * d.TY * 8);
-  lo.tile_hist = take((size_t)d.B * d.TY * d.n_row_segs * d.TX * 4);
+  lo.tile_hist = take((size_t)d.B * d.TY * d.n_row_segs_max * d.TX * 4);
   lo.tile_tot = take((size_t)d.B * d.T * 4);
   lo.ranges = take((size_t)d.B * d.T * 8);
   lo.t_final = take((size_t)d.B * d.L * HW * 4);
@@ -183,6 +193,7 @@ Layout make_layout(const RenderDims& d) {
   lo.grad2d = take(Bn * kGradStride * 4);
   lo.composed = take((size_t)d.F * d.Rc * d.n * 4);
   lo.d_composed = take((size_t)d.F * d.Rc * d.n * 4);
+  lo.check = take(256);  // the autotuner's image checksum
   // the pair lists are last, so every other offset is independent of their capacity
   lo.lists = take((size_t)d.capacity * 4);
   lo.row_lists = take((size_t)d.row_capacity * 8);
@@ -341,6 +352,99 @@ int gs_check_status(void* ws, void* stream, int64_t* needed_pairs) {
   if (e != hipSuccess) return fail_hip(e, "check_status sync");
   if (needed_pairs) *needed_pairs = (int64_t)h.needed_pairs;
   return h.overflow ? GS_ERR_PAIR_OVERFLOW : GS_OK;
+}
+
+int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int32_t n_frames,
+                       const float* residuals, int32_t n_views, const gs_camera* cams, float* image, float* d_params,
+                       float* d_residuals, void* ws, size_t ws_bytes, void* stream, gs_settings* best,
+                       float* times_ms) {
+  if (!s || !best || !image || !ws) return fail_arg("NULL argument");
+  RenderDims d;
+  int rc = make_dims(s, n, n_frames, n_views, 0, d);
+  if (rc) return rc;
+  if (n > 0 && !d_params) return fail_arg("the timed backward needs d_params scratch");
+  Layout lo0 = make_layout(d);
+  if (ws_bytes < lo0.total) {
+    g_last_error = "workspace too small";
+    return GS_ERR_WORKSPACE;
+  }
+  set_capacity(d, lo0, ws_bytes);
+  const Layout lo = make_layout(d);
+  if ((rc = check_device())) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long* chk = (unsigned long long*)((char*)ws + lo.check);
+  const size_t img_words = (size_t)d.B * d.L * 3 * d.W * d.H;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return fail_hip(hipErrorUnknown, "autotune events");
+  }
+  gs_settings cur = *s;
+  cur.bin_chunk = d.bin_chunk;
+  cur.row_seg = d.row_seg;
+  cur.wave_layout = d.wave_layout;
+  unsigned long long ref = 0;
+  bool have_ref = false;
+  // one trial: forward, parity check of the image against the first trial, then two timed
+  // forward + backward passes; *ms = -1 if the image differs
+  auto trial = [&](const gs_settings& t, float* ms) -> int {
+    int r = gs_render_forward(&t, n, params, n_frames, residuals, n_views, cams, image, ws, ws_bytes, stream);
+    if (r) return r;
+    hipError_t e = launch_checksum((const uint32_t*)image, img_words, chk, st);
+    if (e != hipSuccess) return fail_hip(e, "checksum");
+    if ((r = gs_check_status(ws, stream, nullptr))) return r;
+    unsigned long long h = 0;
+    if ((e = hipMemcpyAsync(&h, chk, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return fail_hip(e, "checksum copy");
+    if (!have_ref) {
+      ref = h;
+      have_ref = true;
+    } else if (h != ref) {
+      *ms = -1.f;
+      return GS_OK;
+    }
+    if ((e = hipEventRecord(e0, st)) != hipSuccess) return fail_hip(e, "event");
+    for (int k = 0; k < 2; ++k) {
+      if ((r = gs_render_forward(&t, n, params, n_frames, residuals, n_views, cams, image, ws, ws_bytes, stream)))
+        return r;
+      if ((r = gs_render_backward(&t, n, params, n_frames, residuals, n_views, cams, image, image, nullptr, d_params,
+                                  d_residuals, nullptr, ws, ws_bytes, stream)))
+        return r;
+    }
+    if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+      return fail_hip(e, "event");
+    float el = 0.f;
+    if ((e = hipEventElapsedTime(&el, e0, e1)) != hipSuccess) return fail_hip(e, "event");
+    *ms = 0.5f * el;
+    return GS_OK;
+  };
+  // greedy: the wave layout, then the binning chunk, then the row segment
+  static const int32_t kLayouts[2] = {1, 2}, kChunks[3] = {512, 1024, 2048}, kSegs[3] = {1024, 2048, 4096};
+  int ti = 0;
+  for (int phase = 0; phase < 3 && rc == GS_OK; ++phase) {
+    const int32_t* vals = phase == 0 ? kLayouts : phase == 1 ? kChunks : kSegs;
+    const int nv = phase == 0 ? 2 : 3;
+    float best_ms = -1.f;
+    int32_t best_v = phase == 0 ? cur.wave_layout : phase == 1 ? cur.bin_chunk : cur.row_seg;
+    for (int k = 0; k < nv && rc == GS_OK; ++k) {
+      gs_settings t = cur;
+      (phase == 0 ? t.wave_layout : phase == 1 ? t.bin_chunk : t.row_seg) = vals[k];
+      float ms = -1.f;
+      rc = trial(t, &ms);
+      if (times_ms) times_ms[ti] = ms;
+      ++ti;
+      if (rc == GS_OK && ms >= 0.f && (best_ms < 0.f || ms < best_ms)) {
+        best_ms = ms;
+        best_v = vals[k];
+      }
+    }
+    (phase == 0 ? cur.wave_layout : phase == 1 ? cur.bin_chunk : cur.row_seg) = best_v;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == GS_OK) *best = cur;
+  return rc;
 }
 
 int gs_workspace_stats(void* ws, void* stream, gs_stats* out) {

@@ -13,8 +13,12 @@ constexpr int kTilePix = kTile * kTile;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortChunk = kSortThreads * kSortItems;  // keys per radix block
+// Launch shapes of the binning (gs_settings bin_chunk / row_seg): defaults and the smallest
+// values, for which the workspace histograms are sized.
 constexpr int kBinChunk = 1024;      // depth-sorted Gaussians per row-binning wave
+constexpr int kBinChunkMin = 512;
 constexpr int kRowSeg = 2048;        // row-list entries per tile-binning wave
+constexpr int kRowSegMin = 1024;
 constexpr int kMaxTilesX = 128;      // tile columns one tile-binning wave covers (two per lane)
 constexpr int kMaxTilesPerView = 16384;
 constexpr int kMaxLevels = 8;
@@ -41,6 +45,9 @@ struct RenderDims {
   float near_plane, dilation, alpha_min, alpha_max, t_stop;
   float bg[3];
   int n_sort_chunks, n_bin_chunks, n_row_segs;
+  int bin_chunk, row_seg;             // launch shapes of the binning
+  int wave_layout;                    // 1: 8x8 quadrant per wave, 2: 16x4 strip per wave
+  int n_bin_chunks_max, n_row_segs_max;  // at the smallest shapes (workspace sizing)
   unsigned long long capacity;      // (tile, Gaussian) pairs
   unsigned long long row_capacity;  // (tile row, Gaussian) pairs
 };
@@ -48,7 +55,7 @@ struct RenderDims {
 // Byte offsets inside the workspace.
 struct Layout {
   size_t status, records, rects, keys0, vals0, keys1, vals1, sort_hist, bin_rec, bin_hist, row_tot, row_ranges,
-      tile_hist, tile_tot, ranges, t_final, n_last, grad2d, composed, d_composed, lists, row_lists, total;
+      tile_hist, tile_tot, ranges, t_final, n_last, grad2d, composed, d_composed, check, lists, row_lists, total;
 };
 
 Layout make_layout(const RenderDims& d);
@@ -70,5 +77,7 @@ hipError_t launch_project_bwd(const RenderDims& d, const float* params, const fl
 hipError_t launch_compose_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,
                               const float* d_composed, float* d_params, float* d_res, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// order-sensitive 64-bit checksum of n words (written to *out, which it zeroes first)
+hipError_t launch_checksum(const uint32_t* p, size_t n, unsigned long long* out, hipStream_t st);
 
 }  // namespace gs

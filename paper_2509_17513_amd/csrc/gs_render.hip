@@ -767,7 +767,7 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-// Level 1: rows. Each wave walks kBinChunk depth-sorted Gaussians of one
+// Level 1: rows. Each wave walks bin_chunk depth-sorted Gaussians of one
 // frame-view, 64 at a time with one Gaussian per lane. A lane evaluates the
 // first kRowPre tile rows of its Gaussian up front (column ranges kept in
 // LDS); the wave then visits the tile rows the batch reaches, and per row a
@@ -790,8 +790,8 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
   for (int t = lane; t < TY; t += 64) cnt[t] = EMIT ? row_ranges[(size_t)b * TY + t].x + bh[t] : 0u;
   __syncthreads();
   const size_t seg = (size_t)b * d.n;
-  const int start = chunk * kBinChunk;
-  const int end = min(start + kBinChunk, d.n);
+  const int start = chunk * d.bin_chunk;
+  const int end = min(start + d.bin_chunk, d.n);
   for (int base = start; base < end; base += 64) {
     const int e = base + lane;
     uint32_t gi = 0;
@@ -856,7 +856,7 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
     for (int t = lane; t < TY; t += 64) bh[t] = cnt[t];
 }
 
-// Level 2: tiles of one row. One wave takes a segment of kRowSeg entries of a
+// Level 2: tiles of one row. One wave takes a segment of row_seg entries of a
 // (frame-view, row) list; lane l owns tile column l (and l + 64 when the image
 // is wider than 64 tiles, TWO) and appends, in list (= depth) order, every
 // entry whose column range covers it, so each lane writes its own tile list
@@ -874,9 +874,9 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
   const int lane = threadIdx.x;
   const int s = blockIdx.x, ty = blockIdx.y, b = blockIdx.z;
   const uint2 rr = row_ranges[(size_t)b * d.TY + ty];
-  const uint32_t start = rr.x + (uint32_t)s * kRowSeg;
+  const uint32_t start = rr.x + (uint32_t)s * (uint32_t)d.row_seg;
   if (start >= rr.y) return;
-  const uint32_t end = min(start + (uint32_t)kRowSeg, rr.y);
+  const uint32_t end = min(start + (uint32_t)d.row_seg, rr.y);
   const int tx0 = lane, tx1 = lane + 64;
   uint32_t* hb = hist + (((size_t)b * d.TY + ty) * d.n_row_segs + s) * d.TX;
   uint32_t c0 = 0, c1 = 0;   // next list position (emit) or count
@@ -960,7 +960,7 @@ __global__ __launch_bounds__(256) void k_seg_scan(RenderDims d, const Status* __
   uint32_t run = 0;
   if (!(st->overflow & 2u)) {
     const uint2 rr = row_ranges[(size_t)b * d.TY + ty];
-    const int nseg = (int)((rr.y - rr.x + kRowSeg - 1) / kRowSeg);
+    const int nseg = (int)((rr.y - rr.x + d.row_seg - 1) / d.row_seg);
     for (int sgi = 0; sgi < nseg; ++sgi) {
       const size_t o = (((size_t)b * d.TY + ty) * d.n_row_segs + sgi) * d.TX + tx;
       const uint32_t v = hist[o];
@@ -1028,10 +1028,16 @@ __device__ __forceinline__ bool tile_ctx(const RenderDims& d, const uint2* range
   const int tx = c.tile % d.TX, ty = c.tile / d.TX;
   c.ox = tx * kTile;
   c.oy = ty * kTile;
-  // wave w covers the 8x8 quadrant (w & 1, w >> 1) of the tile, lane l its pixel (l & 7, l >> 3)
+  // layout 1: wave w covers the 8x8 quadrant (w & 1, w >> 1) of the tile, lane l its pixel
+  // (l & 7, l >> 3); layout 2: wave w covers rows 4w..4w+3, lane l pixel (l & 15, l >> 4)
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  c.px = tx * kTile + (w & 1) * 8 + (l & 7);
-  c.py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+  if (d.wave_layout == 2) {
+    c.px = tx * kTile + (l & 15);
+    c.py = ty * kTile + 4 * w + (l >> 4);
+  } else {
+    c.px = tx * kTile + (w & 1) * 8 + (l & 7);
+    c.py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+  }
   c.inside = c.px < d.W && c.py < d.H;
   c.range = ranges[(size_t)c.b * d.T + c.tile];
   return true;
@@ -1089,10 +1095,11 @@ __device__ __forceinline__ uint32_t wave_max_u(uint32_t v) {
   return __builtin_amdgcn_readfirstlane(max(r32[0], r32[1]));
 }
 
-// Quadrants (bit 2 qy + qx) of the 16x16 tile with origin (x0, y0) whose pixel
-// centres the ellipse q(p) <= tau of alpha >= alpha_min may reach. The same
-// exact row-extent test (and margins) as the binning, on 8-pixel bands; a wave
-// skips every entry whose bit for its quadrant is clear.
+// Sub-tiles of the 16x16 tile with origin (x0, y0) whose pixel centres the
+// ellipse q(p) <= tau of alpha >= alpha_min may reach: bit w for the pixels of
+// wave w (layout 1: the 8x8 quadrant (w & 1, w >> 1); layout 2: rows 4w..4w+3).
+// The same exact row-extent test (and margins) as the binning, on the sub-tiles'
+// bands of pixel-centre rows; a wave skips every entry whose bit is clear.
 __device__ __forceinline__ uint32_t quad_mask(const RenderDims& d, float mx, float my, float A, float B, float C,
                                               float o, int x0, int y0) {
   // hardware log / reciprocal / square root: their relative errors (~1e-7) are far inside the
@@ -1103,19 +1110,26 @@ __device__ __forceinline__ uint32_t quad_mask(const RenderDims& d, float mx, flo
   const float iA = __builtin_amdgcn_rcpf(A), idet = __builtin_amdgcn_rcpf(det);
   const float dxm = __builtin_amdgcn_sqrtf(tau * C * idet);
   const float dyr = -B * dxm * __builtin_amdgcn_rcpf(C), dym = __builtin_amdgcn_sqrtf(A * tau * idet);
+  const bool strips = d.wave_layout == 2;
+  const int nb = strips ? 4 : 2;           // bands of pixel-centre rows
+  const float bh = strips ? 3.f : 7.f;     // band height - 1
   uint32_t m = 0;
-#pragma unroll
-  for (int qy = 0; qy < 2; ++qy) {
-    const float Y0 = (float)(y0 + 8 * qy) + 0.5f - my;
-    const float lo = fmaxf(Y0, -dym), hi = fminf(Y0 + 7.f, dym);
+  for (int q = 0; q < nb; ++q) {
+    const float Y0 = (float)(y0 + (strips ? 4 : 8) * q) + 0.5f - my;
+    const float lo = fmaxf(Y0, -dym), hi = fminf(Y0 + bh, dym);
     if (!(lo <= hi)) continue;
     const float dr = fminf(fmaxf(dyr, lo), hi), dl = fminf(fmaxf(-dyr, lo), hi);
     const float xr = mx + (-B * dr + __builtin_amdgcn_sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
     const float xl = mx + (-B * dl - __builtin_amdgcn_sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
+    if (strips) {
+      const float X0 = (float)x0 + 0.5f;
+      if (xl <= X0 + 15.f && xr >= X0) m |= 1u << q;
+    } else {
 #pragma unroll
-    for (int qx = 0; qx < 2; ++qx) {
-      const float X0 = (float)(x0 + 8 * qx) + 0.5f;
-      if (xl <= X0 + 7.f && xr >= X0) m |= 1u << (2 * qy + qx);
+      for (int qx = 0; qx < 2; ++qx) {
+        const float X0 = (float)(x0 + 8 * qx) + 0.5f;
+        if (xl <= X0 + 7.f && xr >= X0) m |= 1u << (2 * q + qx);
+      }
     }
   }
   return m;
@@ -1510,6 +1524,17 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   flush_counters(n_eval, n_contrib, &st->bwd_evals, &st->bwd_contribs);
 }
 
+// Order-sensitive checksum: sum over i of word_i * (2 i + 1) (mod 2^64).
+__global__ __launch_bounds__(256) void k_checksum(const uint32_t* __restrict__ p, size_t n,
+                                                  unsigned long long* __restrict__ out) {
+  unsigned long long acc = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    acc += (unsigned long long)p[i] * (2ull * i + 1ull);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
 __global__ void k_zero(uint32_t* p, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -1527,6 +1552,13 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
     ProfScope ps_(K_ZERO, st);
     hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, (uint32_t*)p, n);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_checksum(const uint32_t* p, size_t n, unsigned long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, (uint32_t*)out, (size_t)2);
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  if (blocks > 0) hipLaunchKernelGGL(k_checksum, dim3(blocks), dim3(256), 0, st, p, n, out);
   return hipGetLastError();
 }
 

@@ -28,6 +28,10 @@ class RenderSettings:
     alpha_max: float = 0.99
     t_stop: float = 1e-4
     bg: tuple = (0.0, 0.0, 0.0)
+    # launch shapes (identical images for every value; see autotune): 0 = library default
+    bin_chunk: int = 0
+    row_seg: int = 0
+    wave_layout: int = 0
 
     def c_struct(self, n: int) -> GsSettings:
         s = GsSettings()
@@ -46,6 +50,7 @@ class RenderSettings:
         for i in range(3):
             s.bg[i] = self.bg[i]
         s.tile_w = s.tile_h = 0
+        s.bin_chunk, s.row_seg, s.wave_layout = self.bin_chunk, self.row_seg, self.wave_layout
         return s
 
     @property
@@ -172,6 +177,30 @@ def render_backward(settings: RenderSettings, params: torch.Tensor, cams: torch.
                                    _ptr(image), _ptr(d_image), _ptr(target), _ptr(d_params), _ptr(d_residuals),
                                    _ptr(loss), _ptr(ws.buf), ws.nbytes, _stream(dev)), "gs_render_backward")
     return d_params, d_residuals
+
+
+def autotune(settings: RenderSettings, params: torch.Tensor, cams: torch.Tensor, ws: Workspace, n_frames: int = 1,
+             residuals: torch.Tensor | None = None, image: torch.Tensor | None = None):
+    """Launch shapes for this workload (gs_autotune_render): returns (tuned settings, the eight trial
+    times in ms per forward + backward, -1 for a trial whose image differed). The workspace must
+    already hold the pairs (render once with check_overflow first)."""
+    dev = params.device
+    n = params.shape[1]
+    B = cams.shape[0]
+    if image is None:
+        shape = (n_frames, B // n_frames, settings.n_levels, 3, settings.height, settings.width)
+        image = torch.empty(shape, dtype=torch.float32, device=dev)
+    dp = torch.zeros_like(params)
+    dr = torch.zeros_like(residuals) if residuals is not None else None
+    s = settings.c_struct(n)
+    best = GsSettings()
+    times = (ctypes.c_float * 8)()
+    check(lib().gs_autotune_render(ctypes.byref(s), n, _ptr(params), n_frames, _ptr(residuals), B // n_frames,
+                                   _ptr(cams), _ptr(image), _ptr(dp), _ptr(dr), _ptr(ws.buf), ws.nbytes, _stream(dev),
+                                   ctypes.byref(best), times), "gs_autotune_render")
+    tuned = dataclasses.replace(settings, bin_chunk=best.bin_chunk, row_seg=best.row_seg,
+                                wave_layout=best.wave_layout)
+    return tuned, list(times)
 
 
 class RenderFunction(torch.autograd.Function):

@@ -68,6 +68,19 @@ def test_workspace_size_and_validation(L):
     st.tile_w = st.tile_h = 8
     assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 1, 10, ctypes.byref(sz)) == -6
     assert L.gs_error_string(-3) == b"pair list capacity exceeded"
+    # launch shapes: only the listed values, and the workspace does not depend on them
+    for field, value in (("bin_chunk", 300), ("bin_chunk", 4096), ("row_seg", 512), ("wave_layout", 3)):
+        st = _settings(1000)
+        setattr(st, field, value)
+        assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 2, 10000, ctypes.byref(sz2)) == -1, (field, value)
+    ref = ctypes.c_size_t()
+    st = _settings(1000)
+    assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 2, 10000, ctypes.byref(ref)) == 0
+    for bc, rs, wl in ((512, 1024, 1), (2048, 4096, 2), (1024, 2048, 0)):
+        st = _settings(1000)
+        st.bin_chunk, st.row_seg, st.wave_layout = bc, rs, wl
+        assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 2, 10000, ctypes.byref(sz2)) == 0
+        assert sz2.value == ref.value
 
 
 def test_render_calls_reject_bad_args_before_launch(L):
