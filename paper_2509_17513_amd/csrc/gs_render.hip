@@ -619,31 +619,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(RenderDims d, const
 }
 
 // Exclusive scan of one segment's [256][chunks] digit-major histogram.
-__global__ __launch_bounds__(1024) void k_radix_scan(RenderDims d, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t part[1024];
-  const int b = blockIdx.x, t = threadIdx.x;
-  const int total = 256 * d.n_sort_chunks;
-  uint32_t* h = hist + (size_t)b * total;
-  const int per = (total + 1023) / 1024;
-  const int lo = t * per, hi = min(lo + per, total);
-  uint32_t s = 0;
-  for (int j = lo; j < hi; ++j) s += h[j];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = t >= off ? part[t - off] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[t] - s;
-  for (int j = lo; j < hi; ++j) {
-    const uint32_t v = h[j];
-    h[j] = run;
-    run += v;
-  }
-}
-
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RenderDims d, const uint32_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                uint32_t* __restrict__ kout,
@@ -933,20 +908,76 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
   }
 }
 
-// Per (frame-view, bin): exclusive prefix over the chunks of level 1 (bins = rows).
-__global__ __launch_bounds__(256) void k_chunk_scan(int nbins_total, int nbins, int nchunks,
-                                                    uint32_t* __restrict__ hist, uint32_t* __restrict__ tot) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nbins_total) return;
-  const int b = g / nbins, t = g - b * nbins;
-  uint32_t run = 0;
-  for (int c = 0; c < nchunks; ++c) {
-    const size_t o = ((size_t)b * nchunks + c) * nbins + t;
-    const uint32_t v = hist[o];
-    hist[o] = run;
-    run += v;
+// Inclusive prefix sum over the wave (every lane active).
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long u = __shfl_up(v, off);
+    if (lane >= off) v += u;
   }
-  tot[g] = run;
+  return v;
+}
+
+// Per (frame-view, bin): exclusive prefix over the chunks of level 1 (bins = rows).
+// One wave per bin, 64 chunks per step.
+__global__ __launch_bounds__(64) void k_chunk_scan(int nbins_total, int nbins, int nchunks,
+                                                   uint32_t* __restrict__ hist, uint32_t* __restrict__ tot) {
+  const int g = blockIdx.x;
+  if (g >= nbins_total) return;
+  const int lane = threadIdx.x;
+  const int b = g / nbins, t = g - b * nbins;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nchunks; c0 += 64) {
+    const int c = c0 + lane;
+    const size_t o = ((size_t)b * nchunks + c) * nbins + t;
+    const uint32_t v = c < nchunks ? hist[o] : 0u;
+    const uint32_t incl = (uint32_t)wave_incl_scan_u64(v, lane);
+    if (c < nchunks) hist[o] = carry + incl - v;
+    carry += (uint32_t)__shfl(incl, 63);
+  }
+  if (lane == 0) tot[g] = carry;
+}
+
+// Exclusive scan of count values by one 1024-thread block, 4 consecutive values per thread
+// per pass (coalesced 16-byte loads); emit(i, prefix, value) is called for every element, and
+// the returned value is the total. All threads of the block must call it.
+template <class Emit>
+__device__ unsigned long long block_scan_u32(const uint32_t* __restrict__ in, int count, Emit emit) {
+  __shared__ unsigned long long s_w[16];
+  __shared__ unsigned long long s_tile;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  unsigned long long carry = 0;
+  for (int base = 0; base < count; base += 4096) {
+    const int i0 = base + 4 * t;
+    uint32_t v[4];
+    if (i0 + 3 < count && ((reinterpret_cast<uintptr_t>(in + i0) & 15) == 0)) {
+      const uint4 q = *reinterpret_cast<const uint4*>(in + i0);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = i0 + k < count ? in[i0 + k] : 0u;
+    }
+    const unsigned long long tsum = (unsigned long long)v[0] + v[1] + v[2] + v[3];
+    const unsigned long long wincl = wave_incl_scan_u64(tsum, lane);
+    if (lane == 63) s_w[w] = wincl;
+    __syncthreads();
+    if (w == 0) {
+      const unsigned long long x = lane < 16 ? s_w[lane] : 0ull;
+      const unsigned long long xi = wave_incl_scan_u64(x, lane);
+      if (lane < 16) s_w[lane] = xi - x;
+      if (lane == 15) s_tile = xi;
+    }
+    __syncthreads();
+    unsigned long long run = carry + s_w[w] + wincl - tsum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < count) emit(i0 + k, run, v[k]);
+      run += v[k];
+    }
+    carry += s_tile;
+    __syncthreads();
+  }
+  return carry;
 }
 
 // Per (frame-view, tile): exclusive prefix over the level-2 segments of its row.
@@ -974,32 +1005,21 @@ __global__ __launch_bounds__(256) void k_seg_scan(RenderDims d, const Status* __
 // Exclusive scan of `count` totals into [start, end) ranges. level 0 (rows):
 // flags overflow bit 2 if the row pairs exceed their capacity; level 1 (tiles):
 // flags bit 1 for the tile pairs and records the pairs needed.
+// Per frame-view: exclusive scan of the (digit-major, chunk-minor) radix histogram.
+__global__ __launch_bounds__(1024) void k_radix_scan(RenderDims d, uint32_t* __restrict__ hist) {
+  uint32_t* h = hist + (size_t)blockIdx.x * 256 * d.n_sort_chunks;
+  block_scan_u32(h, 256 * d.n_sort_chunks, [&](int j, unsigned long long run, uint32_t) { h[j] = (uint32_t)run; });
+}
+
 __global__ __launch_bounds__(1024) void k_scan_ranges(int count, int level, unsigned long long cap,
                                                       const uint32_t* __restrict__ tot, uint2* __restrict__ ranges,
                                                       Status* __restrict__ st) {
-  __shared__ unsigned long long part[1024];
-  const int t = threadIdx.x;
-  const int per = (count + 1023) / 1024;
-  const int lo = t * per, hi = min(lo + per, count);
-  unsigned long long sum = 0;
-  for (int j = lo; j < hi; ++j) sum += tot[j];
-  part[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    unsigned long long v = t >= off ? part[t - off] : 0ull;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  unsigned long long run = part[t] - sum;
-  for (int j = lo; j < hi; ++j) {
-    const uint32_t v = tot[j];
-    const unsigned long long e = run + v;
-    ranges[j] = make_uint2((uint32_t)min(run, 0xFFFFFFFFull), (uint32_t)min(e, 0xFFFFFFFFull));
-    run = e;
-  }
-  if (t == 1023) {
-    const unsigned long long total = part[1023];
+  const unsigned long long total =
+      block_scan_u32(tot, count, [&](int j, unsigned long long run, uint32_t v) {
+        const unsigned long long e = run + v;
+        ranges[j] = make_uint2((uint32_t)min(run, 0xFFFFFFFFull), (uint32_t)min(e, 0xFFFFFFFFull));
+      });
+  if (threadIdx.x == 0) {
     if (level == 0) {
       st->overflow = total > cap ? 2u : 0u;
       st->needed_pairs = 2ull * total;  // a lower bound of the tile pairs while the rows overflow
@@ -1670,7 +1690,7 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   }
   {
     ProfScope ps_(K_BIN_CHUNK_SCAN, st);
-    hipLaunchKernelGGL(k_chunk_scan, dim3((d.B * d.TY + 255) / 256), dim3(256), 0, st, d.B * d.TY, d.TY,
+    hipLaunchKernelGGL(k_chunk_scan, dim3(d.B * d.TY), dim3(64), 0, st, d.B * d.TY, d.TY,
                        d.n_bin_chunks, rhist, rtot);
     hipLaunchKernelGGL(k_scan_ranges, dim3(1), dim3(1024), 0, st, d.B * d.TY, 0, d.row_capacity, rtot, rranges,
                        status);
