@@ -841,10 +841,12 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
                                                  const uint2* __restrict__ row_ranges,
                                                  const uint2* __restrict__ row_lists, uint32_t* __restrict__ hist,
                                                  const uint2* __restrict__ ranges, uint32_t* __restrict__ lists) {
-  // emit: each lane gathers up to kWc entries of each of its tiles in LDS and writes them out as
-  // one contiguous run that ends on a kWc-entry boundary of the list
-  constexpr int kWc = 16;
-  __shared__ __align__(16) uint32_t wbuf[TWO ? 2 : 1][64][kWc];
+  // emit: each lane appends its tile's entries to a 32-entry ring in LDS indexed by list
+  // position; every 16 entries of the segment the wave drains, per lane, the unaligned head up to
+  // the next 16-entry boundary of the list and then whole aligned 16-entry runs (four 16-byte
+  // stores each), so that at most 31 entries are outstanding
+  constexpr int kRing = 32, kStride = 36;  // stride: 16-byte aligned rows, spread banks
+  __shared__ __align__(16) uint32_t wbuf[TWO ? 2 : 1][64][kStride];
   if (st->overflow & 2u) return;
   const int lane = threadIdx.x;
   const int s = blockIdx.x, ty = blockIdx.y, b = blockIdx.z;
@@ -854,24 +856,41 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
   const uint32_t end = min(start + (uint32_t)d.row_seg, rr.y);
   const int tx0 = lane, tx1 = lane + 64;
   uint32_t* hb = hist + (((size_t)b * d.TY + ty) * d.n_row_segs + s) * d.TX;
-  uint32_t c0 = 0, c1 = 0;   // next list position (emit) or count
-  uint32_t n0 = 0, n1 = 0;   // buffered entries (emit)
+  uint32_t c0 = 0, c1 = 0;   // next list position to fill (emit) or count
+  uint32_t w0 = 0, w1 = 0;   // next list position to write out (emit)
   if (EMIT) {
-    if (tx0 < d.TX) c0 = ranges[(size_t)b * d.T + ty * d.TX + tx0].x + hb[tx0];
-    if (tx1 < d.TX) c1 = ranges[(size_t)b * d.T + ty * d.TX + tx1].x + hb[tx1];
+    if (tx0 < d.TX) c0 = w0 = ranges[(size_t)b * d.T + ty * d.TX + tx0].x + hb[tx0];
+    if (tx1 < d.TX) c1 = w1 = ranges[(size_t)b * d.T + ty * d.TX + tx1].x + hb[tx1];
   }
-  auto flush = [&](int q, uint32_t& c, uint32_t& nb) {
-    if (nb == kWc && c + kWc <= d.capacity) {  // a whole aligned run: four 16-byte stores
-      const uint4* src = (const uint4*)wbuf[q][lane];
-      uint4* dst = (uint4*)(lists + c);
-#pragma unroll
-      for (int v = 0; v < kWc / 4; ++v) dst[v] = src[v];
-    } else {
-      for (uint32_t k = 0; k < nb; ++k)
-        if (c + k < d.capacity) lists[c + k] = wbuf[q][lane][k];
+  const unsigned long long cap = d.capacity;
+  auto drain = [&](int q, uint32_t c, uint32_t& w, bool last) {
+    const uint32_t* ring = wbuf[q][lane];
+    if (w & 15u) {  // head: up to the next aligned position
+      const uint32_t bnd = (w + 15u) & ~15u;
+      if (c >= bnd || last) {
+        const uint32_t stop = min(bnd, c);
+        for (uint32_t p = w; p < stop; ++p)
+          if (p < cap) lists[p] = ring[p & (kRing - 1)];
+        w = stop;
+      }
     }
-    c += nb;
-    nb = 0;
+    while (c - w >= 16u) {  // whole aligned runs
+      if ((unsigned long long)w + 16ull <= cap) {
+        const uint4* src = (const uint4*)(ring + (w & (kRing - 1)));
+        uint4* dst = (uint4*)(lists + w);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[v] = src[v];
+      } else {
+        for (uint32_t k = 0; k < 16u; ++k)
+          if (w + k < cap) lists[w + k] = ring[(w + k) & (kRing - 1)];
+      }
+      w += 16u;
+    }
+    if (last) {
+      for (uint32_t p = w; p < c; ++p)
+        if (p < cap) lists[p] = ring[p & (kRing - 1)];
+      w = c;
+    }
   };
   for (uint32_t base = start; base < end; base += 64) {
     const uint32_t e = base + lane;
@@ -882,26 +901,26 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
       const uint32_t rg = __builtin_amdgcn_readlane(ent.y, j);
       const int txl = (int)(rg & 0xFFFF), txh = (int)(rg >> 16);
       if (tx0 >= txl && tx0 <= txh) {
-        if (EMIT) {
-          wbuf[0][lane][n0++] = gi;
-          if (((c0 + n0) & (kWc - 1)) == 0) flush(0, c0, n0);
-        } else {
-          ++c0;
-        }
+        if (EMIT) wbuf[0][lane][c0 & (kRing - 1)] = gi;
+        ++c0;
       }
       if (TWO && tx1 >= txl && tx1 <= txh) {
-        if (EMIT) {
-          wbuf[1][lane][n1++] = gi;
-          if (((c1 + n1) & (kWc - 1)) == 0) flush(1, c1, n1);
-        } else {
-          ++c1;
-        }
+        if (EMIT) wbuf[TWO ? 1 : 0][lane][c1 & (kRing - 1)] = gi;
+        ++c1;
       }
+      if (EMIT && (j & 15) == 15) {  // uniform: at most 16 new entries per lane since the last drain
+        drain(0, c0, w0, false);
+        if (TWO) drain(TWO ? 1 : 0, c1, w1, false);
+      }
+    }
+    if (EMIT && (nin & 15)) {
+      drain(0, c0, w0, false);
+      if (TWO) drain(TWO ? 1 : 0, c1, w1, false);
     }
   }
   if (EMIT) {
-    flush(0, c0, n0);
-    if (TWO) flush(1, c1, n1);
+    drain(0, c0, w0, true);
+    if (TWO) drain(TWO ? 1 : 0, c1, w1, true);
   } else {
     if (tx0 < d.TX) hb[tx0] = c0;
     if (TWO && tx1 < d.TX) hb[tx1] = c1;
