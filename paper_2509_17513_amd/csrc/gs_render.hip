@@ -8,18 +8,22 @@
 //                     view-dependent SH colour; writes 48-byte records
 //   k_radix_*         segmented stable LSD radix sort of float32 depth keys
 //                     (one segment per frame-view, 4 passes of 8 bits)
-//   k_bin_*           stable counting scatter of the depth-sorted Gaussians
-//                     into per-(view, tile) lists: the (tile, depth) order
-//   k_raster_fwd      one 256-thread block per (view, 16x16 tile): records are
-//                     staged through LDS in batches of 256; every pixel
-//                     composites all layers at once (Eq. 2 for each index set
-//                     of Eq. 4) and stops when every layer has reached the
-//                     transmittance floor
+//   k_bin_gather, k_row_bin, k_tile_bin, scans
+//                     two-level stable counting scatter of the depth-sorted
+//                     Gaussians into per-(view, tile) lists, the (tile, depth)
+//                     order: tile rows first, then the tiles of each row
+//   k_raster_fwd      one 256-thread block per (view, 16x16 tile), a wave per
+//                     8x8 quadrant (or 16x4 strip): records are staged through
+//                     LDS in batches of 256; every pixel composites all layers
+//                     at once (Eq. 2 for each index set of Eq. 4) and stops
+//                     when every layer has reached the transmittance floor
 // Backward:
-//   k_raster_bwd      reverse traversal from each layer's last contributor;
+//   k_raster_bwd      reverse traversal from each layer's last contributor over
+//                     per-wave lists of the staged entries the wave can use;
 //                     the transmittance is recovered by division, so no
-//                     per-pixel lists are stored; wave reductions, then one
-//                     atomic per (wave, record, value)
+//                     per-pixel lists are stored; a permlane/DPP reduce-scatter
+//                     per entry, LDS sums of the four waves, then one atomic
+//                     per (record, value) and batch
 //   k_project_bwd     one thread per Gaussian, all views and frames in registers
 //   k_compose_bwd     suffix sums and the quaternion-product chain over frames
 #include <hip/hip_runtime.h>
@@ -32,7 +36,6 @@ namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
 
-__device__ __forceinline__ float rcp_f(float x) { return 1.0f / x; }
 
 __device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float* R) {
   R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
