@@ -36,7 +36,6 @@ namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
 
-
 __device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float* R) {
   R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
   R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
