@@ -57,11 +57,24 @@ def kernel_bytes(name, n, B, pairs, L, HW, C=59):
     return None
 
 
-def source_hash():
+def code_text(src: str) -> str:
+    """Kernel source without comments, blank lines and indentation (what the counters depend on)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    lines = (ln.split("//", 1)[0].strip() for ln in src.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
+def source_hash(read=None):
+    """Hash of the code of the render kernels and their host orchestration."""
     h = hashlib.sha256()
     for f in ("gs_render.hip", "gs_api.hip", "gs_internal.h"):
-        with open(os.path.join(ROOT, "paper_2509_17513_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_2509_17513_amd", "csrc", f)) as fh:
+                txt = fh.read()
+        else:
+            txt = read(f)
+        h.update(code_text(txt).encode())
     return h.hexdigest()[:16]
 
 
