@@ -139,7 +139,7 @@ BF16_PEAK_FLOPS = 2.5e15
 
 def bench_rate(torch, dev, L, steps, n=1_000_000, tune=True):
     """Learned rate at 1M Gaussians x 56 attributes: train-mode forward + backward of the
-    per-attribute MLP (BF16 MFMA) and the histogram judge, timed with HIP events per kernel."""
+    per-attribute MLP (BF16 MFMA) and the histogram rate it is checked against, timed with HIP events per kernel."""
     import ctypes
 
     import synth
@@ -274,8 +274,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding of views is a design "
-                                   "(see DESIGN.md), not part of this benchmark", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; sharding views over several GPUs is "
+                                   "not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import ctypes

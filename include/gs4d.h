@@ -236,7 +236,7 @@ int gs_rate_autotune(const gs_rate_desc* desc, const float* attrs, const uint16_
                      const float* b_f32, double* bits_scratch, float* d_attrs, float* d_w, float* d_b, void* stream,
                      int32_t* best_blocks, float* times_ms);
 
-/* Empirical-histogram rate (the judge of the learned rate): per attribute
+/* Empirical-histogram rate (the reference the learned rate is checked against): per attribute
  * bits = -sum_i log2(count(k_i) / n) = n H over its symbol histogram, in FP64.
  * bits_out [n_attr] float64 (overwritten). The symbol range of one attribute
  * must span at most 65536 symbols (else bits_out is left undefined and the

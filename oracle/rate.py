@@ -6,7 +6,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   (round half to even); the paper simulates quantisation in training with
   additive uniform noise of one step's width (Sec. 3.3, differentiable
   quantisation; the noise here is u ~ U(-q/2, q/2)).
-* Histogram rate (the judge): bits = -sum_i log2(n(k_i) / N) over the
+* Histogram rate (the reference of the learned rate): bits = -sum_i log2(n(k_i) / N) over the
   empirical symbol counts n(k) of one attribute, i.e. N times the empirical
   entropy.
 * Learned rate: a discretised Laplace per symbol, PMF(y) = F(y + q/2) - F(y - q/2)
