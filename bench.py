@@ -34,6 +34,11 @@ ALU_PEAK_OPS = 256 * 64 * 2.4e9
 # and one compositing update of one layer (forward) or its gradient (backward)
 FWD_OPS_EVAL, FWD_OPS_CONTRIB = 12, 8
 BWD_OPS_EVAL, BWD_OPS_CONTRIB = 12, 30
+# algorithmic VALU operations per image element (pixel, channel, layer) of the D-SSIM kernels:
+# forward = two 11-tap passes of x, x^2, x y (66) + the two products + the per-pixel SSIM value and
+# derivatives (30), plus the target's two moments shared by the L layers; backward = two passes of
+# the three derivative maps (66) + the combination with x, y and the L1 term (7)
+SSIM_FWD_OPS, SSIM_FWD_OPS_SHARED, SSIM_BWD_OPS = 98, 45, 73
 
 
 def log(msg):
@@ -267,6 +272,7 @@ def main():
     ap.add_argument("--views", type=int, default=24)
     ap.add_argument("--no-rate", action="store_true", help="skip the learned-rate measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the group and training-step measurements")
+    ap.add_argument("--no-dssim", action="store_true", help="skip the D-SSIM colour-loss measurement")
     ap.add_argument("--no-autotune", action="store_true", help="no autotuning: default shapes or --shapes")
     ap.add_argument("--shapes", default="", help="launch shapes bin_chunk,row_seg,wave_layout (with --no-autotune)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -366,6 +372,10 @@ def main():
 
     graph = capture(step)
     ms_step_graph = time_graph(graph, args.steps)
+    # forward only (what a decoder renders per frame), same workload and shapes
+    graph_fwd = capture(lambda: render_forward(st, p, c, ws=ws, image=img, check_overflow=False))
+    ms_fwd = time_graph(graph_fwd, args.steps)
+    del graph_fwd
     ms_step = min(ms_step_eager, ms_step_graph)
     log(f"[bench] batched eager {ms_step_eager:.3f} ms/step, graph replay {ms_step_graph:.3f} ms/step")
     stats = _lib.GsStats()
@@ -428,10 +438,54 @@ def main():
                    "loss": "sum_l lambda^l mean L1 vs uniform-noise targets"},
         "roofline": roof,
         "autotune": tune,
+        "forward_only": {"ms_per_step": ms_fwd, "ms_per_view": ms_fwd / B},
         "step_hbm": step_hbm,
         "hbm_kernels": hbm_kernels,
         "kernels": kernels,
     }
+
+    # ---------------- D-SSIM colour loss (lambda_ssim = 0.2) on the same renders and targets
+    if not args.no_dssim:
+        from paper_2509_17513_amd import LossWorkspace, color_loss
+        log("[bench] D-SSIM colour loss")
+        lam = 0.2
+        d_img = torch.empty_like(img)
+        lws = LossWorkspace(st, B, dev)
+        loss_s = torch.zeros(1, device=dev)
+
+        def loss_only():
+            color_loss(st, img, tgt, lam, d_image=d_img, loss=loss_s, ws=lws)
+
+        def step_ssim():
+            render_forward(st, p, c, ws=ws, image=img, check_overflow=False)
+            color_loss(st, img, tgt, lam, d_image=d_img, loss=loss_s, ws=lws)
+            render_backward(st, p, c, ws, d_image=d_img, d_params=dparams)
+
+        for _ in range(args.warmup):
+            step_ssim()
+        torch.cuda.synchronize()
+        L.gs_profile_enable(1)
+        for _ in range(args.steps):
+            step_ssim()
+        torch.cuda.synchronize()
+        L.gs_profile_enable(0)
+        _lib.check(L.gs_profile_collect(nk, tot, cnt), "gs_profile_collect")
+        sk = {L.gs_kernel_name(k).decode(): tot[k] / cnt[k] for k in range(nk) if cnt[k]}
+        ms_ssim_step = time_graph(capture(step_ssim), args.steps)
+        ms_loss = time_graph(capture(loss_only), args.steps)
+        elems = B * Lv * 3 * HW
+        ssim_k = {}
+        for k, ops, by in (("ssim_fwd", elems * SSIM_FWD_OPS + B * 3 * HW * SSIM_FWD_OPS_SHARED,
+                            elems * 16 + B * 3 * HW * 4),
+                           ("ssim_bwd", elems * SSIM_BWD_OPS, elems * 20 + B * 3 * HW * 4)):
+            if k in sk:
+                t = sk[k] * 1e-3
+                ssim_k[k] = {"ms_per_launch": sk[k], "alu_frac": ops / t / ALU_PEAK_OPS,
+                             "hbm_frac": by / t / 1e9 / HBM_PEAK_GBS, "ops": ops, "bytes": by}
+        out["dssim"] = {"lambda_ssim": lam, "ms_loss": ms_loss, "ms_per_step": ms_ssim_step,
+                        "ms_per_view": ms_ssim_step / B, "kernels": ssim_k}
+        log(f"[bench] D-SSIM loss {ms_loss:.3f} ms, step with D-SSIM {ms_ssim_step:.3f} ms ({ssim_k})")
+        del d_img, lws
 
     # ---------------- per-view baseline: 24 x 6 single-view single-layer forward+backward calls
     if not args.no_per_view:

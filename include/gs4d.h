@@ -136,6 +136,28 @@ int gs_render_backward(const gs_settings* s, int32_t n, const float* params, int
                        const float* d_image, const float* target, float* d_params, float* d_residuals,
                        float* loss_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Colour loss of a render with its D-SSIM term, and its gradient (Sec. 3.3: the colour loss of
+ * every layer, L^l = (1 - lambda_ssim) L1 + lambda_ssim D-SSIM, weighted by lambda^l):
+ *   L = sum_{f,v,l} lambda^l [ (1 - lambda_ssim) mean |C^l - target|
+ *                              + lambda_ssim (1 - mean SSIM(C^l, target)) ]
+ * with the means over pixels and channels. SSIM is computed per channel with an 11 x 11
+ * Gaussian window (sigma 1.5) that sees zeros outside the image, C1 = 0.01^2, C2 = 0.03^2.
+ * lambda_ssim = 0 gives the L1 loss of gs_render_backward's fused mode.
+ *  s          width, height, n_levels and level_weights are used; the rest is ignored.
+ *  image      [n_frames][n_views][n_levels][3][height][width] (gs_render_forward's output)
+ *  target     [n_frames][n_views][3][height][width]
+ *  lambda_ssim in [0, 1] (the paper pre-trains with 0.2)
+ *  d_image    dL/dC in the image layout (overwritten), to pass to gs_render_backward; or NULL
+ *             for the loss alone (then ws may be NULL)
+ *  loss_out   one float, accumulated (+=) with L, or NULL
+ *  ws         workspace of gs_color_loss_workspace_size() bytes (three floats per image
+ *             element: the per-pixel SSIM derivatives); independent of the render workspace.
+ * Errors: GS_ERR_INVALID_ARG for sizes, NULL buffers or lambda_ssim outside [0, 1];
+ * GS_ERR_WORKSPACE when ws_bytes is too small. */
+int gs_color_loss_workspace_size(const gs_settings* s, int32_t n_frames, int32_t n_views, size_t* bytes_out);
+int gs_color_loss(const gs_settings* s, int32_t n_frames, int32_t n_views, const float* image, const float* target,
+                  float lambda_ssim, float* d_image, float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Autotuner of the render launch shapes (bin_chunk, row_seg, wave_layout of gs_settings) for
  * one workload: the a10 step of the hot path, with shapes picked by timed trials that must pass
  * parity. Starting from *s, it tries the wave layouts, then the binning chunk sizes, then the

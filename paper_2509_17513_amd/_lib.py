@@ -62,6 +62,8 @@ SIGNATURES = {
     "gs_render_backward": ([P, I32, P, I32, P, I32, P, P, P, P, P, P, P, P, SZ, P], ctypes.c_int),
     "gs_check_status": ([P, P, P], ctypes.c_int),
     "gs_autotune_render": ([P, I32, P, I32, P, I32, P, P, P, P, P, SZ, P, P, P], ctypes.c_int),
+    "gs_color_loss_workspace_size": ([P, I32, I32, P], ctypes.c_int),
+    "gs_color_loss": ([P, I32, I32, P, P, ctypes.c_float, P, P, P, SZ, P], ctypes.c_int),
     "gs_error_string": ([ctypes.c_int], ctypes.c_char_p),
     "gs_last_error": ([], ctypes.c_char_p),
     "gs_workspace_stats": ([P, P, P], ctypes.c_int),

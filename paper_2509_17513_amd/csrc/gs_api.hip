@@ -118,6 +118,10 @@ int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap
 
 }  // namespace
 
+int report_arg(const char* msg) { return fail_arg(msg); }
+int report_hip(hipError_t e, const char* where) { return fail_hip(e, where); }
+int require_device() { return check_device(); }
+
 
 // ------------------------------------------------------------ profiling
 namespace {
@@ -144,7 +148,8 @@ hipEvent_t prof_event() {
 const char* kKernelNames[K_COUNT] = {
     "compose_fwd", "project_fwd", "radix_hist", "radix_scan", "radix_scatter", "bin_count", "bin_chunk_scan",
     "tile_ranges", "bin_emit", "raster_fwd", "zero", "raster_bwd", "project_bwd", "compose_bwd", "rate_ctx",
-    "rate_mlp", "rate_hist_minmax", "rate_hist_count", "rate_hist_bits", "adam", "bin_gather", "row_count", "row_emit"};
+    "rate_mlp", "rate_hist_minmax", "rate_hist_count", "rate_hist_bits", "adam", "bin_gather", "row_count", "row_emit",
+    "ssim_fwd", "ssim_bwd"};
 }  // namespace
 
 int prof_begin(int id, hipStream_t st) {

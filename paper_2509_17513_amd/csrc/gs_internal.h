@@ -80,4 +80,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // order-sensitive 64-bit checksum of n words (written to *out, which it zeroes first)
 hipError_t launch_checksum(const uint32_t* p, size_t n, unsigned long long* out, hipStream_t st);
 
+// ---- error reporting shared by the entry points of every source file (gs_api.hip) ----
+int report_arg(const char* msg);                      // sets gs_last_error, returns GS_ERR_INVALID_ARG
+int report_hip(hipError_t e, const char* where);      // sets gs_last_error, returns GS_ERR_HIP
+int require_device();                                 // GS_OK or GS_ERR_NO_DEVICE (checked once)
+
 }  // namespace gs

@@ -29,6 +29,8 @@ enum KernelId {
   K_BIN_GATHER,
   K_ROW_COUNT,
   K_ROW_EMIT,
+  K_SSIM_FWD,
+  K_SSIM_BWD,
   K_COUNT
 };
 

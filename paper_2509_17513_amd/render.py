@@ -203,6 +203,57 @@ def autotune(settings: RenderSettings, params: torch.Tensor, cams: torch.Tensor,
     return tuned, list(times)
 
 
+class LossWorkspace:
+    """Device workspace of gs_color_loss for one image shape (three floats per image element)."""
+
+    def __init__(self, settings: RenderSettings, n_images: int, device):
+        s = settings.c_struct(0 if not settings.level_counts else settings.level_counts[-1])
+        nbytes = ctypes.c_size_t()
+        check(lib().gs_color_loss_workspace_size(ctypes.byref(s), 1, n_images, ctypes.byref(nbytes)),
+              "gs_color_loss_workspace_size")
+        self.n_images = n_images
+        self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+
+    @property
+    def nbytes(self):
+        return self.buf.numel()
+
+
+def color_loss(settings: RenderSettings, image: torch.Tensor, target: torch.Tensor, lambda_ssim: float,
+               d_image: torch.Tensor | None = None, loss: torch.Tensor | None = None,
+               ws: LossWorkspace | None = None, grad: bool = True):
+    """Layer-weighted colour loss with its D-SSIM term (gs_color_loss).
+
+    image [..., L, 3, H, W] (the render's output), target [..., 3, H, W] with the same leading
+    images. Adds L to ``loss`` (one float) when given; returns dL/d image (for render_backward's
+    d_image), or None when grad is False. Needs a GPU; every step runs in the library's kernels."""
+    dev = image.device
+    L, H, W = settings.n_levels, settings.height, settings.width
+    if image.numel() % (L * 3 * H * W) or image.shape[-3:] != (3, H, W):
+        raise ValueError(f"image of shape {tuple(image.shape)} is not [..., {L}, 3, {H}, {W}]")
+    B = image.numel() // (L * 3 * H * W)
+    _check_tensor(image, "image", device=dev)
+    _check_tensor(target, "target", device=dev)
+    if target.numel() != B * 3 * H * W:
+        raise ValueError(f"target has {target.numel()} elements, expected {B} x 3 x {H} x {W}")
+    if grad:
+        if d_image is None:
+            d_image = torch.empty_like(image)
+        _check_tensor(d_image, "d_image", shape=image.shape, device=dev)
+        if ws is None or ws.n_images != B:
+            ws = LossWorkspace(settings, B, dev)
+    else:
+        d_image = None
+        if loss is None:
+            raise ValueError("nothing to compute: grad is False and loss is None")
+    _check_tensor(loss, "loss", device=dev)
+    s = settings.c_struct(0 if not settings.level_counts else settings.level_counts[-1])
+    check(lib().gs_color_loss(ctypes.byref(s), 1, B, _ptr(image), _ptr(target), float(lambda_ssim), _ptr(d_image),
+                              _ptr(loss), None if ws is None else _ptr(ws.buf), 0 if ws is None else ws.nbytes,
+                              _stream(dev)), "gs_color_loss")
+    return d_image
+
+
 class RenderFunction(torch.autograd.Function):
     """Differentiable render: params (and residuals) -> image [F][V][L][3][H][W]."""
 

@@ -21,7 +21,7 @@ import torch
 
 from . import _lib
 from ._lib import check, lib
-from .render import RenderSettings, Workspace, render_backward, render_forward
+from .render import LossWorkspace, RenderSettings, Workspace, color_loss, render_backward, render_forward
 
 W_PER_ATTR = 16 * 64 + 64 * 64 + 2 * 64
 B_PER_ATTR = 64 + 64 + 2
@@ -185,11 +185,12 @@ class LearningRates:
 
 
 class JointTrainer:
-    """Keyframe training with layer-weighted L1 and the learned rate on all views and layers at once."""
+    """Keyframe training on all views and layers at once: the layer-weighted colour loss (L1, plus
+    D-SSIM when lambda_ssim > 0) and the learned rate."""
 
     def __init__(self, params: torch.Tensor, cams: torch.Tensor, targets: torch.Tensor, settings: RenderSettings,
                  rate: RateModel | None, lambda_rate: float = 0.0, extent: float = 1.0,
-                 lrs: LearningRates | None = None, seed: int = 0):
+                 lrs: LearningRates | None = None, seed: int = 0, lambda_ssim: float = 0.0):
         self.p, self.cams, self.tgt, self.st = params, cams, targets, settings
         self.n = params.shape[1]
         self.rate, self.lam, self.extent = rate, lambda_rate, extent
@@ -203,13 +204,22 @@ class JointTrainer:
         self.img, self.ws = render_forward(settings, params, cams)  # sizes the workspace
         self.levels = list(settings.level_counts) if settings.level_counts else [self.n]
         self.level_w = list(settings.level_weights) if settings.level_weights else [1.0] * len(self.levels)
+        self.lambda_ssim = lambda_ssim
+        if lambda_ssim > 0:
+            self.d_img = torch.empty_like(self.img)
+            self.loss_ws = LossWorkspace(settings, cams.shape[0], params.device)
 
     def step(self, check_overflow: bool = False):
         n = self.n
         zero(self.loss)
         render_forward(self.st, self.p, self.cams, ws=self.ws, image=self.img, check_overflow=check_overflow)
-        render_backward(self.st, self.p, self.cams, self.ws, image=self.img, target=self.tgt, d_params=self.dp,
-                        loss=self.loss)
+        if self.lambda_ssim > 0:
+            color_loss(self.st, self.img, self.tgt, self.lambda_ssim, d_image=self.d_img, loss=self.loss,
+                       ws=self.loss_ws)
+            render_backward(self.st, self.p, self.cams, self.ws, d_image=self.d_img, d_params=self.dp)
+        else:
+            render_backward(self.st, self.p, self.cams, self.ws, image=self.img, target=self.tgt, d_params=self.dp,
+                            loss=self.loss)
         if self.rate is not None:
             self.rate.reset()
             context(self.p, self.extent, self.levels, self.ctx)

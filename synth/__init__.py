@@ -160,6 +160,36 @@ def target_images(n_images: int, width: int, height: int, seed: int) -> np.ndarr
     return np.ascontiguousarray(rng.uniform(0.0, 1.0, (n_images, 3, height, width)).astype(np.float32))
 
 
+def loss_images(n_images: int, n_levels: int, width: int, height: int, seed: int):
+    """Render-like colour layers and targets for the colour-loss path, float32 in [0, 1]:
+    image [n_images][n_levels][3][height][width], target [n_images][3][height][width].
+
+    The target is a few smooth colour blobs with fine texture over a flat background; every
+    layer reproduces the background exactly (ties with the target, flat windows) and the blobs
+    with detail and accuracy that grow with the layer index, like the nested layers of a
+    hierarchy (no layer equals the target)."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float32) + 0.5
+    img = np.empty((n_images, n_levels, 3, height, width), np.float32)
+    tgt = np.empty((n_images, 3, height, width), np.float32)
+    for b in range(n_images):
+        field = np.zeros((3, height, width), np.float32)
+        for _ in range(8):
+            cx, cy = rng.uniform(0, width), rng.uniform(0, height)
+            s = rng.uniform(2.0, 0.15 * max(width, height) + 2.0)
+            amp = rng.uniform(0.1, 0.7, 3).astype(np.float32)
+            field += amp[:, None, None] * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2.0 * s * s))
+        fg = field.sum(axis=0) > 0.15
+        bg = rng.uniform(0.0, 1.0, 3).astype(np.float32)[:, None, None]
+        tex = rng.uniform(-0.15, 0.15, (3, height, width)).astype(np.float32)
+        tgt[b] = np.where(fg, np.clip(bg * 0.3 + field + tex, 0.0, 1.0), bg)
+        for l in range(n_levels):
+            keep = (l + 1) / (n_levels + 1)
+            err = rng.uniform(-0.05, 0.05, (3, height, width)).astype(np.float32) * (1.0 - keep)
+            img[b, l] = np.where(fg, np.clip(bg * 0.3 + field + keep * tex + err, 0.0, 1.0), bg)
+    return np.ascontiguousarray(img), np.ascontiguousarray(tgt)
+
+
 @dataclasses.dataclass
 class Workload:
     """One seeded workload: params, optional residuals, cameras [F*V][16], image size, levels."""

@@ -1,0 +1,286 @@
+"""GPU parity of the colour loss with its D-SSIM term (gs_color_loss through the C ABI) against
+the FP64 oracle.
+
+Bars, from the FP32 arithmetic of the kernels:
+* loss: the windowed moments come out of two 11-tap FP32 passes, so E_xx, mu_x^2 (and the rest)
+  carry relative errors below 45 units of 2^-24; the variances E_xx - mu_x^2 turn these into
+  absolute errors that S feels through A2 and B2 (largest in flat windows, where B2 ~ C2). The
+  bound is evaluated per pixel from the oracle's FP64 moments and summed like the loss. On
+  images with content (noise, render-like layers) the rounding errors of different pixels are
+  independent and cancel in the mean, and those cases must also be within 1e-5 relative; only
+  constant images make them systematic (the constant case's error is 1e-4 relative).
+* dL/dC: every (image, layer, channel) plane within 1e-3 of its gradient scale, the larger of its
+  largest oracle gradient and lambda^l / (3 H W) (the L1 gradient of one pixel). The worst case
+  an FP32 emulation of the kernels finds is 2.2e-4, on constant images (flat windows).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import ssim as OS
+from parity import gpu_settings, grad_mismatch, image_mismatch, oracle_settings, param_groups
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+U = 2.0 ** -24
+
+
+def _loss_bound(img, tgt, lw, lam):
+    """FP32 rounding bound of the loss (see the module docstring), from FP64 moments."""
+    B, L, _, H, W = img.shape
+    tot = 0.0
+    for b in range(B):
+        y = tgt[b].astype(np.float64)
+        mu2, eyy = OS.blur(y), OS.blur(y * y)
+        for l in range(L):
+            x = img[b, l].astype(np.float64)
+            mu1, exx, exy = OS.blur(x), OS.blur(x * x), OS.blur(x * y)
+            A1 = 2 * mu1 * mu2 + OS.C1
+            B1 = mu1 * mu1 + mu2 * mu2 + OS.C1
+            B2 = exx - mu1 * mu1 + eyy - mu2 * mu2 + OS.C2
+            S = A1 * (2 * (exy - mu1 * mu2) + OS.C2) / (B1 * B2)
+            dB2 = 45 * U * (exx + eyy + mu1 * mu1 + mu2 * mu2)
+            dA2 = 2 * 45 * U * (np.abs(exy) + np.abs(mu1 * mu2))
+            dS = np.abs(A1) / (B1 * B2) * dA2 + np.abs(S) / B2 * dB2 + 8 * U
+            tot += lw[l] * (lam * dS.mean() + 4 * U)
+    return tot
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    return torch.device("cuda:0")
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _settings(w, h, lw):
+    from paper_2509_17513_amd import RenderSettings
+    return RenderSettings(w, h, 0, tuple([1] * len(lw)), tuple(lw))
+
+
+def _gpu_loss(img, tgt, lw, lam, grad=True):
+    from paper_2509_17513_amd import color_loss
+    dev = _dev()
+    H, W = img.shape[-2:]
+    it, tt = torch.from_numpy(img).to(dev), torch.from_numpy(tgt).to(dev)
+    loss = torch.zeros(1, device=dev)
+    d = color_loss(_settings(W, H, lw), it, tt, lam, loss=loss, grad=grad)
+    torch.cuda.synchronize()
+    return loss.item(), (None if d is None else d.cpu().numpy().astype(np.float64))
+
+
+def _check(img, tgt, lw, lam, loss, g, content=False):
+    ref_loss, ref_g = OS.color_loss(img.astype(np.float64), tgt.astype(np.float64), lw, lam)
+    B, L, _, H, W = img.shape
+    tol = 1e-6 * abs(ref_loss) + _loss_bound(img, tgt, lw, lam)
+    assert abs(loss - ref_loss) <= tol, (loss, ref_loss, tol)
+    if content:
+        assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
+    worst = 0.0
+    for b in range(B):
+        for l in range(L):
+            for c in range(3):
+                r = ref_g[b, l, c]
+                scale = max(np.abs(r).max(), lw[l] / (3 * H * W))
+                e = np.abs(g[b, l, c] - r).max()
+                worst = max(worst, e / scale)
+                assert e <= GRAD_TOL * scale, (b, l, c, e, scale)
+    print(f"loss {loss:.7g} (oracle {ref_loss:.7g}, error {abs(loss - ref_loss):.2e}, bound {tol:.2e}), "
+          f"worst plane error {worst:.2e} of its scale")
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.2, 1.0])
+def test_color_loss_matches_oracle_ragged_tiles(lam):
+    _case(f"colour loss 2 images x 3 layers 150x70 (ragged 64x32 tiles), lambda_ssim={lam}")
+    img, tgt = synth.loss_images(2, 3, 150, 70, seed=5)
+    lw = [0.25, 0.5, 1.0]
+    loss, g = _gpu_loss(img, tgt, lw, lam)
+    _check(img, tgt, lw, lam, loss, g, content=True)
+
+
+def test_color_loss_noise_images():
+    _case("colour loss on uniform noise 1 image x 2 layers 97x45, lambda_ssim=0.2")
+    rng = np.random.default_rng(9)
+    img = rng.uniform(0, 1, (1, 2, 3, 45, 97)).astype(np.float32)
+    tgt = rng.uniform(0, 1, (1, 3, 45, 97)).astype(np.float32)
+    loss, g = _gpu_loss(img, tgt, [0.5, 1.0], 0.2)
+    _check(img, tgt, [0.5, 1.0], 0.2, loss, g, content=True)
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (5, 3), (11, 11), (64, 32), (65, 33), (3, 200)])
+def test_color_loss_small_and_exact_tile_sizes(wh):
+    W, H = wh
+    _case(f"colour loss {W}x{H}, 2 layers, lambda_ssim=0.2")
+    img, tgt = synth.loss_images(1, 2, W, H, seed=W * 1000 + H)
+    loss, g = _gpu_loss(img, tgt, [0.5, 1.0], 0.2)
+    _check(img, tgt, [0.5, 1.0], 0.2, loss, g)
+
+
+def test_identical_and_constant_images():
+    _case("colour loss: image == target gives zero; constant images give the closed form")
+    img, tgt = synth.loss_images(1, 1, 80, 40, seed=3)
+    loss, g = _gpu_loss(tgt[:, None].copy(), tgt, [1.0], 1.0)
+    # exact arithmetic gives 0; in FP32 the three blurred terms (each up to ~0.1 here) cancel to
+    # rounding, and 1 - S to a few units of 2^-24
+    assert abs(loss) <= 1e-6 and np.abs(g).max() <= 1e-6, (loss, np.abs(g).max())
+    a, b = 0.3, 0.8
+    x = np.full((1, 1, 3, 40, 80), a, np.float32)
+    y = np.full((1, 3, 40, 80), b, np.float32)
+    loss, g = _gpu_loss(x, y, [1.0], 1.0)
+    _check(x, y, [1.0], 1.0, loss, g)
+
+
+def test_loss_only_mode_and_accumulation():
+    _case("colour loss: loss without gradient, accumulated over two calls")
+    from paper_2509_17513_amd import color_loss
+    dev = _dev()
+    img, tgt = synth.loss_images(2, 2, 70, 50, seed=13)
+    it, tt = torch.from_numpy(img).to(dev), torch.from_numpy(tgt).to(dev)
+    loss = torch.zeros(1, device=dev)
+    st = _settings(70, 50, [0.5, 1.0])
+    assert color_loss(st, it, tt, 0.2, loss=loss, grad=False) is None
+    color_loss(st, it, tt, 0.2, loss=loss, grad=False)
+    torch.cuda.synchronize()
+    ref, _ = OS.color_loss(img.astype(np.float64), tgt.astype(np.float64), [0.5, 1.0], 0.2)
+    assert abs(loss.item() - 2 * ref) <= 2e-5 * ref + 1e-6
+
+
+def test_batched_images_equal_single_image_calls():
+    _case("colour loss: 4 images in one call == 4 single-image calls, bit for bit")
+    from paper_2509_17513_amd import color_loss
+    dev = _dev()
+    img, tgt = synth.loss_images(4, 2, 130, 66, seed=21)
+    it, tt = torch.from_numpy(img).to(dev), torch.from_numpy(tgt).to(dev)
+    st = _settings(130, 66, [0.5, 1.0])
+    loss = torch.zeros(1, device=dev)
+    d_all = color_loss(st, it, tt, 0.2, loss=loss)
+    parts, tot = [], 0.0
+    for b in range(4):
+        lb = torch.zeros(1, device=dev)
+        parts.append(color_loss(st, it[b:b + 1].contiguous(), tt[b:b + 1].contiguous(), 0.2, loss=lb))
+        torch.cuda.synchronize()
+        tot += lb.item()
+    torch.cuda.synchronize()
+    assert torch.equal(d_all, torch.cat(parts))
+    assert abs(loss.item() - tot) <= 1e-6 * tot
+
+
+def _ring(n=1500, seed=53, w=128, h=80):
+    p = synth.cube_scene(n, seed, 3)
+    cams = synth.ring_cameras([0, 5], 24, 4.0, w, h)
+    lv = synth.nested_levels(n)
+    lw = synth.paper_level_weights(len(lv))
+    tgt = synth.target_images(2, w, h, seed + 1)
+    return synth.Workload("ring", p, cams, w, h, 3, lv, lw, target=tgt)
+
+
+def test_lambda0_gradient_is_the_l1_gradient_bit_for_bit():
+    _case("colour loss with lambda_ssim = 0: d_image == lambda^l sign(C - target) / (3 H W) bit for bit")
+    img, tgt = synth.loss_images(2, 3, 100, 60, seed=23)
+    lw = [0.25, 0.5, 1.0]
+    _, g = _gpu_loss(img, tgt, lw, 0.0)
+    # FP32 products of the same rounded factors
+    inv_n = np.float32(1.0 / (3 * 100 * 60))
+    w = np.array(lw, np.float32).reshape(1, -1, 1, 1, 1)
+    exp = (w * inv_n) * np.sign(img - tgt[:, None]).astype(np.float32)
+    assert np.array_equal(g.astype(np.float32), exp)
+
+
+def test_lambda0_backward_equals_fused_l1_backward():
+    _case("colour loss with lambda_ssim = 0 + backward(d_image) == fused L1 backward (GPU vs GPU)")
+    from paper_2509_17513_amd import color_loss, render_backward, render_forward
+    dev = _dev()
+    w = _ring()
+    st = gpu_settings(w)
+    p, c = torch.from_numpy(w.params).to(dev), torch.from_numpy(w.cams).to(dev)
+    tgt = torch.from_numpy(w.target).to(dev)
+    img, ws = render_forward(st, p, c)
+    l1 = torch.zeros(1, device=dev)
+    dp1, _ = render_backward(st, p, c, ws, image=img, target=tgt, loss=l1)
+    l2 = torch.zeros(1, device=dev)
+    d_image = color_loss(st, img, tgt, 0.0, loss=l2)
+    dp2, _ = render_backward(st, p, c, ws, d_image=d_image)
+    torch.cuda.synchronize()
+    # the backward accumulates with float atomics, so two runs agree to rounding, not bit for bit
+    a, b = dp1.cpu().numpy(), dp2.cpu().numpy()
+    assert np.allclose(a, b, rtol=1e-5, atol=1e-7 * np.abs(b).max())
+    assert abs(l1.item() - l2.item()) <= 1e-5 * l1.item()
+
+
+def test_render_with_dssim_gradients_match_oracle():
+    _case("render + colour loss (lambda_ssim = 0.2) + backward vs oracle render, loss and backward")
+    from paper_2509_17513_amd import color_loss, render_backward, render_forward
+    dev = _dev()
+    w = _ring(n=2000, seed=57, w=160, h=96)
+    st = gpu_settings(w)
+    p, c = torch.from_numpy(w.params).to(dev), torch.from_numpy(w.cams).to(dev)
+    tgt = torch.from_numpy(w.target).to(dev)
+    img, ws = render_forward(st, p, c)
+    loss = torch.zeros(1, device=dev)
+    d_image = color_loss(st, img, tgt, 0.2, loss=loss)
+    dp, _ = render_backward(st, p, c, ws, d_image=d_image)
+    torch.cuda.synchronize()
+    ost = oracle_settings(w)
+    ref = oracle.render(ost, w.params, w.cams, variants=True)
+    gi = img.cpu().numpy().reshape(ref["image"].shape)
+    bad, _, _, _ = image_mismatch(gi, ref)
+    assert bad == 0
+    ref_loss, dimg = OS.color_loss(ref["image"], w.target.astype(np.float64), w.level_weights, 0.2)
+    assert abs(loss.item() - ref_loss) <= 1e-4 * ref_loss, (loss.item(), ref_loss)
+    dp_ref, _, _ = oracle.backward(ost, w.params, w.cams, dimg)
+    bad, worst = grad_mismatch(dp.cpu().numpy().astype(np.float64), dp_ref, param_groups(w.sh_degree))
+    print(f"grad bad={bad} of {dp.numel()} worst_ratio={worst:.3g}")
+    assert bad <= 1e-3 * dp.numel()
+
+
+def test_fullsize_24views_6layers_960x540_sampled():
+    """The launch the benchmark times (24 views x 6 layers at 960x540, lambda_ssim = 0.2), checked
+    at sampled pixels: the gradient of a pixel depends only on the image within 10 pixels, so the
+    oracle run on a crop of radius 14 gives the exact gradient on the crop's central 9 x 9 block
+    (rescaled from the crop's mean to the image's mean)."""
+    _case("colour loss full size: 24 views x 6 layers x 960x540, lambda_ssim=0.2, sampled")
+    from paper_2509_17513_amd import color_loss
+    dev = _dev()
+    B, L, W, H, lam = 24, 6, 960, 540, 0.2
+    lw = synth.paper_level_weights(L)
+    img, tgt = synth.loss_images(B, L, W, H, seed=31)
+    it, tt = torch.from_numpy(img).to(dev), torch.from_numpy(tgt).to(dev)
+    st = _settings(W, H, lw)
+    loss = torch.zeros(1, device=dev)
+    d = color_loss(st, it, tt, lam, loss=loss)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    samples = [(0, 0, 0, 0), (B - 1, L - 1, H - 1, W - 1), (3, 2, 0, W - 1), (5, 5, H - 1, 0), (7, 1, 270, 64)]
+    samples += [(int(rng.integers(B)), int(rng.integers(L)), int(rng.integers(H)), int(rng.integers(W)))
+                for _ in range(40)]
+    n_full = 3 * H * W
+    R, K = 14, 4
+    for (b, l, y, x) in samples:
+        y0, y1, x0, x1 = max(0, y - R), min(H, y + R + 1), max(0, x - R), min(W, x + R + 1)
+        ci = img[b, l, :, y0:y1, x0:x1][None, None].astype(np.float64)
+        ct = tgt[b, :, y0:y1, x0:x1][None].astype(np.float64)
+        _, g = OS.color_loss(ci, ct, [lw[l]], lam)
+        g = g[0, 0] * (3 * (y1 - y0) * (x1 - x0)) / n_full
+        by0, by1, bx0, bx1 = max(0, y - K), min(H, y + K + 1), max(0, x - K), min(W, x + K + 1)
+        ref = g[:, by0 - y0:by1 - y0, bx0 - x0:bx1 - x0]
+        got = d[b, l, :, by0:by1, bx0:bx1].cpu().numpy().astype(np.float64)
+        tol = GRAD_TOL * max(np.abs(ref).max(), lw[l] / n_full)
+        assert np.abs(got - ref).max() <= tol, ((b, l, y, x), np.abs(got - ref).max(), tol)
+    print(f"{len(samples)} sampled 9x9 blocks within {GRAD_TOL} of their gradient scale", flush=True)
+    # the loss: per-view calls add up to the batched one, and two views agree with the oracle
+    tot = 0.0
+    for b in range(B):
+        lb = torch.zeros(1, device=dev)
+        color_loss(st, it[b:b + 1].contiguous(), tt[b:b + 1].contiguous(), lam, loss=lb, grad=False)
+        torch.cuda.synchronize()
+        tot += lb.item()
+        if b in (0, 17):
+            ref_loss, _ = OS.color_loss(img[b:b + 1].astype(np.float64), tgt[b:b + 1].astype(np.float64), lw, lam)
+            tol = 1e-6 * ref_loss + _loss_bound(img[b:b + 1], tgt[b:b + 1], lw, lam)
+            assert abs(lb.item() - ref_loss) <= tol, (b, lb.item(), ref_loss, tol)
+    assert abs(loss.item() - tot) <= 1e-5 * tot, (loss.item(), tot)
