@@ -71,9 +71,9 @@ def code_text(src: str) -> str:
 
 
 def source_hash(read=None):
-    """Hash of the code of the render kernels and their host orchestration."""
+    """Hash of the code of the render and loss kernels and their host orchestration."""
     h = hashlib.sha256()
-    for f in ("gs_render.hip", "gs_api.hip", "gs_internal.h"):
+    for f in ("gs_render.hip", "gs_api.hip", "gs_internal.h", "gs_loss.hip"):
         if read is None:
             with open(os.path.join(ROOT, "paper_2509_17513_amd", "csrc", f)) as fh:
                 txt = fh.read()
@@ -481,7 +481,8 @@ def main():
             if k in sk:
                 t = sk[k] * 1e-3
                 ssim_k[k] = {"ms_per_launch": sk[k], "alu_frac": ops / t / ALU_PEAK_OPS,
-                             "hbm_frac": by / t / 1e9 / HBM_PEAK_GBS, "ops": ops, "bytes": by}
+                             "hbm_frac": by / t / 1e9 / HBM_PEAK_GBS, "ops": ops, "bytes": by,
+                             "traffic": read_traffic(k)}
         out["dssim"] = {"lambda_ssim": lam, "ms_loss": ms_loss, "ms_per_step": ms_ssim_step,
                         "ms_per_view": ms_ssim_step / B, "kernels": ssim_k}
         log(f"[bench] D-SSIM loss {ms_loss:.3f} ms, step with D-SSIM {ms_ssim_step:.3f} ms ({ssim_k})")

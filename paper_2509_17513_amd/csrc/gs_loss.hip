@@ -10,12 +10,13 @@
 // (the window is symmetric, so the zero-padded G* is its own adjoint).
 //
 // Two kernels, both bound by their VALU work:
-//  ssim_fwd  one block per (view, channel, 64 x TH tile), looping over the layers: the target's
+//  ssim_fwd  one block per (view, channel, 64 x 24 tile), looping over the layers: the target's
 //            windowed moments are made once per tile, each layer stages its tile (with a 5-pixel
 //            halo) in LDS, runs the row pass of x, x^2, x y and the column pass, and writes the
 //            three gradient maps a, b, c (already scaled by the loss weight) and adds its loss.
-//  ssim_bwd  one block per (view, layer, channel, tile): the row and column passes of a, b and c,
-//            combined with the L1 term into dL/dC.
+//  ssim_bwd  one block per (view, layer, channel, 64 x 32 tile): the row and column passes of a,
+//            b and c, combined with the L1 term into dL/dC.
+// Both fetch the next region (layer or map) into registers while the current one is processed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -32,7 +33,9 @@ constexpr int kWinN = 2 * kWinR + 1;
 constexpr int kLossTW = 64;                 // tile columns: one per lane
 constexpr int kRegW = kLossTW + 2 * kWinR;  // staged columns (74)
 constexpr int kRegStride = 76;              // LDS row stride in floats: 16-byte aligned rows
-constexpr int kLossTH = 32;                 // tile rows; each of the four waves owns kLossTH / 4 of them
+// tile rows of the two kernels; each of the four waves of a block owns a quarter of them
+constexpr int kFwdTH = 24;
+constexpr int kBwdTH = 32;
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -43,7 +46,7 @@ struct LossArgs {
   float* d_image;       // [B][L][3][H][W]
   float* loss_out;      // one float (+=), or NULL
   size_t map_stride;    // floats per gradient map (B L 3 H W)
-  int W, H, B, L, tiles_x, tiles, per_xcd;
+  int W, H, B, L, tiles_x, tiles, per_xcd;  // tiles (per image plane) and per_xcd: set per launch
   float lambda_ssim, inv_n;  // inv_n = 1 / (3 H W): the means run over pixels and channels
   float lw[kMaxLevels];
   float g[kWinN];
@@ -52,18 +55,47 @@ struct LossArgs {
 // Consecutive blocks land on the same XCD, so tiles that share halo rows share that XCD's L2.
 __device__ __forceinline__ int xcd_block(int bid, int per_xcd) { return (bid & 7) * per_xcd + (bid >> 3); }
 
-// Stages the (TH + 10) x 74 region around a tile; pixels outside the image read as zero.
+// The (TH + 10) x 74 region around a tile is fetched into registers (kRegion<TH> values per
+// thread) and stored to LDS later, so that the loads of the next region are in flight while the
+// current one is processed. Where each value comes from and goes to depends only on the thread
+// and the tile, so it is worked out once per block: the offset in the image plane (-1 outside
+// the image, which reads as zero) and the LDS offset.
 template <int TH>
-__device__ __forceinline__ void stage_region(float* __restrict__ s, const float* __restrict__ src, int x0, int y0,
-                                             int W, int H) {
-  constexpr int RH = TH + 2 * kWinR;
-  for (int idx = threadIdx.x; idx < RH * kRegW; idx += 256) {
+constexpr int kRegion = ((TH + 2 * kWinR) * kRegW + 255) / 256;
+
+template <int TH>
+struct RegionMap {
+  int src[kRegion<TH>];
+  int lds[kRegion<TH>];  // -1: no value for this thread
+};
+
+template <int TH>
+__device__ __forceinline__ void region_map(RegionMap<TH>& m, int x0, int y0, int W, int H) {
+  constexpr int N = (TH + 2 * kWinR) * kRegW;
+#pragma unroll
+  for (int k = 0; k < kRegion<TH>; ++k) {
+    const int idx = threadIdx.x + 256 * k;
     const int r = idx / kRegW, c = idx - r * kRegW;
     const int gy = y0 - kWinR + r, gx = x0 - kWinR + c;
-    float v = 0.f;
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = src[(size_t)gy * W + gx];
-    s[r * kRegStride + c] = v;
+    const bool in = idx < N && gy >= 0 && gy < H && gx >= 0 && gx < W;
+    m.src[k] = in ? gy * W + gx : -1;
+    m.lds[k] = idx < N ? r * kRegStride + c : -1;
   }
+}
+
+template <int TH>
+__device__ __forceinline__ void fetch_region(float (&v)[kRegion<TH>], const RegionMap<TH>& m,
+                                             const float* __restrict__ src) {
+#pragma unroll
+  for (int k = 0; k < kRegion<TH>; ++k) v[k] = m.src[k] >= 0 ? src[m.src[k]] : 0.f;
+}
+
+template <int TH>
+__device__ __forceinline__ void store_region(float* __restrict__ s, const float (&v)[kRegion<TH>],
+                                             const RegionMap<TH>& m) {
+#pragma unroll
+  for (int k = 0; k < kRegion<TH>; ++k)
+    if (m.lds[k] >= 0) s[m.lds[k]] = v[k];
 }
 
 // The 14 staged values row r, columns 4j .. 4j + 13: the inputs of four row-pass outputs.
@@ -128,7 +160,13 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const LossArgs a) {
   for (int k = 0; k < kWinN; ++k) g[k] = a.g[k];
 
   // windowed moments of the target, shared by every layer
-  stage_region<TH>(s_y, a.target + (size_t)bc * HW, x0, y0, a.W, a.H);
+  RegionMap<TH> rm;
+  region_map<TH>(rm, x0, y0, a.W, a.H);
+  float pre[kRegion<TH>];
+  fetch_region<TH>(pre, rm, a.target + (size_t)bc * HW);
+  store_region<TH>(s_y, pre, rm);
+  const size_t plane0 = (size_t)b * a.L * 3 + ch;  // plane of layer l: plane0 + 3 l
+  fetch_region<TH>(pre, rm, a.image + plane0 * HW);
   __syncthreads();
   for (int it = t; it < RH * 16; it += 256) {
     const int r = it >> 4, j = it & 15;
@@ -151,8 +189,9 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const LossArgs a) {
 
   for (int l = 0; l < a.L; ++l) {
     __syncthreads();  // the previous layer's row-pass buffers and staged tile are consumed
-    const size_t plane = ((size_t)b * a.L + l) * 3 + ch;
-    stage_region<TH>(s_x, a.image + plane * HW, x0, y0, a.W, a.H);
+    const size_t plane = plane0 + 3 * (size_t)l;
+    store_region<TH>(s_x, pre, rm);
+    if (l + 1 < a.L) fetch_region<TH>(pre, rm, a.image + (plane + 3) * HW);
     __syncthreads();
     for (int it = t; it < RH * 16; it += 256) {
       const int r = it >> 4, j = it & 15;
@@ -186,7 +225,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const LossArgs a) {
       const float A2 = 2.f * (exy[i] - m12) + kC2;
       const float B1 = m11 + m22 + kC1;
       const float B2 = (exx[i] - m11) + (eyy[i] - m22) + kC2;
-      const float rB1 = 1.f / B1, rB2 = 1.f / B2;
+      const float rB1 = __builtin_amdgcn_rcpf(B1), rB2 = __builtin_amdgcn_rcpf(B2);  // 1 ulp
       const float S = A1 * A2 * rB1 * rB2;
       loss += wl * ((1.f - lam) * fabsf(xv - yv[i]) + lam * (1.f - S));
       if (a.maps) {
@@ -247,14 +286,21 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const LossArgs a) {
     }
   };
   const float* maps = a.maps + (size_t)plane * HW;
-  stage_region<TH>(s_r, maps, x0, y0, a.W, a.H);
+  RegionMap<TH> rm;
+  region_map<TH>(rm, x0, y0, a.W, a.H);
+  float pre[kRegion<TH>];
+  fetch_region<TH>(pre, rm, maps);
+  store_region<TH>(s_r, pre, rm);
+  fetch_region<TH>(pre, rm, maps + a.map_stride);
   __syncthreads();
   rows();
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    // the staged map is consumed by the row pass: stage the next one while the columns run
-    if (q < 2) stage_region<TH>(s_r, maps + (size_t)(q + 1) * a.map_stride, x0, y0, a.W, a.H);
+    // the staged map is consumed by the row pass: store the next one (fetched during the row
+    // pass) and fetch the one after while the columns run
+    if (q < 2) store_region<TH>(s_r, pre, rm);
+    if (q < 1) fetch_region<TH>(pre, rm, maps + 2 * a.map_stride);
     float o[MR];
     col_pass<MR>(s_h, c, r0, g, o);
 #pragma unroll
@@ -282,13 +328,15 @@ int loss_dims(const gs_settings* s, int32_t F, int32_t V, LossArgs& a) {
   if (F < 1 || V < 1) return report_arg("n_frames and n_views must be >= 1");
   if (s->width < 1 || s->height < 1) return report_arg("width and height must be >= 1");
   if (s->n_levels < 1 || s->n_levels > kMaxLevels) return report_arg("n_levels must be in 1..8");
+  if ((int64_t)s->width * s->height >= ((int64_t)1 << 31)) return report_arg("image plane of 2^31 pixels or more");
   a.W = s->width;
   a.H = s->height;
   a.B = F * V;
   a.L = s->n_levels;
   a.tiles_x = (a.W + kLossTW - 1) / kLossTW;
-  a.tiles = a.tiles_x * ((a.H + kLossTH - 1) / kLossTH);
-  if ((int64_t)F * V * a.L * 3 * a.tiles > (int64_t)0x7FFFFFF0) return report_arg("image batch too large");
+  const int min_th = kFwdTH < kBwdTH ? kFwdTH : kBwdTH;
+  if ((int64_t)F * V * a.L * 3 * a.tiles_x * ((a.H + min_th - 1) / min_th) > (int64_t)0x7FFFFFF0)
+    return report_arg("image batch too large");
   for (int l = 0; l < kMaxLevels; ++l) a.lw[l] = l < a.L ? s->level_weights[l] : 0.f;
   a.map_stride = (size_t)a.B * a.L * 3 * a.W * a.H;
   a.inv_n = (float)(1.0 / (3.0 * (double)a.W * (double)a.H));
@@ -343,17 +391,19 @@ int gs_color_loss(const gs_settings* s, int32_t n_frames, int32_t n_views, const
   hipStream_t st = (hipStream_t)stream;
   {
     ProfScope ps_(K_SSIM_FWD, st);
+    a.tiles = a.tiles_x * ((a.H + kFwdTH - 1) / kFwdTH);
     const int n_blocks = a.B * 3 * a.tiles;
     a.per_xcd = (n_blocks + 7) / 8;
-    hipLaunchKernelGGL(k_ssim_fwd<kLossTH>, dim3(8 * a.per_xcd), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_ssim_fwd<kFwdTH>, dim3(8 * a.per_xcd), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return report_hip(e, "ssim_fwd");
   }
   if (d_image) {
     ProfScope ps_(K_SSIM_BWD, st);
+    a.tiles = a.tiles_x * ((a.H + kBwdTH - 1) / kBwdTH);
     const int n_blocks = a.B * a.L * 3 * a.tiles;
     a.per_xcd = (n_blocks + 7) / 8;
-    hipLaunchKernelGGL(k_ssim_bwd<kLossTH>, dim3(8 * a.per_xcd), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_ssim_bwd<kBwdTH>, dim3(8 * a.per_xcd), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return report_hip(e, "ssim_bwd");
   }
