@@ -9,6 +9,23 @@ import oracle
 IMG_TOL = 1e-4  # max-abs on [0, 1] colours
 
 
+def atomic_order_close(a, b, rel=1e-5):
+    """Two runs of the backward, which accumulates with float atomics in whatever order the
+    hardware gives: each gradient is a float sum of n terms, and reordering such a sum moves it
+    by at most about n u T (T the largest term, u = 2^-24), far more than its own magnitude when
+    the terms cancel. So every element must agree within rel of itself plus rel of the largest
+    gradient of its parameter row ([C][n] layout, one row per parameter channel).
+    Returns (ok, worst ratio of the difference to that bar)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    row = np.abs(b).reshape(b.shape[0], -1).max(axis=1).reshape((-1,) + (1,) * (b.ndim - 1))
+    bar = rel * np.abs(b) + rel * row
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(bar > 0, np.abs(a - b) / bar, np.where(a == b, 0.0, np.inf))
+    worst = float(ratio.max()) if ratio.size else 0.0
+    return worst <= 1.0, worst
+
+
 def oracle_settings(w, **kw):
     return oracle.Settings(width=w.width, height=w.height, sh_degree=w.sh_degree, level_counts=tuple(w.level_counts),
                            res_channels=0 if w.residuals is None else w.residuals.shape[1], **kw)

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import synth
-from parity import gpu_settings
+from parity import atomic_order_close, gpu_settings
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +49,9 @@ def test_graph_replays_match_eager():
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(img, img_ref), r
-        assert torch.allclose(dp, dp_ref, rtol=1e-5, atol=1e-7 * float(dp_ref.abs().max())), r
+        ok, worst = atomic_order_close(dp.cpu().numpy(), dp_ref.cpu().numpy())
+        print(f"replay {r}: gradients within {worst:.3f} of the atomic-order bar", flush=True)
+        assert ok, (r, worst)
         assert loss.item() > 0
         # eager work on another workspace between replays
         render_forward(st, pt, ct, ws=other_ws)
