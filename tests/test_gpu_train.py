@@ -75,3 +75,30 @@ def test_joint_training_and_rate_network_gain():
           f"(vs {R_hist:.0f}, {(hist1.sum() - R_hist) / R_hist:+.4f})", flush=True)
     assert hist1.sum() < R_hist
     assert l1[-1] < 1.25 * l0[-1]
+
+
+def _dssim(tr):
+    """Layer-weighted D-SSIM of the trainer's current render (gs_color_loss, lambda_ssim = 1)."""
+    from paper_2509_17513_amd import color_loss, render_forward
+    render_forward(tr.st, tr.p, tr.cams, ws=tr.ws, image=tr.img)
+    v = torch.zeros(1, device=tr.p.device)
+    color_loss(tr.st, tr.img, tr.tgt, 1.0, loss=v, grad=False)
+    return float(v.item())
+
+
+def test_training_with_dssim_term():
+    print("\n[case] keyframe training with the D-SSIM term (lambda_ssim = 0.2) vs without", flush=True)
+    from paper_2509_17513_amd.train import JointTrainer
+    res = {}
+    for lam in (0.0, 0.2):
+        tr = _setup(0.0)
+        tr = JointTrainer(tr.p, tr.cams, tr.tgt, tr.st, None, lambda_ssim=lam, seed=91)
+        d0 = _dssim(tr)
+        losses = _train(tr, 60)
+        res[lam] = (losses, d0, _dssim(tr))
+        print(f"lambda_ssim={lam}: loss {[round(x, 5) for x in losses]}, D-SSIM {d0:.5f} -> {res[lam][2]:.5f}",
+              flush=True)
+    losses, d0, d1 = res[0.2]
+    assert losses[-1] < 0.9 * losses[0]
+    assert d1 < d0
+    print(f"D-SSIM after 60 steps: {res[0.2][2]:.5f} with the term, {res[0.0][2]:.5f} without", flush=True)
