@@ -98,6 +98,63 @@ def read_traffic(kernel):
     return rec.get("traffic_bytes_per_launch")
 
 
+def significance_sorted(torch, dev, p_host):
+    """The Gaussians in decreasing significance, ranked by the library (gs_significance_order), so
+    that the nested levels are the method's hierarchy; done once, outside every timed region."""
+    import numpy as np
+
+    from paper_2509_17513_amd.bitstream import significance_order
+    order = significance_order(torch.from_numpy(p_host).to(dev)).cpu().numpy()
+    return np.ascontiguousarray(p_host[:, order])
+
+
+def bench_bitstream(torch, dev, w, p, steps, capture, time_graph):
+    """Ranking, encoding to 2D maps and decoding of the batched workload's Gaussians, and the
+    forward render a client runs on the decoded set (all levels, one 1920x1080 view)."""
+    import math
+
+    import synth
+    from paper_2509_17513_amd import RenderSettings, render_forward
+    from paper_2509_17513_amd.bitstream import decode_maps, encode_maps, significance_order
+    n, lv = w.n, list(w.level_counts)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    order = significance_order(p)
+    enc = {}
+
+    def encode():
+        enc["r"] = encode_maps(p, order, lv)
+
+    ms_order = timed(lambda: significance_order(p), steps)
+    ms_encode = timed(encode, steps)
+    lo, ranges, maps, _ = enc["r"]
+    dec = decode_maps(lo, maps, ranges)
+    ms_decode = timed(lambda: decode_maps(lo, maps, ranges), steps)
+    W, H = 1920, 1080
+    cam = torch.from_numpy(synth.ring_cameras([0], 24, 4.0, W, H)).to(dev)
+    st = RenderSettings(W, H, w.sh_degree, (n,), (1.0,))
+    img_ref, _ = render_forward(st, p, cam)
+    img, ws = render_forward(st, dec, cam)
+    torch.cuda.synchronize()
+    mse = float(((img - img_ref) ** 2).mean())
+    g = capture(lambda: render_forward(st, dec, cam, ws=ws, image=img, check_overflow=False))
+    ms_frame = time_graph(g, steps)
+    del g
+    return {"gaussians": n, "levels": lv, "map_bytes": int(lo.total_bytes),
+            "bytes_per_gaussian": lo.total_bytes / n, "ms_significance_order": ms_order, "ms_encode": ms_encode,
+            "ms_decode": ms_decode,
+            "client_render": {"width": W, "height": H, "views": 1, "ms_per_frame": ms_frame,
+                              "psnr_decoded_vs_original_db": 10 * math.log10(1.0 / mse) if mse > 0 else None}}
+
+
 def cpu_baseline(w, target_s=25.0):
     """The FP64 oracle (as it stands) on a band of rows of view 0, all six layers, forward +
     analytic backward of the same layer-weighted L1 loss; scaled to ms per view."""
@@ -150,7 +207,7 @@ def bench_rate(torch, dev, L, steps, n=1_000_000, tune=True):
     import synth
     from paper_2509_17513_amd import _lib
     from paper_2509_17513_amd.train import RateModel, context, histogram_bits
-    p_host = synth.cube_scene(n, 5, 3)
+    p_host = significance_sorted(torch, dev, synth.cube_scene(n, 5, 3))
     p = torch.from_numpy(p_host).to(dev)
     lv = synth.nested_levels(n)
     lw = synth.paper_level_weights(6)
@@ -243,7 +300,7 @@ def bench_train(torch, dev, steps, n=1_000_000, views=8):
     timg, _ = render_forward(RenderSettings(960, 540, 3, (n,), (1.0,)), teacher, cams)
     targets = timg[0, :, 0].contiguous()
     del teacher, timg
-    p_host = synth.cube_scene(n, 5, 3)
+    p_host = significance_sorted(torch, dev, synth.cube_scene(n, 5, 3))
     p = torch.from_numpy(p_host).to(dev)
     lv = synth.nested_levels(n)
     st = RenderSettings(960, 540, 3, tuple(lv), tuple(synth.paper_level_weights(6)))
@@ -273,6 +330,8 @@ def main():
     ap.add_argument("--no-rate", action="store_true", help="skip the learned-rate measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the group and training-step measurements")
     ap.add_argument("--no-dssim", action="store_true", help="skip the D-SSIM colour-loss measurement")
+    ap.add_argument("--no-bitstream", action="store_true",
+                    help="skip the significance-order / 2D-map coding and client-render measurement")
     ap.add_argument("--no-autotune", action="store_true", help="no autotuning: default shapes or --shapes")
     ap.add_argument("--shapes", default="", help="launch shapes bin_chunk,row_seg,wave_layout (with --no-autotune)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -298,6 +357,7 @@ def main():
     torch.cuda.set_device(dev)
     log(f"[bench] building workload n={args.n} views={args.views}")
     w = synth.config_batched(n=args.n, n_views=args.views)
+    w.params = significance_sorted(torch, dev, w.params)
     B = w.cams.shape[0]
     st = RenderSettings(w.width, w.height, w.sh_degree, tuple(w.level_counts), tuple(w.level_weights))
     p = torch.from_numpy(w.params).to(dev)
@@ -487,6 +547,11 @@ def main():
                         "ms_per_view": ms_ssim_step / B, "kernels": ssim_k}
         log(f"[bench] D-SSIM loss {ms_loss:.3f} ms, step with D-SSIM {ms_ssim_step:.3f} ms ({ssim_k})")
         del d_img, lws
+
+    # ---------------- bitstream: significance order, 2D maps, decode, client render at 1920x1080
+    if not args.no_bitstream:
+        log("[bench] bitstream coding and client render")
+        out["bitstream"] = bench_bitstream(torch, dev, w, p, args.steps, capture, time_graph)
 
     # ---------------- per-view baseline: 24 x 6 single-view single-layer forward+backward calls
     if not args.no_per_view:

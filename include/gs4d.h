@@ -158,6 +158,63 @@ int gs_color_loss_workspace_size(const gs_settings* s, int32_t n_frames, int32_t
 int gs_color_loss(const gs_settings* s, int32_t n_frames, int32_t n_views, const float* image, const float* target,
                   float lambda_ssim, float* d_image, float* loss_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Significance order (Sec. 3.1): Psi_i = sigmoid(logit_i) + lambda_psi (4/3) pi a_i b_i c_i with
+ * a, b, c = exp(log-scales), in FP32; Gaussians ranked by Psi descending, ties by lower index
+ * (App. A uses lambda_psi = 1e5). Layer l of the hierarchy is then ranks [N_{l-1}, N_l).
+ *  params     [n_channels][n] (rows 3..5 log-scale and 10 opacity logit are read)
+ *  order      [n] int32 output: order[r] = index of the Gaussian of rank r
+ *  psi        [n] float output (Psi of every Gaussian, by index), or NULL
+ *  ws         gs_significance_workspace_size(n) bytes (sort keys, values and histograms)
+ * Errors: GS_ERR_INVALID_ARG (n < 0, n_channels < 11, lambda_psi negative or not finite, NULL
+ * buffers), GS_ERR_WORKSPACE. */
+int gs_significance_workspace_size(int32_t n, size_t* bytes_out);
+int gs_significance_order(int32_t n, const float* params, int32_t n_channels, float lambda_psi, int32_t* order,
+                          float* psi, void* ws, size_t ws_bytes, void* stream);
+
+/* 2D feature maps of a layered Gaussian set, up to the video codec (Sec. 3.3, progressive
+ * bitstream: per layer, differential quantisation with 16-bit positions and 8-bit other
+ * attributes, each channel flattened into one 2D image).
+ * Layer l holds the Gaussians of ranks [level_counts[l-1], level_counts[l]). Every channel of a
+ * layer is quantised with that layer's minimum and maximum,
+ *   code = rint((v - min) * ((2^b - 1) / (max - min)))   (FP32, half to even; 0 if max == min)
+ * with b = 16 for channels 0..2 (the mean) and 8 for the others; decoding is
+ *   min + code * ((max - min) / (2^b - 1)).
+ * A layer's m Gaussians are ordered by the Morton code of their position codes (top 10, 10, 9
+ * bits of x, y, z; ties by rank) and written 256 at a time into 16 x 16 pixel blocks, the blocks
+ * snaking row by row (odd block rows right to left) and the Gaussians of a block following the 2D
+ * Morton curve inside it; the layer's maps are width = 16 ceil(ceil(sqrt m) / 16) by
+ * height = 16 ceil(ceil(m / width) / 16) pixels and pixels past its m-th Gaussian repeat it.
+ * Maps buffer: layer l at offset[l] holds its three 16-bit planes (channels 0..2) and then one
+ * 8-bit plane per other channel, each plane row-major height x width. */
+typedef struct {
+  int32_t n_channels, n_levels;
+  int32_t level_counts[8];
+  int32_t width[8], height[8];
+  int64_t offset[8];
+  int64_t total_bytes;
+} gs_maps_layout;
+
+/* Fills the layout (host only; no device work). level_counts ascending, n_levels 1..8,
+ * n_channels 11..1024. */
+int gs_maps_describe(int32_t n_channels, int32_t n_levels, const int32_t* level_counts, gs_maps_layout* out);
+
+/* Encodes params [n_channels][n] (n = the last level count), ranked by `order` (a permutation of
+ * 0..n-1, as written by gs_significance_order), into the maps.
+ *  ranges     [n_levels][n_channels][2] float output: (min, max) per layer and channel
+ *  maps       output of layout->total_bytes bytes
+ *  seq        [n] int32 output, or NULL: the Gaussian index at each layer's sequence position
+ *             (layer l's positions at level_counts[l-1] + p, in map order)
+ *  ws         gs_encode_workspace_size() bytes
+ * The layout is re-validated (sizes and offsets must hold every layer). */
+int gs_encode_workspace_size(const gs_maps_layout* layout, size_t* bytes_out);
+int gs_encode_maps(const gs_maps_layout* layout, const float* params, const int32_t* order, float* ranges,
+                   uint8_t* maps, int32_t* seq, void* ws, size_t ws_bytes, void* stream);
+
+/* Decodes the maps into params_out [n_channels][n] in map order (layer by layer, sequence
+ * position by position): the Gaussian set a client renders, with the same level_counts. */
+int gs_decode_maps(const gs_maps_layout* layout, const uint8_t* maps, const float* ranges, float* params_out,
+                   void* stream);
+
 /* Autotuner of the render launch shapes (bin_chunk, row_seg, wave_layout of gs_settings) for
  * one workload: the a10 step of the hot path, with shapes picked by timed trials that must pass
  * parity. Starting from *s, it tries the wave layouts, then the binning chunk sizes, then the

@@ -48,6 +48,14 @@ class GsRateDesc(ctypes.Structure):
     ]
 
 
+class GsMapsLayout(ctypes.Structure):
+    _fields_ = [
+        ("n_channels", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("level_counts", ctypes.c_int32 * 8),
+        ("width", ctypes.c_int32 * 8), ("height", ctypes.c_int32 * 8), ("offset", ctypes.c_int64 * 8),
+        ("total_bytes", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 P = ctypes.c_void_p
@@ -64,6 +72,12 @@ SIGNATURES = {
     "gs_autotune_render": ([P, I32, P, I32, P, I32, P, P, P, P, P, SZ, P, P, P], ctypes.c_int),
     "gs_color_loss_workspace_size": ([P, I32, I32, P], ctypes.c_int),
     "gs_color_loss": ([P, I32, I32, P, P, ctypes.c_float, P, P, P, SZ, P], ctypes.c_int),
+    "gs_significance_workspace_size": ([I32, P], ctypes.c_int),
+    "gs_significance_order": ([I32, P, I32, ctypes.c_float, P, P, P, SZ, P], ctypes.c_int),
+    "gs_maps_describe": ([I32, I32, P, P], ctypes.c_int),
+    "gs_encode_workspace_size": ([P, P], ctypes.c_int),
+    "gs_encode_maps": ([P, P, P, P, P, P, P, SZ, P], ctypes.c_int),
+    "gs_decode_maps": ([P, P, P, P, P], ctypes.c_int),
     "gs_error_string": ([ctypes.c_int], ctypes.c_char_p),
     "gs_last_error": ([], ctypes.c_char_p),
     "gs_workspace_stats": ([P, P, P], ctypes.c_int),

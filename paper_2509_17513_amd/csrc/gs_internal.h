@@ -77,6 +77,11 @@ hipError_t launch_project_bwd(const RenderDims& d, const float* params, const fl
 hipError_t launch_compose_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,
                               const float* d_composed, float* d_params, float* d_res, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// Stable radix sort of n 32-bit (key, value) pairs (one segment): the input is in keys[0]/vals[0],
+// keys[1]/vals[1] and hist (radix_hist_words(n) words) are scratch; *_out name the result.
+size_t radix_hist_words(int n);
+hipError_t launch_radix_sort(int n, uint32_t* keys[2], uint32_t* vals[2], uint32_t* hist, uint32_t** keys_out,
+                             uint32_t** vals_out, hipStream_t st);
 // order-sensitive 64-bit checksum of n words (written to *out, which it zeroes first)
 hipError_t launch_checksum(const uint32_t* p, size_t n, unsigned long long* out, hipStream_t st);
 

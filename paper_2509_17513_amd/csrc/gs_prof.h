@@ -31,6 +31,11 @@ enum KernelId {
   K_ROW_EMIT,
   K_SSIM_FWD,
   K_SSIM_BWD,
+  K_PSI,
+  K_MAPS_RANGE,
+  K_MAPS_KEYS,
+  K_MAPS_WRITE,
+  K_MAPS_DECODE,
   K_COUNT
 };
 

@@ -1654,11 +1654,10 @@ hipError_t launch_project_bwd(const RenderDims& d, const float* params, const fl
   return hipGetLastError();
 }
 
-hipError_t launch_sort(const RenderDims& d, char* ws, const Layout& lo, uint32_t** keys_out, uint32_t** vals_out,
-                       hipStream_t st) {
-  uint32_t* k[2] = {(uint32_t*)(ws + lo.keys0), (uint32_t*)(ws + lo.keys1)};
-  uint32_t* v[2] = {(uint32_t*)(ws + lo.vals0), (uint32_t*)(ws + lo.vals1)};
-  uint32_t* hist = (uint32_t*)(ws + lo.sort_hist);
+// Stable LSD radix sort (four 8-bit passes) of B segments of n (key, value) pairs, ping-ponging
+// between k[0]/v[0] (the input) and k[1]/v[1]; returns the buffers that hold the result.
+static hipError_t radix_passes(const RenderDims& d, uint32_t* k[2], uint32_t* v[2], uint32_t* hist, uint32_t** keys_out,
+                               uint32_t** vals_out, hipStream_t st) {
   dim3 grid(d.n_sort_chunks, d.B);
   int cur = 0;
   for (int pass = 0; pass < 4; ++pass) {
@@ -1674,13 +1673,31 @@ hipError_t launch_sort(const RenderDims& d, char* ws, const Layout& lo, uint32_t
     {
       ProfScope ps_(K_RADIX_SCATTER, st);
       hipLaunchKernelGGL(k_radix_scatter, grid, dim3(kSortThreads), 0, st, d, k[cur], v[cur], k[cur ^ 1], v[cur ^ 1],
-                       hist, shift);
+                         hist, shift);
     }
     cur ^= 1;
   }
   *keys_out = k[cur];
   *vals_out = v[cur];
   return hipGetLastError();
+}
+
+hipError_t launch_sort(const RenderDims& d, char* ws, const Layout& lo, uint32_t** keys_out, uint32_t** vals_out,
+                       hipStream_t st) {
+  uint32_t* k[2] = {(uint32_t*)(ws + lo.keys0), (uint32_t*)(ws + lo.keys1)};
+  uint32_t* v[2] = {(uint32_t*)(ws + lo.vals0), (uint32_t*)(ws + lo.vals1)};
+  return radix_passes(d, k, v, (uint32_t*)(ws + lo.sort_hist), keys_out, vals_out, st);
+}
+
+size_t radix_hist_words(int n) { return (size_t)256 * ((n + kSortChunk - 1) / kSortChunk); }
+
+hipError_t launch_radix_sort(int n, uint32_t* keys[2], uint32_t* vals[2], uint32_t* hist, uint32_t** keys_out,
+                             uint32_t** vals_out, hipStream_t st) {
+  RenderDims d{};
+  d.n = n;
+  d.B = 1;
+  d.n_sort_chunks = (n + kSortChunk - 1) / kSortChunk;
+  return radix_passes(d, keys, vals, hist, keys_out, vals_out, st);
 }
 
 hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t* svals, char* ws, const Layout& lo,

@@ -70,27 +70,21 @@ def slab_scene(n: int, seed: int, sh_degree: int = 0) -> np.ndarray:
     return np.ascontiguousarray(p.astype(np.float32))
 
 
-def cube_scene(n: int, seed: int, sh_degree: int = 3, significance_order: bool = True) -> np.ndarray:
-    """Means ~ U[-1, 1]^3 (a cloud seen by a camera ring).
-
-    With ``significance_order`` the Gaussians are sorted by decreasing
-    significance, opacity plus 1e5 times the ellipsoid volume (Sec. 3.1,
-    significance metric; weight from App. A), so that nested prefixes form
-    the hierarchy layers.
-    """
+def cube_scene(n: int, seed: int, sh_degree: int = 3) -> np.ndarray:
+    """Means ~ U[-1, 1]^3 (a cloud seen by a camera ring), in generation order. The hierarchy's
+    nested layers come from ordering the Gaussians by significance, which is the method's own
+    step: the benchmark does it with the library, the tests with the oracle (see ``reorder``)."""
     rng = np.random.default_rng(seed)
     c = n_channels(sh_degree)
     p = np.zeros((c, n), np.float64)
     p[0:3] = rng.uniform(-1.0, 1.0, (3, n))
     _fill_common(rng, p, n, sh_degree)
-    p = p.astype(np.float32)
-    if significance_order:
-        s = np.exp(p[3:6].astype(np.float64))
-        opac = 1.0 / (1.0 + np.exp(-p[10].astype(np.float64)))
-        psi = opac + 1e5 * (4.0 / 3.0) * math.pi * s[0] * s[1] * s[2]
-        order = np.argsort(-psi, kind="stable")
-        p = p[:, order]
-    return np.ascontiguousarray(p)
+    return np.ascontiguousarray(p.astype(np.float32))
+
+
+def reorder(a: np.ndarray, order) -> np.ndarray:
+    """The columns (last axis: Gaussians) of a parameter or residual array in the given order."""
+    return np.ascontiguousarray(np.asarray(a)[..., np.asarray(order)])
 
 
 def identity_camera(width: int, height: int, focal: float) -> np.ndarray:
@@ -244,7 +238,9 @@ def nested_levels(n: int):
 
 def config_batched(seed: int = 3, n: int = 300_000, n_views: int = 24, width: int = 960, height: int = 540,
                    target_seed: int = 13, view_indices=None) -> Workload:
-    """300k Gaussians in a cube, a 24-camera ring of radius 4, 960x540, SH 3, six nested levels."""
+    """300k Gaussians in a cube, a 24-camera ring of radius 4, 960x540, SH 3, six nested levels
+    (prefixes of the Gaussians in the given order: sort them by significance first to make the
+    levels the method's hierarchy)."""
     p = cube_scene(n, seed, 3)
     idx = list(range(n_views)) if view_indices is None else list(view_indices)
     cams = ring_cameras(idx, 24, 4.0, width, height)

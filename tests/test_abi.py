@@ -132,3 +132,33 @@ def test_workspace_layout_regions_are_disjoint(L):
     assert lo.lists + 4 * 123456 + 8 * (123456 // 2) <= lo.total
     assert offs == sorted(offs) and len(set(offs)) == len(offs)
     assert lo.tiles_x == 13 and lo.tiles_y == 8
+
+
+def test_maps_describe_matches_the_layout_rule_and_validates(L):
+    from oracle import bitstream as BS
+    from paper_2509_17513_amd._lib import GsMapsLayout
+    lv = [300, 300, 900, 3000]  # an empty second layer
+    arr = (ctypes.c_int32 * 8)(*lv)
+    lo = GsMapsLayout()
+    assert L.gs_maps_describe(14, 4, arr, ctypes.byref(lo)) == 0
+    prev = 0
+    end = 0
+    for l, c in enumerate(lv):
+        assert (lo.width[l], lo.height[l]) == BS.map_size(c - prev), l
+        assert lo.offset[l] >= end and lo.offset[l] % 256 == 0
+        end = lo.offset[l] + lo.width[l] * lo.height[l] * (6 + 11)
+        prev = c
+    assert lo.total_bytes >= end
+    bad = (ctypes.c_int32 * 8)(300, 200, 900)
+    assert L.gs_maps_describe(14, 3, bad, ctypes.byref(lo)) == -1
+    assert L.gs_maps_describe(10, 3, arr, ctypes.byref(lo)) == -1
+    assert L.gs_maps_describe(14, 9, arr, ctypes.byref(lo)) == -1
+    # encode re-validates a layout that does not hold its layers, before any device work
+    assert L.gs_maps_describe(14, 4, arr, ctypes.byref(lo)) == 0
+    lo.width[3] = 16
+    sz = ctypes.c_size_t()
+    assert L.gs_encode_workspace_size(ctypes.byref(lo), ctypes.byref(sz)) == -1
+    P = ctypes.c_void_p
+    assert L.gs_significance_order(-1, P(8), 14, 1e5, P(8), None, P(8), 1 << 20, None) == -1
+    assert L.gs_significance_order(10, P(8), 14, float("inf"), P(8), None, P(8), 1 << 20, None) == -1
+    assert L.gs_significance_order(10, P(8), 14, 1e5, P(8), None, P(8), 16, None) == -2

@@ -27,7 +27,10 @@ def _setup(lam, seed=91, n=20000, W=240, H=136, views=(0, 6, 12, 18)):
     st1 = RenderSettings(W, H, 3, (n,), (1.0,))
     timg, _ = render_forward(st1, teacher, cams)
     targets = timg[0, :, 0].contiguous()  # [V][3][H][W]
+    # the hierarchy: Gaussians in decreasing significance (ordered by the oracle's ranking)
+    from oracle.bitstream import significance_order
     p_host = synth.cube_scene(n, seed, 3)
+    p_host = synth.reorder(p_host, significance_order(p_host))
     p = torch.from_numpy(p_host).to(dev)
     lv = synth.nested_levels(n)
     st = RenderSettings(W, H, 3, tuple(lv), tuple(synth.paper_level_weights(6)))

@@ -62,7 +62,7 @@ def _fd_check(st, p, cams, w, F=1, res=None, h=1e-4, sample=None, target="params
 
 
 def _tiny(seed, n=12, deg=3, wdt=24, hgt=20, n_views=2):
-    p = synth.cube_scene(n, seed, deg, significance_order=False)
+    p = synth.cube_scene(n, seed, deg)
     p[3:6] += 1.2  # larger footprints so that every Gaussian covers pixels of the small image
     cams = synth.ring_cameras(list(range(0, 24, 24 // n_views))[:n_views], 24, 4.0, wdt, hgt, float(wdt))
     return p, cams

@@ -328,7 +328,7 @@ def test_frame_composition_equals_plain_render():
     """Frame f of a group = plain render of the keyframe composed with the deltas of frames 0..f
     (Sec. 3.2: mu_t = mu_{t-1} + d mu_t, R_t = dR_t R_{t-1}, Eq. 7 additive residuals)."""
     n, F = 200, 3
-    p = synth.cube_scene(n, 11, 1, significance_order=False)
+    p = synth.cube_scene(n, 11, 1)
     res = synth.frame_residuals(n, F, 12, channels=11 + 3 * 4, sd_mean=0.05, sd_angle=0.3,
                                 sd_logit=0.3, sd_log_scale=0.1, sd_sh=0.1)
     cams1 = synth.ring_cameras([0, 7], 24, 4.0, 48, 32, 48.0)
