@@ -233,7 +233,7 @@ def bench_rate(torch, dev, L, steps, n=1_000_000, tune=True):
     hb = histogram_bits(p[3:59])
     torch.cuda.synchronize()
     L.gs_profile_enable(0)
-    nk = 32
+    nk = 64
     tot = (ctypes.c_double * nk)()
     cnt = (ctypes.c_int32 * nk)()
     _lib.check(L.gs_profile_collect(nk, tot, cnt), "gs_profile_collect")
@@ -241,12 +241,37 @@ def bench_rate(torch, dev, L, steps, n=1_000_000, tune=True):
     ms = times.get("rate_mlp", float("nan"))
     flop = n * 56 * (MLP_FLOP_FWD + MLP_FLOP_BWD)
     hist_ms = sum(v for k, v in times.items() if k.startswith("rate_hist"))
+    # the paper's own entropy models on the same symbols (KDE) and on residual-like attributes
+    # (Gaussian + temporal L1: translations excluded, 52 channels of rotation, opacity, scale, SH)
+    from paper_2509_17513_amd.entropy import GAUSSIAN, KDE, EntropyModel
+    at = p[3:59]
+    em = EntropyModel(56, n, KDE, dev, 1.0 / 64, lv, lw, 1e-3)
+    da2 = torch.zeros_like(at)
+    res = torch.from_numpy(synth.frame_residuals(n, 1, 17, channels=59, sd_log_scale=0.02, sd_sh=0.02)[0][7:59].copy()).to(dev)
+    eg = EntropyModel(52, n, GAUSSIAN, dev, 1.0 / 64, lv, lw, 1e-4, 1e-3)
+    dr = torch.zeros_like(res)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps
+
+    kde_ms = timed(lambda: em.run(at, 1, seed=1, offset=0, d_attrs=da2))
+    kde_bits = float(em.bits.sum().item())
+    gauss_ms = timed(lambda: eg.run(res, 1, seed=1, offset=0, d_attrs=dr))
+    entropy = {"kde_train_ms": kde_ms, "kde_bits": kde_bits, "kde_bits_vs_hist": kde_bits / float(hb.sum().item()),
+               "gaussian_train_ms": gauss_ms, "gaussian_workload": f"residuals_{n}x52_6_layers"}
     return {"workload": "rate_1000000x56_train_fwd_bwd", "mlp_ms": ms, "mlp_flop": flop,
             "mlp_tflops": flop / (ms * 1e-3) / 1e12, "mfma_frac": flop / (ms * 1e-3) / BF16_PEAK_FLOPS,
             "histogram_ms": hist_ms, "histogram_GB/s": n * 56 * 4 * 2 / (hist_ms * 1e-3) / 1e9,
             "mlp_bits": float(rm.bits.sum().item()), "hist_bits": float(hb.sum().item()),
             "kernels_ms": times, "autotune": {"blocks_per_attr": blocks,
-                                               "candidates": dict(zip((16, 32, 64, 128, 256), cand_ms or ()))}}
+                                               "candidates": dict(zip((16, 32, 64, 128, 256), cand_ms or ()))},
+            "entropy_models": entropy}
 
 
 def bench_group(torch, dev, steps):
@@ -399,7 +424,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     L.gs_profile_enable(0)
-    nk = 32
+    nk = 64
     tot = (ctypes.c_double * nk)()
     cnt = (ctypes.c_int32 * nk)()
     _lib.check(L.gs_profile_collect(nk, tot, cnt), "gs_profile_collect")

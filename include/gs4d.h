@@ -215,6 +215,45 @@ int gs_encode_maps(const gs_maps_layout* layout, const float* params, const int3
 int gs_decode_maps(const gs_maps_layout* layout, const uint8_t* maps, const float* ranges, float* params_out,
                    void* stream);
 
+/* The paper's entropy models of the quantised attributes (Sec. 3.3), per layer and attribute:
+ *  kind 0, keyframe attributes: a Gaussian KDE of the layer's symbols with Silverman's bandwidth
+ *          h = sigma (3 m / 4)^(-1/5) (sigma the sample standard deviation of its m symbols; at
+ *          least step / 4); its CDF on a grid of spacing min(step, h) / 4 from lo = min - 8 h - step
+ *          to max + 8 h + step (at most 16384 points and 3071 a kernel side, widening the spacing),
+ *          made by linearly binning the symbols and convolving the counts with the kernel's CDF,
+ *          and taken between grid points by linear interpolation. The gradient holds the binned
+ *          density fixed (binning has no derivative).
+ *  kind 1, residual attributes: a normal CDF with the layer's symbol mean and standard deviation
+ *          (1/m, at least step 1e-3); the gradient includes the mean's and deviation's dependence
+ *          on every symbol. Adds the temporal term lambda^l lambda_reg |y| per symbol.
+ * Symbols: mode 0 rint(y / step) step; mode 1 y + u step with u uniform in [-1/2, 1/2) from the
+ * counter-based SplitMix64 generator of gs_rate_model (counter = offset + a n + i + 1). A symbol
+ * costs -log2 max(F(y + step/2) - F(y - step/2), 1e-9) bits (the PMF as CDF differences), weighted
+ * by w = lambda_rate lambda^l / |G^l| in the loss.
+ *  attrs     [n_attr][n] (n = level_counts[n_levels-1]; layer l = symbols [N_{l-1}, N_l))
+ *  bits_out  [n_attr] float64 per attribute bit totals (written), or NULL
+ *  loss_out  one float64 (+= L), or NULL
+ *  sym_bits  [n_attr][n] float per-symbol bits, or NULL
+ *  d_attrs   [n_attr][n] (+= dL/dy, mode 1 only), or NULL
+ *  ws        gs_entropy_workspace_size() bytes (about 130 MB per 336 (layer, attribute) pairs
+ *            for the KDE, which keeps a full-size grid per pair)
+ * All sums are taken in a fixed order: results do not depend on scheduling. */
+typedef struct {
+  int32_t n, n_attr;
+  float step;
+  int32_t mode;
+  uint64_t seed, offset;
+  int32_t n_levels;
+  int32_t level_counts[8];
+  float level_weights[8];
+  float lambda_rate;
+  int32_t kind;
+  float lambda_reg;
+} gs_entropy_desc;
+int gs_entropy_workspace_size(const gs_entropy_desc* desc, size_t* bytes_out);
+int gs_entropy_model(const gs_entropy_desc* desc, const float* attrs, double* bits_out, double* loss_out,
+                     float* sym_bits, float* d_attrs, void* ws, size_t ws_bytes, void* stream);
+
 /* Autotuner of the render launch shapes (bin_chunk, row_seg, wave_layout of gs_settings) for
  * one workload: the a10 step of the hot path, with shapes picked by timed trials that must pass
  * parity. Starting from *s, it tries the wave layouts, then the binning chunk sizes, then the

@@ -17,7 +17,7 @@ KDE (keyframe attributes), in the paper's order of steps:
      at least q / 4 (a layer of equal symbols);
   2. the CDF on a grid through a convolution: the symbols are linearly binned on the grid
      x_k = lo + k Delta (Delta = min(q, h) / 4, lo = min - 8 h - q, up to max + 8 h + q; Delta is
-     widened if the grid would pass 16384 points or the kernel 4095 points a side), and the
+     widened if the grid would pass 16384 points or the kernel 3071 points a side), and the
      binned counts are convolved (FFT) with the kernel's CDF, F_k = sum_j c_j Phi((k - j) Delta / h) / m;
   3. the PMF by differencing the CDF one step apart, the CDF taken between grid points by linear
      interpolation.
@@ -40,7 +40,7 @@ from . import rate
 
 P_FLOOR = 1e-9
 G_MAX = 16384
-K_MAX = 4095
+K_MAX = 3071
 LN2 = math.log(2.0)
 
 

@@ -56,6 +56,15 @@ class GsMapsLayout(ctypes.Structure):
     ]
 
 
+class GsEntropyDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_attr", ctypes.c_int32), ("step", ctypes.c_float), ("mode", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("offset", ctypes.c_uint64), ("n_levels", ctypes.c_int32),
+        ("level_counts", ctypes.c_int32 * 8), ("level_weights", ctypes.c_float * 8), ("lambda_rate", ctypes.c_float),
+        ("kind", ctypes.c_int32), ("lambda_reg", ctypes.c_float),
+    ]
+
+
 _lib = None
 
 P = ctypes.c_void_p
@@ -78,6 +87,8 @@ SIGNATURES = {
     "gs_encode_workspace_size": ([P, P], ctypes.c_int),
     "gs_encode_maps": ([P, P, P, P, P, P, P, SZ, P], ctypes.c_int),
     "gs_decode_maps": ([P, P, P, P, P], ctypes.c_int),
+    "gs_entropy_workspace_size": ([P, P], ctypes.c_int),
+    "gs_entropy_model": ([P, P, P, P, P, P, P, SZ, P], ctypes.c_int),
     "gs_error_string": ([ctypes.c_int], ctypes.c_char_p),
     "gs_last_error": ([], ctypes.c_char_p),
     "gs_workspace_stats": ([P, P, P], ctypes.c_int),

@@ -36,6 +36,10 @@ enum KernelId {
   K_MAPS_KEYS,
   K_MAPS_WRITE,
   K_MAPS_DECODE,
+  K_ENT_STATS,
+  K_ENT_HIST,
+  K_ENT_CDF,
+  K_ENT_EVAL,
   K_COUNT
 };
 
