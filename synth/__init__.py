@@ -154,6 +154,21 @@ def target_images(n_images: int, width: int, height: int, seed: int) -> np.ndarr
     return np.ascontiguousarray(rng.uniform(0.0, 1.0, (n_images, 3, height, width)).astype(np.float32))
 
 
+def motion_params(seed: int, table_floats: int, weight_shapes, table_scale: float = 1e-4):
+    """Seeded parameters of a hash-grid + MLP motion network: a table of uniform values in
+    [-table_scale, table_scale], He-normal weight matrices [out][in] and zero biases, flattened
+    in the order of weight_shapes (2-tuples are matrices, 1-tuples biases)."""
+    rng = np.random.default_rng(seed)
+    table = rng.uniform(-table_scale, table_scale, table_floats).astype(np.float32)
+    parts = []
+    for s in weight_shapes:
+        if len(s) == 2:
+            parts.append(rng.normal(0.0, math.sqrt(2.0 / s[1]), s).ravel())
+        else:
+            parts.append(np.zeros(s).ravel())
+    return table, np.concatenate(parts).astype(np.float32)
+
+
 def loss_images(n_images: int, n_levels: int, width: int, height: int, seed: int):
     """Render-like colour layers and targets for the colour-loss path, float32 in [0, 1]:
     image [n_images][n_levels][3][height][width], target [n_images][3][height][width].
