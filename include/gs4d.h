@@ -254,6 +254,37 @@ int gs_entropy_workspace_size(const gs_entropy_desc* desc, size_t* bytes_out);
 int gs_entropy_model(const gs_entropy_desc* desc, const float* attrs, double* bits_out, double* loss_out,
                      float* sym_bits, float* d_attrs, void* ws, size_t ws_bytes, void* stream);
 
+/* Rigid-motion module of inter-frame training (Sec. 3.2, rigid transformation; Eq. 5-6): the
+ * previous frame's positions are encoded by a multi-resolution hash grid (16 levels of 2
+ * features, 2^15 entries per level, resolutions floor(16 b^l) from 16 to 1024; trilinear
+ * interpolation of the cell corners, indexed densely while (N + 1)^3 <= 2^15, else by the
+ * spatial hash (i ^ j 2654435761 ^ k 805459861) mod 2^15) inside the scene box, and two MLPs
+ * (32 -> 64 -> 64 -> 3 and 32 -> 64 -> 64 -> 4, ReLU, FP32) predict each Gaussian's translation
+ * d_mu and rotation quaternion dq = (1 + o0, o1, o2, o3), written as the residual channels 0..6
+ * of a frame (mu_t = mu_{t-1} + d_mu, q_t = dq (x) q_{t-1} in gs_render_forward's composition).
+ *  table    [16][2^15][2] float features (gs_motion_sizes gives the float count)
+ *  weights  W1 [64][32], b1, W2 [64][64], b2, W3 [3][64], b3 of the translation MLP, then the
+ *           rotation MLP's with W3 [4][64], b3 (row-major [out][in]; gs_motion_sizes gives the
+ *           count)
+ *  means    rows 0..2 of an array of row stride row_stride (the previous frame's positions)
+ *  out      rows 0..6 of an array of row stride row_stride (a frame's residual block)
+ *  d_out    rows 0..6 of dL/d(those residuals), row stride row_stride
+ *  d_table, d_weights   accumulated (+=) with float atomics
+ *  ws       gs_motion_workspace_size(n) bytes (the per-Gaussian activations and gradients the
+ *           weight gradients are summed from)
+ * Errors: GS_ERR_INVALID_ARG for n < 0, row_stride < n, a degenerate box or NULL buffers. */
+typedef struct {
+  int32_t n;
+  float box_lo[3], box_hi[3];
+} gs_motion_desc;
+int gs_motion_sizes(int64_t* table_floats, int64_t* n_weights);
+int gs_motion_workspace_size(int32_t n, size_t* bytes_out);
+int gs_motion_forward(const gs_motion_desc* desc, const float* means, int32_t row_stride, const float* table,
+                      const float* weights, float* out, void* stream);
+int gs_motion_backward(const gs_motion_desc* desc, const float* means, int32_t row_stride, const float* table,
+                       const float* weights, const float* d_out, float* d_table, float* d_weights, void* ws,
+                       size_t ws_bytes, void* stream);
+
 /* Autotuner of the render launch shapes (bin_chunk, row_seg, wave_layout of gs_settings) for
  * one workload: the a10 step of the hot path, with shapes picked by timed trials that must pass
  * parity. Starting from *s, it tries the wave layouts, then the binning chunk sizes, then the

@@ -121,6 +121,17 @@ def forward(means, lo, hi, table, weights):
     return np.concatenate([o_mu, q], axis=1).T
 
 
+def min_preactivation(means, lo, hi, table, weights):
+    """Per Gaussian, the smallest |pre-activation| of any hidden unit of either MLP: how close its
+    ReLU decisions are to the kink (FP32 and FP64 can take the other side there)."""
+    h, _ = encode(means, lo, hi, table)
+    out = np.full(h.shape[0], np.inf)
+    for head in unpack(weights):
+        z1, _, z2, _, _ = _head_forward(h, *head)
+        out = np.minimum(out, np.minimum(np.abs(z1).min(axis=1), np.abs(z2).min(axis=1)))
+    return out
+
+
 def backward(means, lo, hi, table, weights, d_out):
     """(d_table [16 * 2^15 * 2], d_weights [n_weights]) of the loss whose gradient in the
     module's output is d_out [7][n]."""

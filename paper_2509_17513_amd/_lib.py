@@ -65,6 +65,10 @@ class GsEntropyDesc(ctypes.Structure):
     ]
 
 
+class GsMotionDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("box_lo", ctypes.c_float * 3), ("box_hi", ctypes.c_float * 3)]
+
+
 _lib = None
 
 P = ctypes.c_void_p
@@ -89,6 +93,10 @@ SIGNATURES = {
     "gs_decode_maps": ([P, P, P, P, P], ctypes.c_int),
     "gs_entropy_workspace_size": ([P, P], ctypes.c_int),
     "gs_entropy_model": ([P, P, P, P, P, P, P, SZ, P], ctypes.c_int),
+    "gs_motion_sizes": ([P, P], ctypes.c_int),
+    "gs_motion_workspace_size": ([I32, P], ctypes.c_int),
+    "gs_motion_forward": ([P, P, I32, P, P, P, P], ctypes.c_int),
+    "gs_motion_backward": ([P, P, I32, P, P, P, P, P, P, SZ, P], ctypes.c_int),
     "gs_error_string": ([ctypes.c_int], ctypes.c_char_p),
     "gs_last_error": ([], ctypes.c_char_p),
     "gs_workspace_stats": ([P, P, P], ctypes.c_int),

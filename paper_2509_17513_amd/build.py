@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgs4d.so")
-SOURCES = ["gs_api.hip", "gs_render.hip", "gs_rate.hip", "gs_loss.hip", "gs_bitstream.hip", "gs_entropy.hip"]
+SOURCES = ["gs_api.hip", "gs_render.hip", "gs_rate.hip", "gs_loss.hip", "gs_bitstream.hip", "gs_entropy.hip", "gs_motion.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -40,6 +40,9 @@ enum KernelId {
   K_ENT_HIST,
   K_ENT_CDF,
   K_ENT_EVAL,
+  K_MOTION_FWD,
+  K_MOTION_BWD,
+  K_MOTION_WGRAD,
   K_COUNT
 };
 

@@ -162,3 +162,9 @@ def test_maps_describe_matches_the_layout_rule_and_validates(L):
     assert L.gs_significance_order(-1, P(8), 14, 1e5, P(8), None, P(8), 1 << 20, None) == -1
     assert L.gs_significance_order(10, P(8), 14, float("inf"), P(8), None, P(8), 1 << 20, None) == -1
     assert L.gs_significance_order(10, P(8), 14, 1e5, P(8), None, P(8), 16, None) == -2
+
+
+def test_package_modules_import():
+    import importlib
+    for m in ("render", "train", "bitstream", "entropy", "motion", "_lib"):
+        importlib.import_module(f"paper_2509_17513_amd.{m}")
