@@ -108,6 +108,56 @@ def significance_sorted(torch, dev, p_host):
     return np.ascontiguousarray(p_host[:, order])
 
 
+# FP32 FLOPs of the motion MLPs per Gaussian (two heads of 32 -> 64 -> 64 -> 3 / 4): forward, and
+# backward (data path and weight gradients, each as large as the forward's products)
+MOTION_FLOP_FWD = 2 * (2 * (32 * 64 + 64 * 64) + 64 * 3 + 64 * 4)
+MOTION_FLOP_BWD = 2 * MOTION_FLOP_FWD
+FP32_PEAK_FLOPS = 157.3e12
+
+
+def bench_motion(torch, dev, p, steps):
+    """The hash-grid + MLP motion predictor on the keyframe's Gaussians: forward, and forward +
+    backward to the table and weights."""
+    import numpy as np
+
+    import synth
+    from paper_2509_17513_amd.motion import MotionModule, sizes
+    n = p.shape[1]
+    nt, nw = sizes()
+    shapes = [s for out in (3, 4) for s in ((64, 32), (64,), (64, 64), (64,), (out, 64), (out,))]
+    table_h, w_h = synth.motion_params(9, nt, shapes, table_scale=1e-2)
+    table, weights = torch.from_numpy(table_h).to(dev), torch.from_numpy(w_h).to(dev)
+    mm = MotionModule(n, (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0), dev)
+    res = torch.zeros((8, n), device=dev)
+    d_res = torch.from_numpy(np.random.default_rng(3).normal(0, 1e-3, (8, n)).astype(np.float32)).to(dev)
+    d_table, d_w = torch.zeros_like(table), torch.zeros_like(weights)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps
+
+    ms_fwd = timed(lambda: mm.forward(p, table, weights, res))
+    from paper_2509_17513_amd import _lib
+    L = _lib.lib()
+    L.gs_profile_enable(1)
+    ms_fb = timed(lambda: (mm.forward(p, table, weights, res), mm.backward(p, table, weights, d_res, d_table, d_w)))
+    L.gs_profile_enable(0)
+    import ctypes
+    nk = 64
+    tot, cnt = (ctypes.c_double * nk)(), (ctypes.c_int32 * nk)()
+    _lib.check(L.gs_profile_collect(nk, tot, cnt), "gs_profile_collect")
+    kern = {L.gs_kernel_name(k).decode(): tot[k] / cnt[k] for k in range(nk) if cnt[k]}
+    return {"gaussians": n, "table_floats": nt, "weights": nw, "ms_forward": ms_fwd, "ms_forward_backward": ms_fb,
+            "kernels_ms": kern,
+            "alu_frac_forward": n * MOTION_FLOP_FWD / (ms_fwd * 1e-3) / FP32_PEAK_FLOPS,
+            "alu_frac_forward_backward": n * (MOTION_FLOP_FWD + MOTION_FLOP_BWD) / (ms_fb * 1e-3) / FP32_PEAK_FLOPS}
+
+
 def bench_bitstream(torch, dev, w, p, steps, capture, time_graph):
     """Ranking, encoding to 2D maps and decoding of the batched workload's Gaussians, and the
     forward render a client runs on the decoded set (all levels, one 1920x1080 view)."""
@@ -355,6 +405,7 @@ def main():
     ap.add_argument("--no-rate", action="store_true", help="skip the learned-rate measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the group and training-step measurements")
     ap.add_argument("--no-dssim", action="store_true", help="skip the D-SSIM colour-loss measurement")
+    ap.add_argument("--no-motion", action="store_true", help="skip the rigid-motion module measurement")
     ap.add_argument("--no-bitstream", action="store_true",
                     help="skip the significance-order / 2D-map coding and client-render measurement")
     ap.add_argument("--no-autotune", action="store_true", help="no autotuning: default shapes or --shapes")
@@ -577,6 +628,11 @@ def main():
     if not args.no_bitstream:
         log("[bench] bitstream coding and client render")
         out["bitstream"] = bench_bitstream(torch, dev, w, p, args.steps, capture, time_graph)
+
+    # ---------------- rigid-motion module (inter-frame translation / rotation) on the same Gaussians
+    if not args.no_motion:
+        log("[bench] rigid-motion module")
+        out["motion"] = bench_motion(torch, dev, p, args.steps)
 
     # ---------------- per-view baseline: 24 x 6 single-view single-layer forward+backward calls
     if not args.no_per_view:

@@ -181,10 +181,13 @@ __global__ __launch_bounds__(256) void k_motion_fwd(MotionDims d, const float* _
   const HeadW wm = head_weights<3>(sw + kWMu), wr = head_weights<4>(sw + kWR);
   hidden2(wm, h, a2);
   head_out<3>(wm, a2, y3);
-  hidden2(wr, h, a2);
-  head_out<4>(wr, a2, y4);
 #pragma unroll
   for (int k = 0; k < 3; ++k) out[(size_t)k * d.row + i] = y3[k];
+  // one head at a time: keeps the compiler from interleaving the two heads' 64 accumulators
+  // (165 registers, three waves per SIMD, instead of more than 256)
+  asm volatile("" ::: "memory");
+  hidden2(wr, h, a2);
+  head_out<4>(wr, a2, y4);
   out[(size_t)3 * d.row + i] = 1.f + y4[0];
 #pragma unroll
   for (int k = 1; k < 4; ++k) out[(size_t)(3 + k) * d.row + i] = y4[k];
