@@ -282,3 +282,54 @@ def gaussian_fit_bits(attrs: np.ndarray, step: float) -> np.ndarray:
         P = np.maximum(hi - lo, 1e-9)
         out[a] = -(cnt * np.log2(P)).sum()
     return out
+
+
+class RigidTrainer:
+    """Rigid-transformation phase of inter-frame training (Sec. 3.2 rigid transformation, trained
+    with the colour loss as in Sec. 3.3): the motion module predicts every Gaussian's translation and
+    rotation from the previous frame's positions (the keyframe's means here), the frame is the
+    keyframe composed with them (residual channels 0..6; the opacity residual stays 0), and the
+    layer-weighted L1 against the frame's views trains the hash table and the MLP weights (Adam).
+
+    One step, every compute step a C-ABI call: motion forward -> render forward (composition,
+    projection, binning, rasterisation of all views and layers) -> fused L1 backward down to the
+    residuals -> motion backward to the table and weights -> Adam on both."""
+
+    def __init__(self, keyframe: torch.Tensor, cams: torch.Tensor, targets: torch.Tensor, settings: RenderSettings,
+                 box_lo, box_hi, table: torch.Tensor, weights: torch.Tensor, lr_table: float = 1e-2,
+                 lr_mlp: float = 1e-3):
+        from .motion import MotionModule
+        dev = keyframe.device
+        self.p, self.cams, self.tgt = keyframe, cams, targets
+        self.n = keyframe.shape[1]
+        self.st = dataclasses.replace(settings, res_channels=8)
+        self.res = torch.zeros((1, 8, self.n), dtype=torch.float32, device=dev)
+        self.d_res = torch.zeros_like(self.res)
+        self.dp = torch.zeros_like(keyframe)  # the keyframe stays fixed in this phase
+        self.table, self.weights = table, weights
+        self.d_table, self.d_w = torch.zeros_like(table), torch.zeros_like(weights)
+        self.opt_t, self.opt_w = Adam(table), Adam(weights)
+        self.lr_table, self.lr_mlp = lr_table, lr_mlp
+        self.mm = MotionModule(self.n, box_lo, box_hi, dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.t = 0
+        self.mm.forward(self.p, self.table, self.weights, self.res[0])
+        self.img, self.ws = render_forward(self.st, self.p, cams, 1, self.res)  # sizes the workspace
+
+    def step(self, check_overflow: bool = False):
+        zero(self.loss)
+        self.mm.forward(self.p, self.table, self.weights, self.res[0])
+        render_forward(self.st, self.p, self.cams, 1, self.res, ws=self.ws, image=self.img,
+                       check_overflow=check_overflow)
+        zero(self.d_res)
+        zero(self.dp)
+        render_backward(self.st, self.p, self.cams, self.ws, 1, self.res, image=self.img, target=self.tgt,
+                        d_params=self.dp, d_residuals=self.d_res, loss=self.loss)
+        self.mm.backward(self.p, self.table, self.weights, self.d_res[0], self.d_table, self.d_w)
+        self.t += 1
+        self.opt_t.step(self.d_table, self.lr_table, self.t)
+        self.opt_w.step(self.d_w, self.lr_mlp, self.t)
+
+    def translation(self) -> torch.Tensor:
+        """The current predicted translation of every Gaussian, [3][n]."""
+        return self.res[0, 0:3]
