@@ -115,9 +115,11 @@ MOTION_FLOP_BWD = 2 * MOTION_FLOP_FWD
 FP32_PEAK_FLOPS = 157.3e12
 
 
-def bench_motion(torch, dev, p, steps):
+def bench_motion(torch, dev, p, steps, st=None, cams=None, targets=None):
     """The hash-grid + MLP motion predictor on the keyframe's Gaussians: forward, and forward +
-    backward to the table and weights."""
+    backward to the table and weights; and one step of the rigid phase of inter-frame training
+    (motion, render of all views and layers with the residuals, L1 backward, motion backward,
+    Adam) on the same workload."""
     import numpy as np
 
     import synth
@@ -152,8 +154,15 @@ def bench_motion(torch, dev, p, steps):
     tot, cnt = (ctypes.c_double * nk)(), (ctypes.c_int32 * nk)()
     _lib.check(L.gs_profile_collect(nk, tot, cnt), "gs_profile_collect")
     kern = {L.gs_kernel_name(k).decode(): tot[k] / cnt[k] for k in range(nk) if cnt[k]}
+    rigid = None
+    if st is not None:
+        from paper_2509_17513_amd.train import RigidTrainer
+        tr = RigidTrainer(p, cams, targets, st, (-1.2, -1.2, -1.2), (1.2, 1.2, 1.2), table.clone(), weights.clone())
+        tr.step(check_overflow=True)
+        rigid = {"views": int(cams.shape[0]), "ms_per_step": timed(tr.step)}
+        del tr
     return {"gaussians": n, "table_floats": nt, "weights": nw, "ms_forward": ms_fwd, "ms_forward_backward": ms_fb,
-            "kernels_ms": kern,
+            "kernels_ms": kern, "rigid_step": rigid,
             "alu_frac_forward": n * MOTION_FLOP_FWD / (ms_fwd * 1e-3) / FP32_PEAK_FLOPS,
             "alu_frac_forward_backward": n * (MOTION_FLOP_FWD + MOTION_FLOP_BWD) / (ms_fb * 1e-3) / FP32_PEAK_FLOPS}
 
@@ -632,7 +641,7 @@ def main():
     # ---------------- rigid-motion module (inter-frame translation / rotation) on the same Gaussians
     if not args.no_motion:
         log("[bench] rigid-motion module")
-        out["motion"] = bench_motion(torch, dev, p, args.steps)
+        out["motion"] = bench_motion(torch, dev, p, args.steps, st, c, tgt)
 
     # ---------------- per-view baseline: 24 x 6 single-view single-layer forward+backward calls
     if not args.no_per_view:

@@ -267,70 +267,76 @@ __global__ __launch_bounds__(256) void k_motion_bwd(MotionDims d, const float* _
   }
 }
 
-// Weight-gradient tasks: d W[o][i] = sum_g A[o][g] B[i][g], B's last row a constant 1 (the bias).
-struct WTask {
-  int a_field, a_rows;  // A: staged fields [a_field, a_field + a_rows)
-  int b_field, b_rows;  // B: staged fields [b_field, b_field + b_rows), then the row of ones
-  int w_off, b_off;     // where d W and d b go in the weight vector
-};
-
-constexpr int kWTile = 64;  // Gaussians per LDS tile
+// Weight gradients: d W[o][c] = sum_g A[o][g] B[c][g] and d b[o] = sum_g A[o][g], with A the
+// layer's output gradients and B its inputs, both staged per Gaussian. A block takes one layer of
+// one head (blockIdx.y) and a range of Gaussians, 64 at a time through LDS stored Gaussian-major,
+// so that four consecutive rows are one 16-byte read; each thread owns a 4 x 4 tile of d W
+// (2 reads per 16 FMAs) and, for the tiles in column 0, the 4 bias sums.
+constexpr int kWTile = 64;     // Gaussians per LDS tile
+constexpr int kWPad = kHid + 4;  // LDS row: 64 values + pad (16-byte aligned rows)
 
 __global__ __launch_bounds__(256) void k_motion_wgrad(int n, int per_block, const float* __restrict__ stage,
                                                       float* __restrict__ d_weights) {
-  __shared__ float sa[kHid][kWTile + 1];
-  __shared__ float sb[kHid + 1][kWTile + 1];
-  // six tasks per head: W1 (A = dz1, B = h), W2 (A = dz2, B = a1), W3 (A = dy, B = a2)
+  __shared__ __align__(16) float sa[kWTile][kWPad];  // [g][o]
+  __shared__ __align__(16) float sb[kWTile][kWPad];  // [g][c]
   const int task = blockIdx.y;
   const int head = task / 3, layer = task % 3;
   const int f0 = head_fields(head);
   const int out = head == 0 ? 3 : 4;
   const int wbase = head == 0 ? kWMu : kWR;
-  WTask tk;
-  if (layer == 0) {
-    tk = {f0 + kHid, kHid, kFH, kIn, wbase, wbase + kHid * kIn};
-  } else if (layer == 1) {
-    tk = {f0 + 3 * kHid, kHid, f0, kHid, wbase + kHid * kIn + kHid, wbase + kHid * kIn + kHid + kHid * kHid};
-  } else {
-    const int w3 = wbase + kHid * kIn + kHid + kHid * kHid + kHid;
-    tk = {f0 + 4 * kHid, out, f0 + 2 * kHid, kHid, w3, w3 + out * kHid};
+  int a_field, a_rows, b_field, b_rows, w_off;
+  if (layer == 0) {         // W1: A = dz1, B = h
+    a_field = f0 + kHid; a_rows = kHid; b_field = kFH; b_rows = kIn; w_off = wbase;
+  } else if (layer == 1) {  // W2: A = dz2, B = a1
+    a_field = f0 + 3 * kHid; a_rows = kHid; b_field = f0; b_rows = kHid; w_off = wbase + kHid * kIn + kHid;
+  } else {                  // W3: A = dy, B = a2
+    a_field = f0 + 4 * kHid; a_rows = out; b_field = f0 + 2 * kHid; b_rows = kHid;
+    w_off = wbase + kHid * kIn + kHid + kHid * kHid + kHid;
   }
-  const int cols = tk.b_rows + 1;
-  const int entries = tk.a_rows * cols;
-  float acc[17];
+  const int bias_off = w_off + a_rows * b_rows;
+  const int tiles_c = b_rows / 4, tiles_o = (a_rows + 3) / 4;
+  const int t = threadIdx.x;
+  const bool owner = t < tiles_o * tiles_c;
+  const int o0 = 4 * (t / tiles_c), c0 = 4 * (t % tiles_c);
+  float acc[4][4], bacc[4];
 #pragma unroll
-  for (int k = 0; k < 17; ++k) acc[k] = 0.f;
+  for (int r = 0; r < 4; ++r) {
+    bacc[r] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.f;
+  }
   const int g0 = blockIdx.x * per_block, g1 = min(g0 + per_block, n);
   for (int t0 = g0; t0 < g1; t0 += kWTile) {
     __syncthreads();
-    for (int e = threadIdx.x; e < tk.a_rows * kWTile; e += 256) {
+    // rows beyond a_rows (the 3-row head) and Gaussians beyond the range read as zero
+    for (int e = t; e < kHid * kWTile; e += 256) {
       const int r = e / kWTile, g = e % kWTile;
-      sa[r][g] = t0 + g < g1 ? stage[(size_t)(tk.a_field + r) * n + t0 + g] : 0.f;
-    }
-    for (int e = threadIdx.x; e < cols * kWTile; e += 256) {
-      const int r = e / kWTile, g = e % kWTile;
-      sb[r][g] = t0 + g < g1 ? (r < tk.b_rows ? stage[(size_t)(tk.b_field + r) * n + t0 + g] : 1.f) : 0.f;
+      const bool in = t0 + g < g1;
+      sa[g][r] = in && r < a_rows ? stage[(size_t)(a_field + r) * n + t0 + g] : 0.f;
+      sb[g][r] = in && r < b_rows ? stage[(size_t)(b_field + r) * n + t0 + g] : 0.f;
     }
     __syncthreads();
+    if (owner) {
+      for (int g = 0; g < kWTile; ++g) {
+        const float4 av = *reinterpret_cast<const float4*>(&sa[g][o0]);
+        const float4 bv = *reinterpret_cast<const float4*>(&sb[g][c0]);
+        const float ar[4] = {av.x, av.y, av.z, av.w}, br[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
-    for (int k = 0; k < 17; ++k) {
-      const int e = threadIdx.x + 256 * k;
-      if (e < entries) {
-        const int o = e / cols, c = e % cols;
-        float s = 0.f;
-        for (int g = 0; g < kWTile; ++g) s = fmaf(sa[o][g], sb[c][g], s);
-        acc[k] += s;
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(ar[r], br[c], acc[r][c]);
+          bacc[r] += ar[r];
+        }
       }
     }
   }
+  if (!owner) return;
 #pragma unroll
-  for (int k = 0; k < 17; ++k) {
-    const int e = threadIdx.x + 256 * k;
-    if (e < entries) {
-      const int o = e / cols, c = e % cols;
-      float* dst = c < tk.b_rows ? d_weights + tk.w_off + o * tk.b_rows + c : d_weights + tk.b_off + o;
-      unsafeAtomicAdd(dst, acc[k]);
-    }
+  for (int r = 0; r < 4; ++r) {
+    if (o0 + r >= a_rows) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) unsafeAtomicAdd(d_weights + w_off + (o0 + r) * b_rows + c0 + c, acc[r][c]);
+    if (c0 == 0) unsafeAtomicAdd(d_weights + bias_off + o0 + r, bacc[r]);
   }
 }
 
