@@ -186,11 +186,13 @@ class LearningRates:
 
 class JointTrainer:
     """Keyframe training on all views and layers at once: the layer-weighted colour loss (L1, plus
-    D-SSIM when lambda_ssim > 0) and the learned rate."""
+    D-SSIM when lambda_ssim > 0) and a rate term: the learned rate (`rate`), or the paper's own KDE
+    rate of the attributes (`kde_rate=True`, Sec. 3.3: the keyframe objective
+    sum_l lambda^l (L_color^l + lambda_rate L_rate^l) with the Silverman-bandwidth KDE)."""
 
     def __init__(self, params: torch.Tensor, cams: torch.Tensor, targets: torch.Tensor, settings: RenderSettings,
                  rate: RateModel | None, lambda_rate: float = 0.0, extent: float = 1.0,
-                 lrs: LearningRates | None = None, seed: int = 0, lambda_ssim: float = 0.0):
+                 lrs: LearningRates | None = None, seed: int = 0, lambda_ssim: float = 0.0, kde_rate: bool = False):
         self.p, self.cams, self.tgt, self.st = params, cams, targets, settings
         self.n = params.shape[1]
         self.rate, self.lam, self.extent = rate, lambda_rate, extent
@@ -205,6 +207,12 @@ class JointTrainer:
         self.levels = list(settings.level_counts) if settings.level_counts else [self.n]
         self.level_w = list(settings.level_weights) if settings.level_weights else [1.0] * len(self.levels)
         self.lambda_ssim = lambda_ssim
+        self.kde = None
+        if kde_rate:
+            from .entropy import KDE, EntropyModel
+            A = params.shape[0] - 3
+            self.kde = EntropyModel(A, self.n, KDE, params.device, 1.0 / 64, self.levels, self.level_w, lambda_rate)
+            self.kde_loss = torch.zeros(1, dtype=torch.float64, device=params.device)
         if lambda_ssim > 0:
             self.d_img = torch.empty_like(self.img)
             self.loss_ws = LossWorkspace(settings, cams.shape[0], params.device)
@@ -228,6 +236,12 @@ class JointTrainer:
                           seed=self.seed, offset=self.t * A * n,
                           d_attrs_ptr=_off(self.dp, 3 * n) if self.lam > 0 else None)
             self.rate.adam(self.lrs.mlp)
+        if self.kde is not None:
+            # the rate of the attribute rows (everything but the means), noisy symbols, its
+            # gradient added into the same rows of d_params
+            zero(self.kde_loss)
+            self.kde.run(self.p[3:], 1, seed=self.seed, offset=self.t * self.kde.desc.n_attr * n,
+                         loss=self.kde_loss, d_attrs=self.dp[3:])
         self.t += 1
         K = self.p.shape[0] - 11
         lr = self.lrs
@@ -235,6 +249,13 @@ class JointTrainer:
                           (11, 14, lr.sh_dc), (14, 11 + K, lr.sh_rest)):
             if hi > lo:
                 self.opt.step(self.dp, r, self.t, start=lo * n, count=(hi - lo) * n)
+
+    def histogram_rate(self):
+        """Histogram bits per attribute of the current attributes (float64 numpy)."""
+        A = self.p.shape[0] - 3
+        hb = histogram_bits(self.p[3:3 + A], 1.0 / 64)
+        torch.cuda.synchronize()
+        return hb.cpu().numpy()
 
     def eval_rate(self):
         """(MLP bits per attribute in evaluation mode, histogram bits per attribute), float64 numpy."""

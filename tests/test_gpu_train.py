@@ -142,3 +142,21 @@ def test_rigid_phase_recovers_a_translation():
           flush=True)
     assert losses[-1] < 0.67 * losses[0]
     assert float(mean_t @ shift) > 0.5 * float(shift @ shift)
+
+
+def test_keyframe_training_with_the_kde_rate():
+    """The paper's keyframe objective with its own rate (Sec. 3.3): sum_l lambda^l (L1^l +
+    lambda_rate KDE-rate^l). Training with the rate term cuts the histogram rate of the attributes
+    relative to lambda_rate = 0 at a small L1 increase."""
+    print("\n[case] keyframe training with the KDE rate, lambda_rate 0 vs 3e-3", flush=True)
+    from paper_2509_17513_amd.train import JointTrainer
+    res = {}
+    for lam in (0.0, 3e-3):
+        base = _setup(0.0)
+        tr = JointTrainer(base.p, base.cams, base.tgt, base.st, None, lambda_rate=lam, seed=91, kde_rate=True)
+        losses = _train(tr, 120)
+        res[lam] = (losses[-1], tr.histogram_rate().sum(), float(tr.kde_loss.item()))
+        print(f"lambda_rate={lam}: L1 {losses[0]:.5f} -> {losses[-1]:.5f}, histogram bits {res[lam][1]:.0f}, "
+              f"KDE rate term {res[lam][2]:.4g}", flush=True)
+    assert res[3e-3][1] < res[0.0][1]
+    assert res[3e-3][0] < 1.25 * res[0.0][0]
