@@ -354,3 +354,54 @@ class RigidTrainer:
     def translation(self) -> torch.Tensor:
         """The current predicted translation of every Gaussian, [3][n]."""
         return self.res[0, 0:3]
+
+
+class ResidualTrainer:
+    """Residual-deformation phase of inter-frame training (Sec. 3.2 residual deformation, trained with
+    the inter-frame objective of Sec. 3.3): with the frame's translation and rotation fixed (rows
+    0..6 of its residual block, e.g. from the rigid phase), the opacity, scale and colour residuals
+    (rows 7..C-1) are trained with sum_l lambda^l (L1^l + lambda_rate R^l + lambda_reg |residuals|^l),
+    R the Gaussian rate of the residual symbols (the paper's entropy model for residuals) and the
+    last term the temporal L1.
+
+    One step: render forward of all views and layers with the residuals -> fused L1 backward down
+    to the residuals -> Gaussian rate + temporal L1 of the residual rows (their gradient added to
+    the same rows) -> Adam on the residual rows."""
+
+    def __init__(self, keyframe: torch.Tensor, residuals: torch.Tensor, cams: torch.Tensor, targets: torch.Tensor,
+                 settings: RenderSettings, lambda_rate: float = 1e-4, lambda_reg: float = 1e-3, lr: float = 1e-3,
+                 seed: int = 0):
+        from .entropy import GAUSSIAN, EntropyModel
+        dev = keyframe.device
+        C, n = keyframe.shape
+        if tuple(residuals.shape) != (1, C, n):
+            raise ValueError("residuals must be one frame's full block [1][C][n]")
+        self.p, self.res, self.cams, self.tgt = keyframe, residuals, cams, targets
+        self.n, self.C = n, C
+        self.st = dataclasses.replace(settings, res_channels=C)
+        self.d_res = torch.zeros_like(residuals)
+        self.dp = torch.zeros_like(keyframe)
+        self.opt = Adam(residuals)
+        self.lr, self.seed = lr, seed
+        levels = list(settings.level_counts) if settings.level_counts else [n]
+        weights = list(settings.level_weights) if settings.level_weights else [1.0] * len(levels)
+        self.ent = EntropyModel(C - 7, n, GAUSSIAN, dev, 1.0 / 64, levels, weights, lambda_rate, lambda_reg)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.rate_loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.t = 0
+        self.img, self.ws = render_forward(self.st, keyframe, cams, 1, residuals)  # sizes the workspace
+
+    def step(self, check_overflow: bool = False):
+        zero(self.loss)
+        zero(self.rate_loss)
+        render_forward(self.st, self.p, self.cams, 1, self.res, ws=self.ws, image=self.img,
+                       check_overflow=check_overflow)
+        zero(self.d_res)
+        zero(self.dp)
+        render_backward(self.st, self.p, self.cams, self.ws, 1, self.res, image=self.img, target=self.tgt,
+                        d_params=self.dp, d_residuals=self.d_res, loss=self.loss)
+        A = self.C - 7
+        self.ent.run(self.res[0, 7:], 1, seed=self.seed, offset=self.t * A * self.n, loss=self.rate_loss,
+                     d_attrs=self.d_res[0, 7:])
+        self.t += 1
+        self.opt.step(self.d_res, self.lr, self.t, start=7 * self.n, count=(self.C - 7) * self.n)
