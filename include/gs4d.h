@@ -5,9 +5,14 @@
  * (Sec. 3.1, Eq. 1 and the covariance factorisation), front-to-back alpha
  * compositing of depth-ordered Gaussians (Eq. 2) for every nested layer
  * (progressive rendering, Eq. 4), frame composition of a group from its
- * keyframe and residuals (Sec. 3.2, pose update and Eq. 7), the backward of
- * all of these for the layer-weighted L1 colour loss (Sec. 3.3, keyframe loss,
- * D-SSIM weight 0), and the rate terms of the attributes.
+ * keyframe and residuals (Sec. 3.2, pose update and Eq. 7), and the backward of
+ * all of these (with the layer-weighted L1 colour loss fused, Sec. 3.3);
+ * around it: the colour loss with its D-SSIM term (gs_color_loss), the rate of
+ * the quantised attributes (a learned Laplace model, gs_rate_model; the empirical
+ * histogram, gs_rate_histogram; the paper's KDE and Gaussian entropy models,
+ * gs_entropy_model), the rigid-motion module of inter-frame training
+ * (gs_motion_*), and the significance ranking and quantised 2D feature maps of
+ * the progressive bitstream (gs_significance_order, gs_*_maps).
  *
  * General rules
  *  - Every buffer pointer is a DEVICE pointer owned by the caller, unless a
