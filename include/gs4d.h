@@ -314,12 +314,21 @@ int gs_check_status(void* ws, void* stream, int64_t* needed_pairs);
 /* Work counters of the last forward and backward on ws (synchronises stream).
  *  fwd_evals / bwd_evals       (pixel, list entry) pairs whose Gaussian weight
  *                              was evaluated by the raster pass
- *  fwd_contribs / bwd_contribs (pixel, entry, layer) compositing updates */
+ *  fwd_contribs / bwd_contribs (pixel, entry, layer) compositing updates
+ * The raster passes count only while counting is enabled (gs_set_work_counters);
+ * otherwise these four read 0. */
 typedef struct {
   int32_t overflow, pad;
   int64_t needed_pairs, fwd_evals, fwd_contribs, bwd_evals, bwd_contribs;
 } gs_stats;
 int gs_workspace_stats(void* ws, void* stream, gs_stats* out);
+
+/* Process-wide switch of the raster work counters (off at load): raster passes launched
+ * while it is on run an instrumented variant of their kernels that also counts its work
+ * (a few per cent slower; results are identical). Host-only, thread-safe; takes effect at
+ * the next launch (a captured graph keeps the variant it captured). Returns the previous
+ * setting. */
+int gs_set_work_counters(int enable);
 
 /* Text of an error code, and the last HIP error message of this thread. */
 const char* gs_error_string(int code);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
@@ -119,6 +120,9 @@ int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap
 }  // namespace
 
 int report_arg(const char* msg) { return fail_arg(msg); }
+
+std::atomic<int> g_work_counting{0};
+bool work_counting() { return g_work_counting.load(std::memory_order_relaxed) != 0; }
 int report_hip(hipError_t e, const char* where) { return fail_hip(e, where); }
 int require_device() { return check_device(); }
 
@@ -452,6 +456,8 @@ int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int
   if (rc == GS_OK) *best = cur;
   return rc;
 }
+
+int gs_set_work_counters(int enable) { return g_work_counting.exchange(enable ? 1 : 0); }
 
 int gs_workspace_stats(void* ws, void* stream, gs_stats* out) {
   if (!ws || !out) return fail_arg("NULL argument");

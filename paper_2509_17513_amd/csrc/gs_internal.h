@@ -60,6 +60,9 @@ struct Layout {
 
 Layout make_layout(const RenderDims& d);
 
+// Whether the raster passes count their work (gs_set_work_counters; off by default).
+bool work_counting();
+
 // ---- launchers (gs_render.hip) ----
 hipError_t launch_compose_fwd(const RenderDims& d, const float* params, const float* res, float* composed,
                               hipStream_t st);

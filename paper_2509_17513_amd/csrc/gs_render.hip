@@ -16,14 +16,20 @@
 //                     8x8 quadrant (or 16x4 strip): records are staged through
 //                     LDS in batches of 256; every pixel composites all layers
 //                     at once (Eq. 2 for each index set of Eq. 4) and stops
-//                     when every layer has reached the transmittance floor
+//                     when every layer has reached the transmittance floor.
+//                     Each wave walks the staged entries it may need (a ballot
+//                     mask per 64 entries, scalar find-first-set) and updates
+//                     its layers with selects, skipping layers closed in all
+//                     of its lanes
 // Backward:
 //   k_raster_bwd      reverse traversal from each layer's last contributor over
-//                     per-wave lists of the staged entries the wave can use;
-//                     the transmittance is recovered by division, so no
-//                     per-pixel lists are stored; a permlane/DPP reduce-scatter
-//                     per entry, LDS sums of the four waves, then one atomic
-//                     per (record, value) and batch
+//                     the staged entries each wave can use (ballot masks walked
+//                     back to front); the transmittance is recovered by
+//                     division, so no per-pixel lists are stored; a
+//                     permlane/DPP reduce-scatter per entry, LDS sums of the
+//                     four waves, then one atomic per (record, value) and batch
+// Both raster kernels have a variant that also counts their work (COUNT), used
+// only while counting is switched on.
 //   k_project_bwd     one thread per Gaussian, all views and frames in registers
 //   k_compose_bwd     suffix sums and the quaternion-product chain over frames
 #include <hip/hip_runtime.h>
@@ -1194,7 +1200,30 @@ __device__ __forceinline__ int compact_slot(bool keep, uint32_t* s_wcnt, int* to
   return off + (int)popc_below(m);
 }
 
+// Open-layer state of the forward compositor, read from the signs of Tr (a closed layer holds
+// -T): nlhi = bound of the lane's highest open layer (0 if none), wopen = the layers open in
+// some lane of the wave and whi = the bound of the highest of them (both wave-uniform). Called
+// with every lane of the wave active. The state only shrinks, so a stale copy is a superset of
+// the true one: it costs evaluations, never a contribution.
 template <int MAXL>
+__device__ __forceinline__ void open_state(const RenderDims& d, const float* Tr, uint32_t& nlhi, uint32_t& wopen,
+                                           uint32_t& whi) {
+  nlhi = 0;
+  wopen = 0;
+  whi = 0;
+#pragma unroll
+  for (int l = 0; l < MAXL; ++l) {
+    if (l >= d.L) break;
+    const bool open = Tr[l] > 0.f;
+    nlhi = open ? (uint32_t)d.lv[l] : nlhi;
+    if (__ballot(open) != 0ull) {
+      wopen |= 1u << l;
+      whi = (uint32_t)d.lv[l];
+    }
+  }
+}
+
+template <int MAXL, bool COUNT>
 __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ lists,
@@ -1204,27 +1233,28 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
   TileCtx c;
   if (!tile_ctx(d, ranges, c)) return;
   __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
-  __shared__ float4 s_b[kTilePix];  // scaled conic a2, b2, c2, first layer bits
+  __shared__ float4 s_b[kTilePix];  // scaled conic a2, b2, c2, (first layer | quadrant mask << 8) bits
   __shared__ float4 s_c[kTilePix];  // r, g, b, list position bits
   __shared__ uint32_t s_wcnt[kTilePix / 64];
   __shared__ uint32_t s_hi;
   const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
+  const int t = threadIdx.x;
+  const uint32_t qbit = 1u << (8 + __builtin_amdgcn_readfirstlane(t >> 6));
   // Tr[l] > 0: open layer and its transmittance; a closed layer keeps -T (its final
   // transmittance, negated), so that T (1 - alpha) < t_stop rejects it with no extra test
   float Tr[MAXL], Cr[MAXL], Cg[MAXL], Cb[MAXL];
   uint32_t last[MAXL];
-  uint32_t alive = c.inside ? ((1u << d.L) - 1u) : 0u;
 #pragma unroll
   for (int l = 0; l < MAXL; ++l) {
-    Tr[l] = ((alive >> l) & 1u) ? 1.f : -1.f;
+    Tr[l] = (c.inside && l < d.L) ? 1.f : -1.f;
     Cr[l] = Cg[l] = Cb[l] = 0.f;
     last[l] = 0;
   }
-  uint32_t nlhi = alive ? (uint32_t)d.lv[d.L - 1] : 0u;
+  uint32_t nlhi, wopen, whi;
   const size_t recbase = (size_t)c.b * d.n;
-  const int t = threadIdx.x;
   uint32_t n_eval = 0, n_contrib = 0;
   for (uint32_t base = c.range.x; base < c.range.y; base += kTilePix) {
+    open_state<MAXL>(d, Tr, nlhi, wopen, whi);
     // entries of index >= every pixel's highest open layer bound are useless to the whole tile
     if (t == 0) s_hi = 0;
     __syncthreads();
@@ -1240,60 +1270,64 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
     if (gi < hib) {
       const float4* r = rec + 3 * (recbase + gi);
       const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+      const uint32_t qm = quad_mask(d, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, c.ox, c.oy);
       s_a[slot] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
       s_b[slot] = make_float4(-0.5f * kLog2e * r0.z, -kLog2e * r0.w, -0.5f * kLog2e * r1.x,
-                              __uint_as_float(first_layer(d, gi)));
+                              __uint_as_float(first_layer(d, gi) | (qm << 8)));
       s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k - c.range.x + 1));
     }
     __syncthreads();
-    // every wave walks all staged entries: a per-wave quadrant/open-layer list was measured to cost
-    // more (list building, a dependent LDS read per entry) than the evaluations it saves here
-    if (alive) {
-      for (int e = 0; e < cnt; ++e) {
-        const float4 a = s_a[e];
-        if (__float_as_uint(a.w) >= nlhi) continue;
-        const float4 cb = s_b[e];
-        const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
-        ++n_eval;
-        if (!(ev.ga >= d.alpha_min)) continue;
+    // the staged entries this wave may need (ellipse reaching its pixels, index below the bound
+    // of its highest open layer), as a 256-bit ballot mask walked in order with scalar
+    // find-first-set; per lane, the layer updates are selects, and a layer closed in every lane of
+    // the wave is skipped
+    int walked = 0;
+    for (int q = 0; q * 64 < cnt && wopen; ++q) {
+      uint64_t m;
+      {
+        const int e = q * 64 + (t & 63);
+        bool need = false;
+        if (e < cnt) need = (__float_as_uint(s_b[e].w) & qbit) && __float_as_uint(s_a[e].w) < whi;
+        m = __ballot(need);
+      }
+      while (m != 0) {
+      const int e = (q << 6) + (int)__builtin_ctzll(m);
+      m &= m - 1;
+      const float4 a = s_a[e];
+      const float4 cb = s_b[e];
+      const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
+      const bool cand = __float_as_uint(a.w) < nlhi;
+      if (COUNT) n_eval += cand ? 1u : 0u;
+      if (cand && ev.ga >= d.alpha_min) {
         const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
         const float oma = 1.f - al;
         const float4 col = s_c[e];
+        const uint32_t pos = __float_as_uint(col.w);
         const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
-        bool died = false;
 #pragma unroll
         for (int l = 0; l < MAXL; ++l) {
-          if ((uint32_t)l < lmin) continue;  // uniform
+          if ((uint32_t)l < lmin || !((wopen >> l) & 1u)) continue;  // uniform
           const float Tn = Tr[l] * oma;
-          if (!(Tn >= d.t_stop)) {
-            if (Tr[l] > 0.f) {  // this Gaussian would take the layer below the floor: close it
-              Tr[l] = -Tr[l];
-              alive &= ~(1u << l);
-              died = true;
-            }
-            continue;
-          }
-          const float wgt = al * Tr[l];
+          // false for a closed layer; for an open one, this Gaussian would take the layer below
+          // the floor: it closes the layer and does not contribute
+          const bool ok = Tn >= d.t_stop;
+          const float wgt = ok ? al * Tr[l] : 0.f;
           Cr[l] = fmaf(col.x, wgt, Cr[l]);
           Cg[l] = fmaf(col.y, wgt, Cg[l]);
           Cb[l] = fmaf(col.z, wgt, Cb[l]);
-          Tr[l] = Tn;
-          last[l] = __float_as_uint(col.w);
-          ++n_contrib;
-        }
-        if (died) {
-          if (!alive) break;
-          uint32_t hb = 0;
-#pragma unroll
-          for (int l = 0; l < MAXL; ++l)
-            if (l < d.L && ((alive >> l) & 1u)) hb = (uint32_t)d.lv[l];
-          nlhi = hb;
+          Tr[l] = ok ? Tn : -fabsf(Tr[l]);
+          last[l] = ok ? pos : last[l];
+          if (COUNT) n_contrib += ok ? 1u : 0u;
         }
       }
-      if (!alive) nlhi = 0;
+      if ((++walked & 15) == 0) {
+        open_state<MAXL>(d, Tr, nlhi, wopen, whi);
+        if (!wopen) break;
+      }
+      }
     }
   }
-  flush_counters(n_eval, n_contrib, &st->fwd_evals, &st->fwd_contribs);
+  if (COUNT) flush_counters(n_eval, n_contrib, &st->fwd_evals, &st->fwd_contribs);
   if (!c.inside) return;
   const size_t HW = (size_t)d.W * d.H;
   const size_t pix = (size_t)c.py * d.W + c.px;
@@ -1353,7 +1387,7 @@ __device__ __forceinline__ void reduce_scatter9(float* g, int lane) {
   g[8] = v;
 }
 
-template <int MAXL>
+template <int MAXL, bool COUNT>
 __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ lists,
@@ -1374,7 +1408,6 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   __shared__ uint32_t s_wcnt[kTilePix / 64];
   __shared__ uint32_t s_lmax[kMaxLevels];
   __shared__ float s_loss;
-  __shared__ uint8_t s_idx[kTilePix / 64][kTilePix];  // per wave: the staged entries it needs, in order
   const int t = threadIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const uint32_t qbit = 1u << (8 + wv);
@@ -1474,78 +1507,78 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k));
     }
     __syncthreads();
-    // this wave's list: staged entries whose ellipse reaches its quadrant and that lie before the
-    // last contributor of some layer they belong to, for some pixel of the wave
-    int cw = 0;
-    for (int q = 0; q < cnt; q += 64) {
-      const int e = q + lane;
-      bool keep = false;
-      if (e < cnt) {
-        const uint32_t meta = __float_as_uint(s_b[e].w);
-        const uint32_t lm = meta & 0xFFu;
-        uint32_t lim = 0;
+    // this wave's entries: staged entries whose ellipse reaches its quadrant and that lie before the
+    // last contributor of some layer they belong to, for some pixel of the wave; one ballot mask
+    // per 64 staged entries, walked back to front with scalar find-last-set
+    for (int q = (cnt - 1) >> 6; q >= 0; --q) {
+      uint64_t m;
+      {
+        const int e = q * 64 + lane;
+        bool keep = false;
+        if (e < cnt) {
+          const uint32_t meta = __float_as_uint(s_b[e].w);
+          const uint32_t lm = meta & 0xFFu;
+          uint32_t lim = 0;
 #pragma unroll
-        for (int l = 0; l < MAXL; ++l) lim = lm == (uint32_t)l ? lw[l] : lim;
-        keep = (meta & qbit) && __float_as_uint(s_c[e].w) < lim;
+          for (int l = 0; l < MAXL; ++l) lim = lm == (uint32_t)l ? lw[l] : lim;
+          keep = (meta & qbit) && __float_as_uint(s_c[e].w) < lim;
+        }
+        m = __ballot(keep);
       }
-      const unsigned long long m = __ballot(keep);
-      if (keep) s_idx[wv][cw + (int)popc_below(m)] = (uint8_t)e;
-      cw += (int)__popcll(m);
-    }
-    for (int jw = cw - 1; jw >= 0; --jw) {
-      const int j = s_idx[wv][jw];
+      while (m != 0) {
+      const int bit = 63 - (int)__builtin_clzll(m);
+      m &= ~(1ull << bit);
+      const int j = (q << 6) + bit;
       const float4 cb = s_b[j];
       const float4 a = s_a[j];
       const float4 col = s_c[j];
       const uint32_t kk = __float_as_uint(col.w);
       const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
-      // some lane of the wave is a candidate (the list holds no other entries); straight-line
-      // code from here on (lanes that are not candidates compute and discard), so that the
-      // accumulators below need no copies at control-flow joins
-      bool cand = false;
-#pragma unroll
-      for (int l = 0; l < MAXL; ++l) cand = cand || ((uint32_t)l >= lmin && kk < last[l]);
+      // some lane of the wave is a candidate (the list holds no other entries); lanes that are
+      // not candidates compute the evaluation and discard it
       const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
-      n_eval += cand ? 1u : 0u;
-      const bool hit = cand && ev.ga >= d.alpha_min;
+      const bool hit = ev.ga >= d.alpha_min;
       const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
       const float oma = 1.f - al;
       const float ioma = __builtin_amdgcn_rcpf(oma);
-      float g[9];
-      g[6] = g[7] = g[8] = 0.f;
-      float dal = 0.f;
-      bool contrib = false;
+      float gr = 0.f, gg = 0.f, gb = 0.f, dal = 0.f;
+      // cand: the pixel lies before the last contributor of some layer the entry belongs to; the
+      // per-layer comparisons serve both the count and the layer updates (bitwise, no branches)
+      bool cand = false, contrib = false;
 #pragma unroll
       for (int l = 0; l < MAXL; ++l) {
         if ((uint32_t)l < lmin) continue;  // uniform
-        if (!(hit && kk < last[l])) continue;
+        const bool before = kk < last[l];
+        if (COUNT) cand |= before;
+        if (!(hit & before)) continue;
         const float Tb = Tr[l] * ioma;  // transmittance in front of this Gaussian
         const float wT = al * Tb;
-        g[6] = fmaf(wr[l], wT, g[6]);
-        g[7] = fmaf(wg[l], wT, g[7]);
-        g[8] = fmaf(wb[l], wT, g[8]);
+        gr = fmaf(wr[l], wT, gr);
+        gg = fmaf(wg[l], wT, gg);
+        gb = fmaf(wb[l], wT, gb);
         const float wc = fmaf(wr[l], col.x, fmaf(wg[l], col.y, wb[l] * col.z));
         dal = fmaf(Tb, wc, fmaf(-Q[l], ioma, dal));
         Q[l] = fmaf(wT, wc, Q[l]);
         Tr[l] = Tb;
         contrib = true;
-        ++n_contrib;
+        if (COUNT) ++n_contrib;
       }
-      // the clamp at alpha_max has zero derivative; dal is zero without a contribution
-      const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
-      g[5] = dl * ev.G;
-      const float dp = dl * ev.ga;
-      // conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2)
-      const float dpl = -kLn2 * dp;
-      g[0] = dpl * fmaf(2.f * cb.x, ev.dx, cb.y * ev.dy);
-      g[1] = dpl * fmaf(cb.y, ev.dx, 2.f * cb.z * ev.dy);
-      g[2] = -0.5f * dp * ev.dx * ev.dx;
-      g[3] = -dp * ev.dx * ev.dy;
-      g[4] = -0.5f * dp * ev.dy * ev.dy;
+      if (COUNT) n_eval += cand ? 1u : 0u;
       if (__ballot(contrib) != 0ull) {
+        // the clamp at alpha_max has zero derivative; dal is zero without a contribution
+        const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
+        const float dp = dl * ev.ga;
+        // conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2)
+        const float dpl = -kLn2 * dp;
+        float g[9] = {dpl * fmaf(2.f * cb.x, ev.dx, cb.y * ev.dy), dpl * fmaf(cb.y, ev.dx, 2.f * cb.z * ev.dy),
+                      -0.5f * dp * ev.dx * ev.dx, -dp * ev.dx * ev.dy, -0.5f * dp * ev.dy * ev.dy, dl * ev.G,
+                      gr, gg, gb};
         reduce_scatter9(g, lane);
-        if ((lane & 7) == 0 && g[0] != 0.f) atomicAdd(&s_g[j][vid], g[0]);
-        if (lane == 0 && g[8] != 0.f) atomicAdd(&s_g[j][8], g[8]);
+        // the group leaders add their value, lane 1 the opacity sum (one LDS atomic, per-lane addresses)
+        const bool lead = (lane & 7) == 0;
+        const float x = lead ? g[0] : g[8];
+        if ((lead || lane == 1) && x != 0.f) atomicAdd(&s_g[j][lead ? vid : 8], x);
+      }
       }
     }
     __syncthreads();
@@ -1562,7 +1595,7 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       }
     }
   }
-  flush_counters(n_eval, n_contrib, &st->bwd_evals, &st->bwd_contribs);
+  if (COUNT) flush_counters(n_eval, n_contrib, &st->bwd_evals, &st->bwd_contribs);
 }
 
 // Order-sensitive checksum: sum over i of word_i * (2 i + 1) (mod 2^64).
@@ -1773,16 +1806,25 @@ hipError_t launch_raster_fwd(const RenderDims& d, char* ws, const Layout& lo, fl
   const int per = (d.B * d.T + 7) / 8;
   dim3 grid(per * 8), block(kTilePix);
   ProfScope ps_(K_RASTER_FWD, st);
+  const bool cnt = work_counting();
+#define GS_FWD(L_)                                                                                             \
+  do {                                                                                                         \
+    if (cnt)                                                                                                   \
+      hipLaunchKernelGGL((k_raster_fwd<L_, true>), grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);  \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_raster_fwd<L_, false>), grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl); \
+  } while (0)
   if (d.L == 1)
-    hipLaunchKernelGGL(k_raster_fwd<1>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+    GS_FWD(1);
   else if (d.L == 2)
-    hipLaunchKernelGGL(k_raster_fwd<2>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+    GS_FWD(2);
   else if (d.L <= 4)
-    hipLaunchKernelGGL(k_raster_fwd<4>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+    GS_FWD(4);
   else if (d.L <= 6)
-    hipLaunchKernelGGL(k_raster_fwd<6>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+    GS_FWD(6);
   else
-    hipLaunchKernelGGL(k_raster_fwd<8>, grid, block, 0, st, d, status, ranges, lists, rec, image, tf, nl);
+    GS_FWD(8);
+#undef GS_FWD
   return hipGetLastError();
 }
 
@@ -1797,9 +1839,16 @@ hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, co
   float* g2d = (float*)(ws + lo.grad2d);
   const int per = (d.B * d.T + 7) / 8;
   dim3 grid(per * 8), block(kTilePix);
-#define GS_BWD(L_)                                                                                            \
-  hipLaunchKernelGGL(k_raster_bwd<L_>, grid, block, 0, st, d, status, ranges, lists, rec, tf, nl, image, d_image, \
-                     target, g2d, loss_out)
+  const bool cnt = work_counting();
+#define GS_BWD(L_)                                                                                          \
+  do {                                                                                                      \
+    if (cnt)                                                                                                \
+      hipLaunchKernelGGL((k_raster_bwd<L_, true>), grid, block, 0, st, d, status, ranges, lists, rec, tf, nl, \
+                         image, d_image, target, g2d, loss_out);                                            \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_raster_bwd<L_, false>), grid, block, 0, st, d, status, ranges, lists, rec, tf, nl, \
+                         image, d_image, target, g2d, loss_out);                                            \
+  } while (0)
   ProfScope ps_(K_RASTER_BWD, st);
   if (d.L == 1) GS_BWD(1);
   else if (d.L == 2) GS_BWD(2);

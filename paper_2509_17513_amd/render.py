@@ -116,6 +116,27 @@ class Workspace:
             check(rc, "gs_check_status")
         return rc == _lib.GS_OK, needed.value
 
+    def stats(self) -> dict:
+        """Work counters of the last raster passes on this workspace (synchronises the current
+        stream); evals and contribs read 0 unless counting was on (``work_counters``)."""
+        st = _lib.GsStats()
+        check(lib().gs_workspace_stats(_ptr(self.buf), _stream(self.device), ctypes.byref(st)),
+              "gs_workspace_stats")
+        return {k: int(getattr(st, k)) for k in ("needed_pairs", "fwd_evals", "fwd_contribs", "bwd_evals",
+                                                  "bwd_contribs")}
+
+
+class work_counters:
+    """Context in which raster passes run their work-counting variant (gs_set_work_counters)."""
+
+    def __enter__(self):
+        self.prev = lib().gs_set_work_counters(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().gs_set_work_counters(self.prev)
+        return False
+
 
 def render_forward(settings: RenderSettings, params: torch.Tensor, cams: torch.Tensor, n_frames: int = 1,
                    residuals: torch.Tensor | None = None, ws: Workspace | None = None, image: torch.Tensor | None = None,

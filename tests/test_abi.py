@@ -168,3 +168,14 @@ def test_package_modules_import():
     import importlib
     for m in ("render", "train", "bitstream", "entropy", "motion", "_lib"):
         importlib.import_module(f"paper_2509_17513_amd.{m}")
+
+
+def test_work_counter_switch_is_host_only_and_returns_previous(L):
+    prev = L.gs_set_work_counters(1)
+    try:
+        assert L.gs_set_work_counters(0) == 1
+        assert L.gs_set_work_counters(0) == 0
+        assert L.gs_set_work_counters(5) == 0
+        assert L.gs_set_work_counters(0) == 1
+    finally:
+        L.gs_set_work_counters(prev)

@@ -353,3 +353,28 @@ def test_autograd_function_matches_direct_backward():
     torch.cuda.synchronize()
     assert torch.equal(out, img)
     assert torch.allclose(pg.grad, dp, rtol=1e-5, atol=1e-6 * float(dp.abs().max()))
+
+
+def test_work_counters_count_only_when_enabled():
+    _case("work counters: zero when off; the counting kernels give the same image and gradients, and the "
+          "forward and backward count the same contributions")
+    from paper_2509_17513_amd import render_backward, work_counters
+    w = _small_ring(n=1500, seed=59, w=128, h=80)
+    img0, ws0, (p, c, r, st) = _gpu_forward(w)
+    tgt = torch.from_numpy(w.target).to(p.device)
+    dp0, _ = render_backward(st, p, c, ws0, image=img0, target=tgt)
+    s0 = ws0.stats()
+    with work_counters():
+        img1, ws1, _ = _gpu_forward(w)
+        dp1, _ = render_backward(st, p, c, ws1, image=img1, target=tgt)
+        s1 = ws1.stats()
+    print(s0, s1)
+    assert s0["fwd_evals"] == s0["fwd_contribs"] == s0["bwd_evals"] == s0["bwd_contribs"] == 0
+    assert torch.equal(img0, img1)
+    ok, worst = atomic_order_close(dp0.cpu().numpy(), dp1.cpu().numpy())
+    assert ok, worst
+    assert s1["fwd_contribs"] == s1["bwd_contribs"] > 0
+    # every compositing update belongs to an evaluated (pixel, entry) pair, at most one per layer
+    L = len(w.level_counts)
+    assert 0 < s1["fwd_contribs"] <= L * s1["fwd_evals"]
+    assert 0 < s1["bwd_contribs"] <= L * s1["bwd_evals"]
