@@ -1293,17 +1293,21 @@ __global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* _
       while (m != 0) {
       const int e = (q << 6) + (int)__builtin_ctzll(m);
       m &= m - 1;
+      // all three staged vectors are read up front, so that the colour and first layer are at hand
+      // when some lane contributes
       const float4 a = s_a[e];
       const float4 cb = s_b[e];
+      const float4 col = s_c[e];
+      const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
       const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
       const bool cand = __float_as_uint(a.w) < nlhi;
       if (COUNT) n_eval += cand ? 1u : 0u;
+      // keeps the colour read here, ahead of the branch (the compiler would sink it into it)
+      asm volatile("" ::"v"(col.x), "v"(col.y), "v"(col.z), "v"(col.w));
       if (cand && ev.ga >= d.alpha_min) {
         const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
         const float oma = 1.f - al;
-        const float4 col = s_c[e];
         const uint32_t pos = __float_as_uint(col.w);
-        const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
 #pragma unroll
         for (int l = 0; l < MAXL; ++l) {
           if ((uint32_t)l < lmin || !((wopen >> l) & 1u)) continue;  // uniform
