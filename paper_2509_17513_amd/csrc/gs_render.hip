@@ -1223,8 +1223,10 @@ __device__ __forceinline__ void open_state(const RenderDims& d, const float* Tr,
   }
 }
 
+// at least 7 waves per SIMD for up to 6 layers: the walk waits on LDS and the exp unit, and a
+// seventh wave hides more of that than the registers it costs (71 VGPRs, no spills)
 template <int MAXL, bool COUNT>
-__global__ __launch_bounds__(kTilePix) void k_raster_fwd(RenderDims d, Status* __restrict__ st,
+__global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <= 6 ? 7 : 1))) void k_raster_fwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ lists,
                                                          const float4* __restrict__ rec, float* __restrict__ image,
