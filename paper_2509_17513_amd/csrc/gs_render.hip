@@ -121,14 +121,16 @@ __device__ __forceinline__ float cam_y(const gs_camera& c, float x, float y, flo
 // that G = 2^(a2 dx^2 + b2 dx dy + c2 dy^2) = exp(-q / 2).
 struct AlphaEval {
   float dx, dy, G, ga;  // ga = o * G before the alpha_max clamp
+  float u, v;           // a2 dx + b2 dy and c2 dy: the exponent is u dx + v dy
 };
 __device__ __forceinline__ AlphaEval alpha_eval(float px, float py, float mx, float my, float a2, float b2, float c2,
                                                 float o) {
   AlphaEval r;
   r.dx = px - mx;
   r.dy = py - my;
-  const float u = fmaf(a2, r.dx, b2 * r.dy);
-  r.G = __builtin_amdgcn_exp2f(fmaf(u, r.dx, (c2 * r.dy) * r.dy));
+  r.u = fmaf(a2, r.dx, b2 * r.dy);
+  r.v = c2 * r.dy;
+  r.G = __builtin_amdgcn_exp2f(fmaf(r.u, r.dx, r.v * r.dy));
   r.ga = o * r.G;
   return r;
 }
@@ -1350,6 +1352,10 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
   }
 }
 
+// Constant factors of the nine per-entry gradient sums of the backward (mean x, y; conic A, B, C;
+// opacity; colour r, g, b), applied once to each sum instead of to every pixel's term.
+constexpr float kGradScale[9] = {-kLn2, -kLn2, -0.5f, -1.f, -0.5f, 1.f, 1.f, 1.f, 1.f};
+
 // Wave reduction of nine per-lane values. Values 0..7 are reduce-scattered:
 // each halving step pairs two values and exchanges the halves of the wave
 // that keep them (v_permlane32_swap, then v_permlane16_swap across rows, then a
@@ -1574,13 +1580,15 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
         // the clamp at alpha_max has zero derivative; dal is zero without a contribution
         const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
         const float dp = dl * ev.ga;
-        // conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2)
-        const float dpl = -kLn2 * dp;
-        float g[9] = {dpl * fmaf(2.f * cb.x, ev.dx, cb.y * ev.dy), dpl * fmaf(cb.y, ev.dx, 2.f * cb.z * ev.dy),
-                      -0.5f * dp * ev.dx * ev.dx, -dp * ev.dx * ev.dy, -0.5f * dp * ev.dy * ev.dy, dl * ev.G,
-                      gr, gg, gb};
+        // mean and conic gradients without their constant factors, which kGradScale applies to
+        // the sums: conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2), so dL/dmx = -ln 2 dp (2 a2 dx + b2 dy)
+        // = -ln 2 dp (u + a2 dx), dL/dmy = -ln 2 dp (b2 dx + 2 c2 dy) = -ln 2 dp (b2 dx + v + v),
+        // dL/d(A, B, C) = -(1/2, 1, 1/2) dp (dx^2, dx dy, dy^2)
+        const float pdx = dp * ev.dx, pdy = dp * ev.dy;
+        float g[9] = {dp * fmaf(cb.x, ev.dx, ev.u), dp * (fmaf(cb.y, ev.dx, ev.v) + ev.v), pdx * ev.dx, pdx * ev.dy,
+                      pdy * ev.dy, dl * ev.G, gr, gg, gb};
         reduce_scatter9(g, lane);
-        // the group leaders add their value, lane 1 the opacity sum (one LDS atomic, per-lane addresses)
+        // the group leaders add their value, lane 1 value 8 (one LDS atomic, per-lane addresses)
         const bool lead = (lane & 7) == 0;
         const float x = lead ? g[0] : g[8];
         if ((lead || lane == 1) && x != 0.f) atomicAdd(&s_g[j][lead ? vid : 8], x);
@@ -1595,7 +1603,7 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       for (int v = 0; v < 9; ++v) {
         const float x = s_g[t][v];
         if (x != 0.f) {
-          unsafeAtomicAdd(dst + v, x);
+          unsafeAtomicAdd(dst + v, x * kGradScale[v]);
           s_g[t][v] = 0.f;
         }
       }
