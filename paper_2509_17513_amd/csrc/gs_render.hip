@@ -1257,7 +1257,11 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
   uint32_t nlhi, wopen, whi;
   const size_t recbase = (size_t)c.b * d.n;
   uint32_t n_eval = 0, n_contrib = 0;
+  // the list entry of the next batch is read while this batch is walked
+  uint32_t gnext = c.range.x + t < c.range.y ? lists[c.range.x + t] : 0xFFFFFFFFu;
   for (uint32_t base = c.range.x; base < c.range.y; base += kTilePix) {
+    const uint32_t gi = gnext;
+    gnext = base + kTilePix + t < c.range.y ? lists[base + kTilePix + t] : 0xFFFFFFFFu;
     open_state<MAXL>(d, Tr, nlhi, wopen, whi);
     // entries of index >= every pixel's highest open layer bound are useless to the whole tile
     if (t == 0) s_hi = 0;
@@ -1267,8 +1271,6 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
     const uint32_t hib = s_hi;
     if (hib == 0) break;
     const uint32_t k = base + t;
-    uint32_t gi = 0xFFFFFFFFu;
-    if (k < c.range.y) gi = lists[k];
     int cnt;
     const int slot = compact_slot(gi < hib, s_wcnt, &cnt);
     if (gi < hib) {
