@@ -1314,9 +1314,11 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
         const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
         const float oma = 1.f - al;
         const uint32_t pos = __float_as_uint(col.w);
+        // the entry's layers (lmin and above) that are open in some lane of the wave (uniform)
+        const uint32_t lmask = wopen & (0xFFu << lmin);
 #pragma unroll
         for (int l = 0; l < MAXL; ++l) {
-          if ((uint32_t)l < lmin || !((wopen >> l) & 1u)) continue;  // uniform
+          if (!((lmask >> l) & 1u)) continue;
           const float Tn = Tr[l] * oma;
           // false for a closed layer; for an open one, this Gaussian would take the layer below
           // the floor: it closes the layer and does not contribute
@@ -1559,9 +1561,10 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       // cand: the pixel lies before the last contributor of some layer the entry belongs to; the
       // per-layer comparisons serve both the count and the layer updates (bitwise, no branches)
       bool cand = false, contrib = false;
+      const uint32_t lmask = 0xFFu << lmin;  // the entry's layers (uniform)
 #pragma unroll
       for (int l = 0; l < MAXL; ++l) {
-        if ((uint32_t)l < lmin) continue;  // uniform
+        if (!((lmask >> l) & 1u)) continue;
         const bool before = kk < last[l];
         if (COUNT) cand |= before;
         if (!(hit & before)) continue;
