@@ -1284,10 +1284,9 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
     }
     __syncthreads();
     // the staged entries this wave may need (ellipse reaching its pixels, index below the bound
-    // of its highest open layer), as a 256-bit ballot mask walked in order with scalar
-    // find-first-set; per lane, the layer updates are selects, and a layer closed in every lane of
-    // the wave is skipped
-    int walked = 0;
+    // of its highest open layer), one ballot mask per 64 staged entries walked in order with
+    // scalar find-first-set; per lane, the layer updates are selects, a layer closed in every
+    // lane of the wave is skipped, and the open-layer state is refreshed after each 64 entries
     for (int q = 0; q * 64 < cnt && wopen; ++q) {
       uint64_t m;
       {
@@ -1297,8 +1296,9 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
         m = __ballot(need);
       }
       while (m != 0) {
-      const int e = (q << 6) + (int)__builtin_ctzll(m);
-      m &= m - 1;
+      const int bit = (int)__builtin_ctzll(m);
+      m &= ~(1ull << bit);
+      const int e = (q << 6) + bit;
       // all three staged vectors are read up front, so that the colour and first layer are at hand
       // when some lane contributes
       const float4 a = s_a[e];
@@ -1332,11 +1332,8 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
           if (COUNT) n_contrib += ok ? 1u : 0u;
         }
       }
-      if ((++walked & 15) == 0) {
-        open_state<MAXL>(d, Tr, nlhi, wopen, whi);
-        if (!wopen) break;
       }
-      }
+      open_state<MAXL>(d, Tr, nlhi, wopen, whi);
     }
   }
   if (COUNT) flush_counters(n_eval, n_contrib, &st->fwd_evals, &st->fwd_contribs);
