@@ -729,8 +729,9 @@ struct EllipseRows {
     const float lo = fmaxf(Y0, -dym), hi = fminf(Y1, dym);
     if (!(lo <= hi)) return false;
     const float dr = fminf(fmaxf(dyr, lo), hi), dl = fminf(fmaxf(-dyr, lo), hi);
-    const float xr = mx + (-B * dr + sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
-    const float xl = mx + (-B * dl - sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
+    // hardware square root (about 1 ulp): far inside the 0.01-pixel and 1e-3 threshold margins
+    const float xr = mx + (-B * dr + __builtin_amdgcn_sqrtf(fmaxf(A * tau - det * dr * dr, 0.f))) * iA + 0.01f;
+    const float xl = mx + (-B * dl - __builtin_amdgcn_sqrtf(fmaxf(A * tau - det * dl * dl, 0.f))) * iA - 0.01f;
     // tile tx has pixel centres 16 tx + 0.5 .. 16 tx + 15.5 (clipped to the image)
     const float fl = fminf(fmaxf(ceilf((xl - 15.5f) * (1.f / kTile)), -1.f), (float)d.TX);
     const float fh = fminf(fmaxf(floorf((xr - 0.5f) * (1.f / kTile)), -1.f), (float)d.TX);
@@ -855,7 +856,7 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
   // position; every 16 entries of the segment the wave drains, per lane, the unaligned head up to
   // the next 16-entry boundary of the list and then whole aligned 16-entry runs (four 16-byte
   // stores each), so that at most 31 entries are outstanding
-  constexpr int kRing = 32, kStride = 36;  // stride: 16-byte aligned rows, spread banks
+  constexpr int kRing = 32, kStride = 36;  // stride: 16-byte aligned rows, spread banks; slot 32 is a sink
   __shared__ __align__(16) uint32_t wbuf[TWO ? 2 : 1][64][kStride];
   if (st->overflow & 2u) return;
   const int lane = threadIdx.x;
@@ -904,28 +905,32 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
   };
   for (uint32_t base = start; base < end; base += 64) {
     const uint32_t e = base + lane;
+    // entries past the end of the segment get an empty column range
     const uint2 ent = e < end ? row_lists[e] : make_uint2(0u, 1u);
     const int nin = (int)min(64u, end - base);
-    for (int j = 0; j < nin; ++j) {
-      const uint32_t gi = __builtin_amdgcn_readlane(ent.x, j);
-      const uint32_t rg = __builtin_amdgcn_readlane(ent.y, j);
-      const int txl = (int)(rg & 0xFFFF), txh = (int)(rg >> 16);
-      if (tx0 >= txl && tx0 <= txh) {
-        if (EMIT) wbuf[0][lane][c0 & (kRing - 1)] = gi;
-        ++c0;
+    // blocks of 16 entries with no branch per entry: a lane whose tile the entry does not cover
+    // writes the ring's spare slot kRing and does not advance; one drain per block, so that at
+    // most 16 entries per lane are new since the last drain
+    for (int jb = 0; jb < nin; jb += 16) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int j = jb + u;
+        const uint32_t rg = __builtin_amdgcn_readlane(ent.y, j);
+        const int txl = (int)(rg & 0xFFFF), txh = (int)(rg >> 16);
+        const bool h0 = (tx0 >= txl) & (tx0 <= txh);
+        const bool h1 = TWO && ((tx1 >= txl) & (tx1 <= txh));
+        if (EMIT) {
+          const uint32_t gi = __builtin_amdgcn_readlane(ent.x, j);
+          wbuf[0][lane][h0 ? (c0 & (kRing - 1)) : kRing] = gi;
+          if (TWO) wbuf[TWO ? 1 : 0][lane][h1 ? (c1 & (kRing - 1)) : kRing] = gi;
+        }
+        c0 += h0 ? 1u : 0u;
+        if (TWO) c1 += h1 ? 1u : 0u;
       }
-      if (TWO && tx1 >= txl && tx1 <= txh) {
-        if (EMIT) wbuf[TWO ? 1 : 0][lane][c1 & (kRing - 1)] = gi;
-        ++c1;
-      }
-      if (EMIT && (j & 15) == 15) {  // uniform: at most 16 new entries per lane since the last drain
+      if (EMIT) {
         drain(0, c0, w0, false);
         if (TWO) drain(TWO ? 1 : 0, c1, w1, false);
       }
-    }
-    if (EMIT && (nin & 15)) {
-      drain(0, c0, w0, false);
-      if (TWO) drain(TWO ? 1 : 0, c1, w1, false);
     }
   }
   if (EMIT) {
