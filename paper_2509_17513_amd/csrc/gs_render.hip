@@ -701,13 +701,16 @@ __global__ __launch_bounds__(256) void k_bin_gather(RenderDims d, const uint32_t
     const uint32_t i = svals[seg + k];
     const float4 r0 = rec[3 * (seg + i)], r1 = rec[3 * (seg + i) + 1];
     const uint2 rc = rects[seg + i];
-    // quadratic-form threshold of alpha >= alpha_min, with a relative margin of 1e-3
-    const float tau = 2.f * (logf(r1.y) - logf(d.alpha_min)) * 1.001f + 1e-3f;
+    // quadratic-form threshold of alpha >= alpha_min, with a relative margin of 1e-3 (hardware
+    // log, reciprocal and square root: their ~1e-7 relative errors are far inside the margins)
+    const float tau = 2.f * (__logf(r1.y) - __logf(d.alpha_min)) * 1.001f + 1e-3f;
     const float A = r0.z, B = r0.w, C = r1.x;
     const float det = A * C - B * B;
-    const float dxm = sqrtf(fmaxf(tau * C / det, 0.f));  // half-width of the ellipse
+    const float idet = __builtin_amdgcn_rcpf(det);
+    const float dxm = __builtin_amdgcn_sqrtf(fmaxf(tau * C * idet, 0.f));  // half-width of the ellipse
     o0 = r0;
-    o1 = make_float4(det, 1.f / A, -B * dxm / C, sqrtf(fmaxf(A * tau / det, 0.f)));
+    o1 = make_float4(det, __builtin_amdgcn_rcpf(A), -B * dxm * __builtin_amdgcn_rcpf(C),
+                     __builtin_amdgcn_sqrtf(fmaxf(A * tau * idet, 0.f)));
     o2 = make_float4(tau, 0.f, __uint_as_float(rc.x), __uint_as_float(rc.y));
   }
   brec[3 * (seg + k)] = o0;
