@@ -1233,8 +1233,8 @@ __device__ __forceinline__ void open_state(const RenderDims& d, const float* Tr,
   }
 }
 
-// at least 7 waves per SIMD for up to 6 layers: the walk waits on LDS and the exp unit, and a
-// seventh wave hides more of that than the registers it costs (71 VGPRs, no spills)
+// at least 7 waves per SIMD for up to 6 layers (71 VGPRs, no spills): the walk has long LDS and
+// exp latencies, and a seventh wave hid more of them than the registers it costs
 template <int MAXL, bool COUNT>
 __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <= 6 ? 7 : 1))) void k_raster_fwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
@@ -1555,8 +1555,8 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       const float4 col = s_c[j];
       const uint32_t kk = __float_as_uint(col.w);
       const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
-      // some lane of the wave is a candidate (the list holds no other entries); lanes that are
-      // not candidates compute the evaluation and discard it
+      // some lane of the wave may use the entry (the mask holds no other entries); lanes that
+      // cannot compute the evaluation and discard it
       const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
       const bool hit = ev.ga >= d.alpha_min;
       const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
