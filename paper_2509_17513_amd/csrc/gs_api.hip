@@ -132,6 +132,7 @@ namespace {
 struct ProfRec {
   int id;
   hipEvent_t a, b;
+  bool ended;  // the end event was recorded
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -160,9 +161,13 @@ const char* kKernelNames[K_COUNT] = {
 int prof_begin(int id, hipStream_t st) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   if (!g_prof_on) return -1;
-  ProfRec r{id, prof_event(), prof_event()};
-  if (!r.a || !r.b) return -1;
-  hipEventRecord(r.a, st);
+  ProfRec r{id, prof_event(), prof_event(), false};
+  // a record whose events cannot be made or started is dropped (its events go back to the pool)
+  if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) {
+    if (r.a) g_prof_pool.push_back(r.a);
+    if (r.b) g_prof_pool.push_back(r.b);
+    return -1;
+  }
   g_prof_recs.push_back(r);
   return (int)g_prof_recs.size() - 1;
 }
@@ -170,7 +175,7 @@ int prof_begin(int id, hipStream_t st) {
 void prof_end(int slot, hipStream_t st) {
   if (slot < 0) return;
   std::lock_guard<std::mutex> g(g_prof_mu);
-  if (slot < (int)g_prof_recs.size()) hipEventRecord(g_prof_recs[slot].b, st);
+  if (slot < (int)g_prof_recs.size()) g_prof_recs[slot].ended = hipEventRecord(g_prof_recs[slot].b, st) == hipSuccess;
 }
 
 Layout make_layout(const RenderDims& d) {
@@ -386,7 +391,7 @@ int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int
   const size_t img_words = (size_t)d.B * d.L * 3 * d.W * d.H;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) hipEventDestroy(e0);
+    if (e0) (void)hipEventDestroy(e0);  // clean-up: the creation error is the one reported
     return fail_hip(hipErrorUnknown, "autotune events");
   }
   gs_settings cur = *s;
@@ -451,8 +456,9 @@ int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int
     }
     (phase == 0 ? cur.wave_layout : phase == 1 ? cur.bin_chunk : cur.row_seg) = best_v;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  // clean-up of the timing events; the trials' own status is what this call reports
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc == GS_OK) *best = cur;
   return rc;
 }
@@ -513,10 +519,10 @@ int gs_profile_collect(int32_t max_ids, double* total_ms, int32_t* counts) {
   }
   int rc = GS_OK;
   for (auto& r : g_prof_recs) {
-    hipError_t e = hipEventSynchronize(r.b);
+    hipError_t e = r.ended ? hipEventSynchronize(r.b) : hipErrorNotReady;
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
-    if (e != hipSuccess) rc = fail_hip(e, "profile");
+    if (e != hipSuccess) rc = fail_hip(e, r.ended ? "profile" : "profile: a kernel's end event was not recorded");
     if (r.id < max_ids) {
       if (total_ms) total_ms[r.id] += ms;
       if (counts) counts[r.id] += 1;

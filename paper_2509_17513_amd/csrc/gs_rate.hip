@@ -734,7 +734,7 @@ int gs_rate_autotune(const gs_rate_desc* desc, const float* attrs, const uint16_
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return GS_ERR_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);  // clean-up: the creation error is the one reported
     return GS_ERR_HIP;
   }
   int rc = GS_OK;
@@ -770,8 +770,9 @@ int gs_rate_autotune(const gs_rate_desc* desc, const float* attrs, const uint16_
       best = cand[c];
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  // clean-up of the timing events; the trials' own status is what this call reports
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc == GS_OK) *best_blocks = best;
   return rc;
 }
