@@ -1565,7 +1565,7 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
       float gr = 0.f, gg = 0.f, gb = 0.f, dal = 0.f;
       // cand: the pixel lies before the last contributor of some layer the entry belongs to; the
       // per-layer comparisons serve both the count and the layer updates (bitwise, no branches)
-      bool cand = false, contrib = false;
+      bool cand = false;
       const uint32_t lmask = 0xFFu << lmin;  // the entry's layers (uniform)
 #pragma unroll
       for (int l = 0; l < MAXL; ++l) {
@@ -1582,11 +1582,12 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
         dal = fmaf(Tb, wc, fmaf(-Q[l], ioma, dal));
         Q[l] = fmaf(wT, wc, Q[l]);
         Tr[l] = Tb;
-        contrib = true;
         if (COUNT) ++n_contrib;
       }
       if (COUNT) n_eval += cand ? 1u : 0u;
-      if (__ballot(contrib) != 0ull) {
+      // the reduction runs for every walked entry: one with no contributing lane is rare, and
+      // testing for it cost more than it saved
+      {
         // the clamp at alpha_max has zero derivative; dal is zero without a contribution
         const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
         const float dp = dl * ev.ga;
