@@ -325,9 +325,10 @@ int gs_workspace_stats(void* ws, void* stream, gs_stats* out);
 
 /* Process-wide switch of the raster work counters (off at load): raster passes launched
  * while it is on run an instrumented variant of their kernels that also counts its work
- * (a few per cent slower; results are identical). Host-only, thread-safe; takes effect at
- * the next launch (a captured graph keeps the variant it captured). Returns the previous
- * setting. */
+ * (meant for measurement runs: on the 300k-Gaussian, 24-view workload its forward takes
+ * about 1.8x and its backward 1.1x the time; images and gradients are identical up to
+ * the order of float atomics). Host-only, thread-safe; takes effect at the next launch (a
+ * captured graph keeps the variant it captured). Returns the previous setting. */
 int gs_set_work_counters(int enable);
 
 /* Text of an error code, and the last HIP error message of this thread. */
