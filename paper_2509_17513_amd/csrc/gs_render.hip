@@ -1304,42 +1304,42 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
         m = __ballot(need);
       }
       while (m != 0) {
-      const int bit = (int)__builtin_ctzll(m);
-      m &= ~(1ull << bit);
-      const int e = (q << 6) + bit;
-      // all three staged vectors are read up front, so that the colour and first layer are at hand
-      // when some lane contributes
-      const float4 a = s_a[e];
-      const float4 cb = s_b[e];
-      const float4 col = s_c[e];
-      const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
-      const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
-      const bool cand = __float_as_uint(a.w) < nlhi;
-      if (COUNT) n_eval += cand ? 1u : 0u;
-      // keeps the colour read here, ahead of the branch (the compiler would sink it into it)
-      asm volatile("" ::"v"(col.x), "v"(col.y), "v"(col.z), "v"(col.w));
-      if (cand && ev.ga >= d.alpha_min) {
-        const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
-        const float oma = 1.f - al;
-        const uint32_t pos = __float_as_uint(col.w);
-        // the entry's layers (lmin and above) that are open in some lane of the wave (uniform)
-        const uint32_t lmask = wopen & (0xFFu << lmin);
+        const int bit = (int)__builtin_ctzll(m);
+        m &= ~(1ull << bit);
+        const int e = (q << 6) + bit;
+        // all three staged vectors are read up front, so that the colour and first layer are at hand
+        // when some lane contributes
+        const float4 a = s_a[e];
+        const float4 cb = s_b[e];
+        const float4 col = s_c[e];
+        const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
+        const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
+        const bool cand = __float_as_uint(a.w) < nlhi;
+        if (COUNT) n_eval += cand ? 1u : 0u;
+        // keeps the colour read here, ahead of the branch (the compiler would sink it into it)
+        asm volatile("" ::"v"(col.x), "v"(col.y), "v"(col.z), "v"(col.w));
+        if (cand && ev.ga >= d.alpha_min) {
+          const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
+          const float oma = 1.f - al;
+          const uint32_t pos = __float_as_uint(col.w);
+          // the entry's layers (lmin and above) that are open in some lane of the wave (uniform)
+          const uint32_t lmask = wopen & (0xFFu << lmin);
 #pragma unroll
-        for (int l = 0; l < MAXL; ++l) {
-          if (!((lmask >> l) & 1u)) continue;
-          const float Tn = Tr[l] * oma;
-          // false for a closed layer; for an open one, this Gaussian would take the layer below
-          // the floor: it closes the layer and does not contribute
-          const bool ok = Tn >= d.t_stop;
-          const float wgt = ok ? al * Tr[l] : 0.f;
-          Cr[l] = fmaf(col.x, wgt, Cr[l]);
-          Cg[l] = fmaf(col.y, wgt, Cg[l]);
-          Cb[l] = fmaf(col.z, wgt, Cb[l]);
-          Tr[l] = ok ? Tn : -fabsf(Tr[l]);
-          last[l] = ok ? pos : last[l];
-          if (COUNT) n_contrib += ok ? 1u : 0u;
+          for (int l = 0; l < MAXL; ++l) {
+            if (!((lmask >> l) & 1u)) continue;
+            const float Tn = Tr[l] * oma;
+            // false for a closed layer; for an open one, this Gaussian would take the layer below
+            // the floor: it closes the layer and does not contribute
+            const bool ok = Tn >= d.t_stop;
+            const float wgt = ok ? al * Tr[l] : 0.f;
+            Cr[l] = fmaf(col.x, wgt, Cr[l]);
+            Cg[l] = fmaf(col.y, wgt, Cg[l]);
+            Cb[l] = fmaf(col.z, wgt, Cb[l]);
+            Tr[l] = ok ? Tn : -fabsf(Tr[l]);
+            last[l] = ok ? pos : last[l];
+            if (COUNT) n_contrib += ok ? 1u : 0u;
+          }
         }
-      }
       }
       open_state<MAXL>(d, Tr, nlhi, wopen, whi);
     }
@@ -1547,63 +1547,63 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
         m = __ballot(keep);
       }
       while (m != 0) {
-      const int bit = 63 - (int)__builtin_clzll(m);
-      m &= ~(1ull << bit);
-      const int j = (q << 6) + bit;
-      const float4 cb = s_b[j];
-      const float4 a = s_a[j];
-      const float4 col = s_c[j];
-      const uint32_t kk = __float_as_uint(col.w);
-      const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
-      // some lane of the wave may use the entry (the mask holds no other entries); lanes that
-      // cannot compute the evaluation and discard it
-      const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
-      const bool hit = ev.ga >= d.alpha_min;
-      const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
-      const float oma = 1.f - al;
-      const float ioma = __builtin_amdgcn_rcpf(oma);
-      float gr = 0.f, gg = 0.f, gb = 0.f, dal = 0.f;
-      // cand: the pixel lies before the last contributor of some layer the entry belongs to; the
-      // per-layer comparisons serve both the count and the layer updates (bitwise, no branches)
-      bool cand = false;
-      const uint32_t lmask = 0xFFu << lmin;  // the entry's layers (uniform)
+        const int bit = 63 - (int)__builtin_clzll(m);
+        m &= ~(1ull << bit);
+        const int j = (q << 6) + bit;
+        const float4 cb = s_b[j];
+        const float4 a = s_a[j];
+        const float4 col = s_c[j];
+        const uint32_t kk = __float_as_uint(col.w);
+        const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
+        // some lane of the wave may use the entry (the mask holds no other entries); lanes that
+        // cannot compute the evaluation and discard it
+        const AlphaEval ev = alpha_eval(fpx, fpy, a.x, a.y, cb.x, cb.y, cb.z, a.z);
+        const bool hit = ev.ga >= d.alpha_min;
+        const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
+        const float oma = 1.f - al;
+        const float ioma = __builtin_amdgcn_rcpf(oma);
+        float gr = 0.f, gg = 0.f, gb = 0.f, dal = 0.f;
+        // cand: the pixel lies before the last contributor of some layer the entry belongs to; the
+        // per-layer comparisons serve both the count and the layer updates (bitwise, no branches)
+        bool cand = false;
+        const uint32_t lmask = 0xFFu << lmin;  // the entry's layers (uniform)
 #pragma unroll
-      for (int l = 0; l < MAXL; ++l) {
-        if (!((lmask >> l) & 1u)) continue;
-        const bool before = kk < last[l];
-        if (COUNT) cand |= before;
-        if (!(hit & before)) continue;
-        const float Tb = Tr[l] * ioma;  // transmittance in front of this Gaussian
-        const float wT = al * Tb;
-        gr = fmaf(wr[l], wT, gr);
-        gg = fmaf(wg[l], wT, gg);
-        gb = fmaf(wb[l], wT, gb);
-        const float wc = fmaf(wr[l], col.x, fmaf(wg[l], col.y, wb[l] * col.z));
-        dal = fmaf(Tb, wc, fmaf(-Q[l], ioma, dal));
-        Q[l] = fmaf(wT, wc, Q[l]);
-        Tr[l] = Tb;
-        if (COUNT) ++n_contrib;
-      }
-      if (COUNT) n_eval += cand ? 1u : 0u;
-      // the reduction runs for every walked entry: one with no contributing lane is rare, and
-      // testing for it cost more than it saved
-      {
-        // the clamp at alpha_max has zero derivative; dal is zero without a contribution
-        const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
-        const float dp = dl * ev.ga;
-        // mean and conic gradients without their constant factors, which kGradScale applies to
-        // the sums: conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2), so dL/dmx = -ln 2 dp (2 a2 dx + b2 dy)
-        // = -ln 2 dp (u + a2 dx), dL/dmy = -ln 2 dp (b2 dx + 2 c2 dy) = -ln 2 dp (b2 dx + v + v),
-        // dL/d(A, B, C) = -(1/2, 1, 1/2) dp (dx^2, dx dy, dy^2)
-        const float pdx = dp * ev.dx, pdy = dp * ev.dy;
-        float g[9] = {dp * fmaf(cb.x, ev.dx, ev.u), dp * (fmaf(cb.y, ev.dx, ev.v) + ev.v), pdx * ev.dx, pdx * ev.dy,
-                      pdy * ev.dy, dl * ev.G, gr, gg, gb};
-        reduce_scatter9(g, lane);
-        // the group leaders add their value, lane 1 value 8 (one LDS atomic, per-lane addresses)
-        const bool lead = (lane & 7) == 0;
-        const float x = lead ? g[0] : g[8];
-        if ((lead || lane == 1) && x != 0.f) atomicAdd(&s_g[j][lead ? vid : 8], x);
-      }
+        for (int l = 0; l < MAXL; ++l) {
+          if (!((lmask >> l) & 1u)) continue;
+          const bool before = kk < last[l];
+          if (COUNT) cand |= before;
+          if (!(hit & before)) continue;
+          const float Tb = Tr[l] * ioma;  // transmittance in front of this Gaussian
+          const float wT = al * Tb;
+          gr = fmaf(wr[l], wT, gr);
+          gg = fmaf(wg[l], wT, gg);
+          gb = fmaf(wb[l], wT, gb);
+          const float wc = fmaf(wr[l], col.x, fmaf(wg[l], col.y, wb[l] * col.z));
+          dal = fmaf(Tb, wc, fmaf(-Q[l], ioma, dal));
+          Q[l] = fmaf(wT, wc, Q[l]);
+          Tr[l] = Tb;
+          if (COUNT) ++n_contrib;
+        }
+        if (COUNT) n_eval += cand ? 1u : 0u;
+        // the reduction runs for every walked entry: one with no contributing lane is rare, and
+        // testing for it cost more than it saved
+        {
+          // the clamp at alpha_max has zero derivative; dal is zero without a contribution
+          const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
+          const float dp = dl * ev.ga;
+          // mean and conic gradients without their constant factors, which kGradScale applies to
+          // the sums: conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2), so dL/dmx = -ln 2 dp (2 a2 dx + b2 dy)
+          // = -ln 2 dp (u + a2 dx), dL/dmy = -ln 2 dp (b2 dx + 2 c2 dy) = -ln 2 dp (b2 dx + v + v),
+          // dL/d(A, B, C) = -(1/2, 1, 1/2) dp (dx^2, dx dy, dy^2)
+          const float pdx = dp * ev.dx, pdy = dp * ev.dy;
+          float g[9] = {dp * fmaf(cb.x, ev.dx, ev.u), dp * (fmaf(cb.y, ev.dx, ev.v) + ev.v), pdx * ev.dx, pdx * ev.dy,
+                        pdy * ev.dy, dl * ev.G, gr, gg, gb};
+          reduce_scatter9(g, lane);
+          // the group leaders add their value, lane 1 value 8 (one LDS atomic, per-lane addresses)
+          const bool lead = (lane & 7) == 0;
+          const float x = lead ? g[0] : g[8];
+          if ((lead || lane == 1) && x != 0.f) atomicAdd(&s_g[j][lead ? vid : 8], x);
+        }
       }
     }
     __syncthreads();
