@@ -65,10 +65,13 @@ typedef struct {
  *                l < L and 1 for l = L); used by the fused L1 gradient.
  *  res_channels  0 (no residuals), 8 (translation 3, rotation quaternion 4,
  *                opacity logit 1), 11 (+ log-scale 3) or 11 + 3 (d+1)^2 (+ SH).
- *  near_plane    Gaussians whose camera depth is <= near_plane are culled.
+ *  near_plane    Gaussians whose camera depth is <= near_plane are culled. The
+ *                depth is computed in FP64 from the frame mean composed in FP64;
+ *                its float32 rounding is the depth-order key (ties by index).
  *  dilation      added to the diagonal of every 2D covariance (pixels^2).
  *  alpha_min     a Gaussian contributes to a pixel iff min(alpha_max, o G) >= alpha_min.
- *  alpha_max     upper clamp of the per-pixel alpha.
+ *  alpha_max     upper clamp of the per-pixel alpha; must be < 1 (the backward
+ *                divides by 1 - alpha), else GS_ERR_INVALID_ARG.
  *  t_stop        compositing stops before a Gaussian that would bring the
  *                transmittance below t_stop (that Gaussian is not included).
  *  bg            background colour added with the final transmittance.

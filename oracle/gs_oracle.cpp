@@ -22,11 +22,10 @@
 //  * alpha = min(alpha_max, o * G); a Gaussian contributes iff alpha >= alpha_min;
 //  * the traversal stops before Gaussian i if T * (1 - alpha_i) < t_stop
 //    (Gaussian i is not included);
-//  * order: increasing camera-space depth, ties broken by lower index. The
-//    depth used for the ORDER (and for the near-plane cull) is the float32
-//    value fmaf(R[8], z, fmaf(R[7], y, fmaf(R[6], x, t[2]))) of float32 inputs,
-//    i.e. the same precision the GPU kernel decides it in; all other
-//    arithmetic is FP64;
+//  * order: increasing depth key, ties broken by lower index, where the key is
+//    the float32 rounding (to nearest) of the camera-space depth t_z of the
+//    exactly composed frame mean (computed here in FP64); a Gaussian is culled
+//    iff t_z <= near_plane;
 //  * pixel (u, v) is sampled at (u + 0.5, v + 0.5);
 //  * EWA projection with the Jacobian's x/z, y/z clamped at 1.3 times the
 //    half-field-of-view tangent, plus `dilation` on the 2D covariance diagonal;
@@ -54,9 +53,10 @@ typedef struct {
   int32_t pad_;
   double near_plane, dilation, alpha_min, alpha_max, t_stop;
   double bg[3];
-  // half-widths of the bands in which an FP32 evaluation may take the other
-  // outcome of a decision (see oc_render)
-  double band_alpha_rel, band_tstop_abs;
+  // Multiplier of the first-order FP32 error bounds that decide which
+  // decisions a float32 evaluation may take the other way (see "Ambiguous
+  // decisions" below); 0 switches the exploration of alternatives off.
+  double band_safety;
 } oc_settings;
 
 }  // extern "C"
@@ -151,7 +151,6 @@ void quat_mul(const T a[4], const T b[4], T out[4]) {
 
 struct Cam {
   double R[9], t[3], fx, fy, cx, cy;
-  float Rf[9], tf[3];
 };
 
 Cam load_cam(const double* c) {
@@ -161,8 +160,6 @@ Cam load_cam(const double* c) {
     k.t[i] = c[4 * i + 3];
   }
   k.fx = c[12]; k.fy = c[13]; k.cx = c[14]; k.cy = c[15];
-  for (int i = 0; i < 9; ++i) k.Rf[i] = (float)k.R[i];
-  for (int i = 0; i < 3; ++i) k.tf[i] = (float)k.t[i];
   return k;
 }
 
@@ -191,18 +188,32 @@ void compose_frame(const oc_settings& s, int n, const double* P, const double* r
   }
 }
 
-// Float32 mean of frame f (sequential float32 sums of the deltas), used only
-// for the depth order and near-plane decision.
-void compose_mean_f32(const oc_settings& s, int n, const float* P32, const float* res32, int f, int i, float m[3]) {
-  for (int c = 0; c < 3; ++c) m[c] = P32[(size_t)c * n + i];
-  if (!res32 || s.res_channels <= 0) return;
-  for (int t = 0; t <= f; ++t)
-    for (int c = 0; c < 3; ++c) m[c] = m[c] + res32[(size_t)t * s.res_channels * n + (size_t)c * n + i];
+// Reading: a Gaussian with any non-finite composed parameter is culled.
+bool all_finite(const oc_settings& s, const double* p) {
+  const int C = n_channels(s.sh_degree);
+  for (int c = 0; c < C; ++c)
+    if (!std::isfinite(p[c])) return false;
+  return true;
 }
 
-inline float depth_key_f32(const Cam& k, const float m[3]) {
-  return std::fma(k.Rf[8], m[2], std::fma(k.Rf[7], m[1], std::fma(k.Rf[6], m[0], k.tf[2])));
-}
+// ------------------------------------------ float32 accuracy (readings)
+// The oracle decides every discrete step (near-plane cull, depth order, the
+// alpha cut, the transmittance stop) in FP64. A float32 evaluation of the same
+// function can take a decision the other way when the FP64 margin is below its
+// rounding error, so the oracle states the accuracy it asks of a float32
+// evaluation and explores both outcomes of every decision inside that band
+// (scaled by band_safety). u = 2^-24 is the float32 unit roundoff. The asked
+// accuracy is that of a careful evaluation from float32 inputs:
+//  * depth: exact up to its float32 rounding (the order key), i.e. computed in
+//    higher precision from the exactly composed frame mean;
+//  * 2D mean: one float32 rounding, 2u |m|;
+//  * conic: (kConicOps + 8 per composed frame) u times its magnitude scale,
+//    grown by sqrt(a c / det) (a cancellation-free determinant);
+//  * the quadratic form: 6 roundings of the magnitude of its terms;
+//  * exp, sigmoid and the product o G: 8u, plus the float32 sums of the
+//    frame's opacity-logit deltas.
+constexpr double kU = 5.9604644775390625e-08;  // 2^-24
+constexpr double kConicOps = 24.0;  // roundings on the path params -> conic, per unit of conditioning
 
 // ------------------------------------------------------ projection (O2-O4)
 template <class T>
@@ -210,12 +221,14 @@ struct Proj {
   T mx, my, A, B, C, o, rgb[3];
   // diagnostics (value only)
   double s2d[3], tz, radius;
+  double t_cam[3];     // camera-space mean
+  double conic_err[3];  // conditioning-scaled magnitudes of (A, B, C), see error_bounds
   int flags;  // bit0 x-clamp, bit1 y-clamp, bit2..4 colour clamp r,g,b
 };
 
 // Projects one Gaussian with composed params p (C channels) into camera k.
 // Returns false if it is culled (non-positive quaternion norm, det <= 0).
-// The near-plane test is decided by the caller on the float32 depth key.
+// The near-plane test is decided by the caller on the FP64 depth t_z.
 template <class T>
 bool project(const T* p, const oc_settings& s, const Cam& k, Proj<T>& out) {
   const int deg = s.sh_degree;
@@ -270,6 +283,19 @@ bool project(const T* p, const oc_settings& s, const Cam& k, Proj<T>& out) {
   out.A = cov[2] / det;
   out.B = -cov[1] / det;
   out.C = cov[0] / det;
+  {
+    // Accuracy asked of a float32 evaluation of the conic (see error_bounds):
+    // each entry within eps_c of its magnitude scale, where eps_c grows with
+    // sqrt(a c / det), the conditioning of the 2D covariance, because b and
+    // the determinant lose relative accuracy as the footprint thins.
+    const double ca = val(cov[0]), cc = val(cov[2]), dt = val(det);
+    const double kappa = std::sqrt(std::max(1.0, ca * cc / dt));
+    const double A = val(out.A), Cc = val(out.C);
+    out.conic_err[0] = kappa * std::fabs(A);
+    out.conic_err[1] = kappa * std::sqrt(std::fabs(A * Cc));
+    out.conic_err[2] = kappa * std::fabs(Cc);
+  }
+  for (int a = 0; a < 3; ++a) out.t_cam[a] = val(t[a]);
   out.mx = k.fx * t[0] / t[2] + k.cx;
   out.my = k.fy * t[1] / t[2] + k.cy;
   out.o = 1.0 / (1.0 + exp(-p[10]));
@@ -299,19 +325,72 @@ bool project(const T* p, const oc_settings& s, const Cam& k, Proj<T>& out) {
 // ------------------------------------------------------- scene projection
 struct Rec {  // one visible (frame-view, Gaussian)
   int idx;
-  float key;  // float32 depth (order key)
+  float key;         // float32 rounding of t_z: the order key
+  bool key_amb;      // t_z lies within FP64 rounding of a float32 rounding boundary
+  double tz;         // FP64 camera-space depth
+  double tz_err;     // bound on the FP64 error of t_z
+  double pos_err;    // asked float32 accuracy of the 2D mean (pixels)
+  double conic_err[3];  // asked float32 accuracy of (A, B, C)
+  double o_err;      // asked relative accuracy of o and of the evaluation of exp
+  bool culled;       // t_z <= near_plane
+  bool near_amb;     // t_z within its FP64 error bound of near_plane
   double mx, my, A, B, C, o, rgb[3], radius;
+  int flags;         // projection clamps (Jacobian x/y, colour r/g/b)
 };
 
 struct Scene {
   oc_settings s;
   int n, F, V, B;
   std::vector<double> P, res;          // FP64 copies of the float32 inputs
-  std::vector<float> P32, res32;
   std::vector<Cam> cams;
 };
 
-// All visible records of frame-view b, sorted by (key, index).
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+
+// Error bounds of one record (see "float32 accuracy" above). nf is the number
+// of composed residual frames (0 for a keyframe). The depth t_z is evaluated
+// here in FP64: a few roundings of 2^-53 of the magnitudes involved.
+void error_bounds(const Cam& k, const double* p, int nf, const Proj<double>& pr, Rec& r) {
+  double mag = std::fabs(k.t[2]);
+  for (int j = 0; j < 3; ++j) mag += std::fabs(k.R[6 + j] * p[j]);
+  const double tz = pr.t_cam[2];
+  r.tz = tz;
+  r.tz_err = 16.0 * kU64 * mag;
+  r.key = (float)tz;
+  // the rounding boundaries between the key and its float32 neighbours
+  const double up = (double)std::nextafter(r.key, INFINITY), dn = (double)std::nextafter(r.key, -INFINITY);
+  const double kd = (double)r.key;
+  r.key_amb = std::fabs(tz - 0.5 * (kd + up)) <= r.tz_err || std::fabs(tz - 0.5 * (kd + dn)) <= r.tz_err;
+  r.pos_err = 2.0 * kU * std::max(std::fabs(pr.mx), std::fabs(pr.my));
+  const double ec = (kConicOps + 8.0 * nf) * kU;
+  for (int j = 0; j < 3; ++j) r.conic_err[j] = ec * pr.conic_err[j];
+  r.o_err = 8.0 * kU + nf * kU * (std::fabs(p[10]) + 1.0) * (1.0 - pr.o);
+}
+
+// The record of Gaussian i with composed params p in camera k; false if it is
+// culled (and not within the error bound of the near plane).
+bool make_record(const oc_settings& s, const Cam& k, const double* p, int i, int nf, Rec& r) {
+  if (!all_finite(s, p)) return false;
+  // FP64 depth first: Gaussians far behind the near plane are never projected
+  double tz = k.R[6] * p[0] + k.R[7] * p[1] + k.R[8] * p[2] + k.t[2];
+  if (!(tz > 0.5 * s.near_plane)) return false;
+  Proj<double> pr;
+  if (!project(p, s, k, pr)) return false;
+  if (!(pr.o >= s.alpha_min)) return false;  // can never reach alpha_min
+  error_bounds(k, p, nf, pr, r);
+  r.culled = !(r.tz > s.near_plane);
+  r.near_amb = s.band_safety > 0.0 && std::fabs(r.tz - s.near_plane) <= r.tz_err;
+  if (r.culled && !r.near_amb) return false;
+  r.idx = i;
+  r.mx = pr.mx; r.my = pr.my; r.A = pr.A; r.B = pr.B; r.C = pr.C; r.o = pr.o;
+  for (int c = 0; c < 3; ++c) r.rgb[c] = pr.rgb[c];
+  r.radius = pr.radius;
+  r.flags = pr.flags;
+  return true;
+}
+
+// All records of frame-view b in front of the near plane (or within the error
+// bound of its depth from it), sorted by (key, index).
 std::vector<Rec> project_view(const Scene& sc, int b) {
   const oc_settings& s = sc.s;
   const int n = sc.n;
@@ -320,7 +399,6 @@ std::vector<Rec> project_view(const Scene& sc, int b) {
   std::vector<Rec> out;
   out.reserve(n);
   const double* res = sc.res.empty() ? nullptr : sc.res.data();
-  const float* res32 = sc.res32.empty() ? nullptr : sc.res32.data();
   std::vector<std::vector<Rec>> part;
   int nt = 1;
 #ifdef _OPENMP
@@ -336,20 +414,9 @@ std::vector<Rec> project_view(const Scene& sc, int b) {
     double p[kMaxC];
 #pragma omp for schedule(static)
     for (int i = 0; i < n; ++i) {
-      float m32[3];
-      compose_mean_f32(s, n, sc.P32.data(), res32, f, i, m32);
-      float key = depth_key_f32(k, m32);
-      if (!(key > (float)s.near_plane)) continue;
       compose_frame(s, n, sc.P.data(), res, f, i, p);
-      Proj<double> pr;
-      if (!project(p, s, k, pr)) continue;
-      if (!(pr.o >= s.alpha_min)) continue;  // can never reach alpha_min
       Rec r;
-      r.idx = i; r.key = key;
-      r.mx = pr.mx; r.my = pr.my; r.A = pr.A; r.B = pr.B; r.C = pr.C; r.o = pr.o;
-      for (int c = 0; c < 3; ++c) r.rgb[c] = pr.rgb[c];
-      r.radius = pr.radius;
-      part[tid].push_back(r);
+      if (make_record(s, k, p, i, res ? f + 1 : 0, r)) part[tid].push_back(r);
     }
   }
   for (auto& v : part) out.insert(out.end(), v.begin(), v.end());
@@ -395,21 +462,31 @@ struct Kept {
   int idx;
   double araw;  // o * G (before the alpha_max clamp)
   double G;
+  double eps;   // bound on the relative float32 error of araw
 };
 
-// Per-pixel scan (O5): candidates with o * G >= alpha_min (or within the
-// ambiguity band of it), in order.
+// Per-pixel scan (O5): candidates with o * G >= alpha_min, or within the band
+// of alpha_min in which a float32 evaluation may decide the other way, in
+// order. The relative error of o * exp(power) is the absolute error of power
+// (from the 2D mean, the conic and the evaluation of the quadratic form) plus
+// that of o and of exp.
 void pixel_candidates(const std::vector<Rec>& recs, const int* cand, int ncand, double px, double py,
                       const oc_settings& s, std::vector<Kept>& out) {
   out.clear();
-  const double lo = s.alpha_min * (1.0 - s.band_alpha_rel);
   for (int j = 0; j < ncand; ++j) {
     const Rec& e = recs[cand ? cand[j] : j];
     double dx = px - e.mx, dy = py - e.my;
-    double power = -0.5 * (e.A * dx * dx + 2.0 * e.B * dx * dy + e.C * dy * dy);
+    double q = e.A * dx * dx + 2.0 * e.B * dx * dy + e.C * dy * dy;
+    double power = -0.5 * q;
     double G = std::exp(power);
     double araw = e.o * G;
-    if (araw >= lo) out.push_back({cand ? cand[j] : j, e.idx, araw, G});
+    const double gx = e.A * dx + e.B * dy, gy = e.B * dx + e.C * dy;
+    const double qabs = std::fabs(e.A) * dx * dx + 2.0 * std::fabs(e.B * dx * dy) + std::fabs(e.C) * dy * dy;
+    const double dpow = 0.5 * (e.conic_err[0] * dx * dx + 2.0 * e.conic_err[1] * std::fabs(dx * dy) +
+                               e.conic_err[2] * dy * dy) +
+                        std::sqrt(gx * gx + gy * gy) * e.pos_err + 6.0 * kU * 0.5 * qabs;
+    const double eps = dpow + e.o_err;
+    if (araw >= s.alpha_min * (1.0 - s.band_safety * eps)) out.push_back({cand ? cand[j] : j, e.idx, araw, G, eps});
   }
 }
 
@@ -417,6 +494,7 @@ struct PixOut {
   double rgb[3];
   double T;
   int ncontrib;
+  int stop_k;  // position in the kept list where the traversal ended
   uint64_t sig;
 };
 
@@ -437,6 +515,7 @@ PixOut composite(const std::vector<Rec>& recs, const std::vector<Kept>& L, int n
   for (; k < L.size(); ++k) {
     const Kept& e = L[k];
     if (e.idx >= nl) continue;
+    if (recs[e.rec].culled) continue;
     if (!(e.araw >= s.alpha_min)) continue;
     double a = std::min(s.alpha_max, e.araw);
     double Tn = T * (1.0 - a);
@@ -452,23 +531,31 @@ PixOut composite(const std::vector<Rec>& recs, const std::vector<Kept>& L, int n
   for (int c = 0; c < 3; ++c) o.rgb[c] = C[c] + T * s.bg[c];
   o.T = T;
   o.ncontrib = nc;
+  o.stop_k = (int)k;
   o.sig = h;
   return o;
 }
 
-// Alternative outcomes. A decision whose FP64 margin is inside the band that
-// a float32 evaluation can cross (alpha_min cut within band_alpha_rel of
-// alpha_min, T-stop test within band_tstop_abs of t_stop) is explored both
-// ways, up to kMaxBranch decisions on one path; the colours of all explored
-// paths are the accepted results of the pixel. If more ambiguous decisions
-// lie on one path the pixel is marked as excluded (nvar = -1).
+// Ambiguous decisions. A decision whose FP64 margin is inside the band that a
+// float32 evaluation can cross is explored both ways: the alpha cut of a
+// candidate with araw within its relative bound of alpha_min, and the T-stop
+// test with T' within the bound accumulated along the path (two roundings per
+// factor plus the relative error of each alpha, scaled by alpha / (1 - alpha)).
+// Every such bound is multiplied by band_safety. The exactly defined
+// decisions are explored both ways only where the FP64 evaluation itself
+// cannot settle them: the near-plane cull of a Gaussian with t_z within its
+// FP64 error of near, and the order of two neighbours one of whose depths lies
+// within its FP64 error of a float32 rounding boundary next to the other's key. Up to
+// kMaxBranch decisions are explored on one path; the colours of all explored
+// paths are the accepted results of the pixel. If more ambiguous decisions lie
+// on one path the pixel is marked as excluded (nvar = -1).
 constexpr int kMaxBranch = 4;
 constexpr int kMaxVar = 1 << kMaxBranch;
 
 struct VarCtx {
   const std::vector<Rec>* recs;
   const std::vector<Kept>* L;
-  int nl;
+  const std::vector<int>* order;  // positions in L (the level's candidates, possibly permuted)
   const oc_settings* s;
   double* out;  // [kMaxVar][3]
   int nout;
@@ -476,61 +563,122 @@ struct VarCtx {
   int nflags;
 };
 
-void var_dfs(VarCtx& c, size_t k, double T, double r, double g, double b, int br);
-
-void var_take(VarCtx& c, size_t k, bool include, double T, double r, double g, double b, int br) {
+void var_emit(VarCtx& c, double T, double r, double g, double b) {
+  if (c.nout >= kMaxVar) { c.overflow = true; return; }
   const oc_settings& s = *c.s;
-  if (!include) { var_dfs(c, k + 1, T, r, g, b, br); return; }
-  const Kept& e = (*c.L)[k];
+  double* o = c.out + 3 * c.nout++;
+  o[0] = r + T * s.bg[0]; o[1] = g + T * s.bg[1]; o[2] = b + T * s.bg[2];
+}
+
+void var_dfs(VarCtx& c, size_t k, double T, double epsT, double r, double g, double b, int br);
+
+void var_take(VarCtx& c, size_t k, bool include, double T, double epsT, double r, double g, double b, int br) {
+  const oc_settings& s = *c.s;
+  if (!include) { var_dfs(c, k + 1, T, epsT, r, g, b, br); return; }
+  const Kept& e = (*c.L)[(*c.order)[k]];
+  const bool clamped = e.araw > s.alpha_max;
   double a = std::min(s.alpha_max, e.araw);
   double Tn = T * (1.0 - a);
+  double epsN = epsT + 2.0 * kU + (clamped ? 0.0 : e.eps * a / (1.0 - a));
   bool stop = Tn < s.t_stop;
-  if (std::fabs(Tn - s.t_stop) < s.band_tstop_abs) {
+  const Rec& q = (*c.recs)[e.rec];
+  if (std::fabs(Tn - s.t_stop) <= s.band_safety * epsN * Tn) {
     c.nflags++;
     if (br >= kMaxBranch) { c.overflow = true; return; }
     // explore the other outcome
-    if (stop) {
-      const Rec& q = (*c.recs)[e.rec];
-      var_dfs(c, k + 1, Tn, r + q.rgb[0] * a * T, g + q.rgb[1] * a * T, b + q.rgb[2] * a * T, br + 1);
-    } else {
-      if (c.nout < kMaxVar) {
-        double* o = c.out + 3 * c.nout++;
-        o[0] = r + T * s.bg[0]; o[1] = g + T * s.bg[1]; o[2] = b + T * s.bg[2];
-      }
-    }
+    if (stop)
+      var_dfs(c, k + 1, Tn, epsN, r + q.rgb[0] * a * T, g + q.rgb[1] * a * T, b + q.rgb[2] * a * T, br + 1);
+    else
+      var_emit(c, T, r, g, b);
+    if (c.overflow) return;
   }
-  if (stop) {
-    if (c.nout < kMaxVar) {
-      double* o = c.out + 3 * c.nout++;
-      o[0] = r + T * s.bg[0]; o[1] = g + T * s.bg[1]; o[2] = b + T * s.bg[2];
-    }
-    return;
-  }
-  const Rec& q = (*c.recs)[e.rec];
-  var_dfs(c, k + 1, Tn, r + q.rgb[0] * a * T, g + q.rgb[1] * a * T, b + q.rgb[2] * a * T, br);
+  if (stop) { var_emit(c, T, r, g, b); return; }
+  var_dfs(c, k + 1, Tn, epsN, r + q.rgb[0] * a * T, g + q.rgb[1] * a * T, b + q.rgb[2] * a * T, br);
 }
 
-void var_dfs(VarCtx& c, size_t k, double T, double r, double g, double b, int br) {
+void var_dfs(VarCtx& c, size_t k, double T, double epsT, double r, double g, double b, int br) {
   const oc_settings& s = *c.s;
-  const std::vector<Kept>& L = *c.L;
-  for (; k < L.size(); ++k) {
-    const Kept& e = L[k];
-    if (e.idx >= c.nl) continue;
-    bool inc = e.araw >= s.alpha_min;
-    if (std::fabs(e.araw - s.alpha_min) < s.band_alpha_rel * s.alpha_min) {
+  const std::vector<int>& ord = *c.order;
+  for (; k < ord.size(); ++k) {
+    const Kept& e = (*c.L)[ord[k]];
+    const Rec& rec = (*c.recs)[e.rec];
+    bool inc = !rec.culled && e.araw >= s.alpha_min;
+    bool amb = rec.near_amb || std::fabs(e.araw - s.alpha_min) <= s.band_safety * e.eps * s.alpha_min;
+    if (!inc && !amb) continue;
+    if (amb) {
       c.nflags++;
       if (br >= kMaxBranch) { c.overflow = true; return; }
-      var_take(c, k, !inc, T, r, g, b, br + 1);
+      var_take(c, k, !inc, T, epsT, r, g, b, br + 1);
       if (c.overflow) return;
     }
-    var_take(c, k, inc, T, r, g, b, br);
+    var_take(c, k, inc, T, epsT, r, g, b, br);
     return;
   }
-  if (c.nout < kMaxVar) {
-    double* o = c.out + 3 * c.nout++;
-    o[0] = r + T * s.bg[0]; o[1] = g + T * s.bg[1]; o[2] = b + T * s.bg[2];
-  }
+  var_emit(c, T, r, g, b);
 }
+
+// All accepted colours of one pixel-level: the depth-order alternatives (each
+// unsettled pair of neighbours up to the end of the FP64 traversal swapped or not)
+// times the alternatives of the other decisions. Returns nvar.
+int pixel_variants(const std::vector<Rec>& recs, const std::vector<Kept>& L, int nl, const oc_settings& s,
+                   int stop_k, double* vbuf) {
+  if (!(s.band_safety > 0.0)) return 0;
+  std::vector<int> ord;
+  for (int k = 0; k < (int)L.size(); ++k)
+    if (L[k].idx < nl) ord.push_back(k);
+  std::vector<int> ties;
+  for (size_t j = 0; j + 1 < ord.size(); ++j) {
+    if (ord[j] > stop_k) break;
+    const Rec& a = recs[L[ord[j]].rec];
+    const Rec& b = recs[L[ord[j + 1]].rec];
+    if ((a.key_amb || b.key_amb) && std::nextafter(a.key, INFINITY) >= b.key) {
+      if (!ties.empty() && ties.back() == (int)j - 1) return -1;  // three mutual near-ties
+      ties.push_back((int)j);
+    }
+  }
+  const int nt = (int)ties.size();
+  if (nt > kMaxBranch) return -1;
+  VarCtx c{&recs, &L, nullptr, &s, vbuf, 0, false, nt};
+  for (int m = 0; m < (1 << nt); ++m) {
+    std::vector<int> perm = ord;
+    for (int t = 0; t < nt; ++t)
+      if (m >> t & 1) std::swap(perm[ties[t]], perm[ties[t] + 1]);
+    c.order = &perm;
+    var_dfs(c, 0, 1.0, 0.0, 0.0, 0.0, 0.0, nt);
+    if (c.overflow) return -1;
+  }
+  return c.nflags == 0 ? 0 : c.nout;
+}
+
+// ------------------------------------------------ finite differences (O8)
+double kept_araw(const Rec& e, double px, double py) {
+  const double dx = px - e.mx, dy = py - e.my;
+  return e.o * std::exp(-0.5 * (e.A * dx * dx + 2.0 * e.B * dx * dy + e.C * dy * dy));
+}
+
+// The kept candidates of one pixel (alpha >= alpha_min) among a bucket's
+// records in (key, index) order, leaving out one Gaussian, built only as far
+// as the traversals ask for them.
+struct LazyKept {
+  const std::vector<int>* lst;
+  const std::vector<Rec>* R;
+  int skip_idx;
+  double px, py, amin;
+  size_t pos;
+  std::vector<Kept> kept;
+  bool extend() {
+    while (pos < lst->size()) {
+      const int ci = (*lst)[pos++];
+      const Rec& e = (*R)[ci];
+      if (e.idx == skip_idx) continue;
+      const double a = kept_araw(e, px, py);
+      if (a >= amin) { kept.push_back({ci, e.idx, a, 0.0, 0.0}); return true; }
+    }
+    return false;
+  }
+};
+
+inline bool rec_before(const Rec& a, const Rec& b) { return a.key < b.key || (a.key == b.key && a.idx < b.idx); }
 
 bool load_scene(Scene& sc, const oc_settings* s, int n, const float* params, int F, const float* res, int V,
                 const float* cams) {
@@ -539,11 +687,9 @@ bool load_scene(Scene& sc, const oc_settings* s, int n, const float* params, int
   sc.s = *s;
   sc.n = n; sc.F = F; sc.V = V; sc.B = F * V;
   const int C = n_channels(s->sh_degree);
-  sc.P32.assign(params, params + (size_t)C * n);
-  sc.P.assign(sc.P32.begin(), sc.P32.end());
+  sc.P.assign(params, params + (size_t)C * n);
   if (res && s->res_channels > 0) {
-    sc.res32.assign(res, res + (size_t)F * s->res_channels * n);
-    sc.res.assign(sc.res32.begin(), sc.res32.end());
+    sc.res.assign(res, res + (size_t)F * s->res_channels * n);
   } else {
     sc.s.res_channels = 0;
   }
@@ -573,7 +719,7 @@ void oc_quat_rot(const double* q, double* R) {
 void oc_quat_mul(const double* a, const double* b, double* out) { quat_mul(a, b, out); }
 
 // Per (frame-view, Gaussian) projection: out[b][i][16] =
-// {valid, tz(f32 key), mx, my, cov_xx, cov_xy, cov_yy, A, B, C, o, r, g, b, radius, flags}.
+// {valid, tz, mx, my, cov_xx, cov_xy, cov_yy, A, B, C, o, r, g, b, radius, flags}.
 int oc_project(const oc_settings* s, int n, const float* params, int F, const float* res, int V, const float* cams,
                double* out) {
   Scene sc;
@@ -584,15 +730,15 @@ int oc_project(const oc_settings* s, int n, const float* params, int F, const fl
       double* o = out + ((size_t)b * n + i) * 16;
       std::memset(o, 0, 16 * sizeof(double));
       const int f = b / V;
-      float m32[3];
-      compose_mean_f32(sc.s, n, sc.P32.data(), sc.res32.empty() ? nullptr : sc.res32.data(), f, i, m32);
-      float key = depth_key_f32(sc.cams[b], m32);
-      o[1] = key;
-      if (!(key > (float)sc.s.near_plane)) continue;
       double p[kMaxC];
       compose_frame(sc.s, n, sc.P.data(), sc.res.empty() ? nullptr : sc.res.data(), f, i, p);
+      if (!all_finite(sc.s, p)) continue;
+      const Cam& k = sc.cams[b];
+      const double tz = k.R[6] * p[0] + k.R[7] * p[1] + k.R[8] * p[2] + k.t[2];
+      o[1] = tz;
+      if (!(tz > sc.s.near_plane)) continue;
       Proj<double> pr;
-      if (!project(p, sc.s, sc.cams[b], pr)) continue;
+      if (!project(p, sc.s, k, pr)) continue;
       o[0] = 1.0;
       o[2] = pr.mx; o[3] = pr.my;
       o[4] = pr.s2d[0]; o[5] = pr.s2d[1]; o[6] = pr.s2d[2];
@@ -654,9 +800,7 @@ int oc_render(const oc_settings* s, int n, const float* params, int F, const flo
           if (ncontrib) ncontrib[o * npix + pi] = po.ncontrib;
           if (sig) sig[o * npix + pi] = po.sig;
           if (nvar) {
-            VarCtx c{&recs, &kept, nl, &S, vbuf, 0, false, 0};
-            var_dfs(c, 0, 1.0, 0.0, 0.0, 0.0, 0);
-            int nv = c.overflow ? -1 : (c.nflags == 0 ? 0 : c.nout);
+            int nv = pixel_variants(recs, kept, nl, S, po.stop_k, vbuf);
             nvar[o * npix + pi] = nv;
             if (var && nv > 0) std::memcpy(var + (o * npix + pi) * kMaxVar * 3, vbuf, sizeof(double) * 3 * nv);
           }
@@ -824,6 +968,7 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
       for (int c = 0; c < C; ++c) acc[c] += dc[c];
       double gq[4];
       for (int c = 0; c < 4; ++c) gq[c] = dc[6 + c] + carry_q[c];
+      const bool zero_q = gq[0] == 0.0 && gq[1] == 0.0 && gq[2] == 0.0 && gq[3] == 0.0;
       if (Rc > 0) {
         double* dr = d_res ? d_res + (size_t)f * Rc * n : nullptr;
         if (dr) {
@@ -839,8 +984,9 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
         }
         quat_mul(a, bq, o);
         double gdq[4] = {0, 0, 0, 0}, gprev[4] = {0, 0, 0, 0};
-        for (int m = 0; m < 4; ++m)
-          for (int c = 0; c < 4; ++c) { gdq[c] += gq[m] * o[m].d[c]; gprev[c] += gq[m] * o[m].d[4 + c]; }
+        if (!zero_q)  // a zero cotangent gives a zero gradient, whatever the (possibly non-finite) deltas
+          for (int m = 0; m < 4; ++m)
+            for (int c = 0; c < 4; ++c) { gdq[c] += gq[m] * o[m].d[c]; gprev[c] += gq[m] * o[m].d[4 + c]; }
         if (dr) for (int c = 0; c < 4; ++c) dr[(size_t)(3 + c) * n + i] = gdq[c];
         for (int c = 0; c < 4; ++c) carry_q[c] = gprev[c];
       } else {
@@ -855,4 +1001,260 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
   return 0;
 }
 
+// Central finite differences (O8) of  L = sum d_image * image  (one frame,
+// every view and level) with respect to single parameters, re-compositing only
+// the pixels inside the perturbed Gaussian's footprint (the union of its discs
+// at every perturbed state, plus 2 px).
+//   gauss[m], chan[m]  the Gaussian and parameter channel of each request
+//   h                  absolute step
+//   fd_out[m]          dL/dtheta
+//   status_out[m]      bit 0: some pixel-level used a one-sided difference,
+//                      bit 1: some pixel-level used the step h/10,
+//                      bit 2: some pixel-level was skipped (a kink on both
+//                      sides at both steps), bit 3: invalid request
+//   skipped_out[m]     number of skipped pixel-levels
+// A pixel-level whose event signature (see composite_with) at theta + step or
+// theta - step differs from the one at theta is a kink: the side that keeps
+// the signature gives a one-sided difference; if neither does, the step h/10
+// is tried; if that fails too the pixel-level is skipped and counted.
+int oc_fd(const oc_settings* s_in, int n, const float* params, int V, const float* cams, const double* d_image,
+          int64_t m, const int32_t* gauss, const int32_t* chan, double h, double* fd_out, int32_t* status_out,
+          int64_t* skipped_out) {
+  if (!s_in || !gauss || !chan || !fd_out || !status_out || !skipped_out || !d_image || m < 0 || !(h > 0.0))
+    return -1;
+  oc_settings s0 = *s_in;
+  s0.band_safety = 0.0;
+  s0.res_channels = 0;
+  Scene sc;
+  if (!load_scene(sc, &s0, n, params, 1, nullptr, V, cams)) return -1;
+  const oc_settings& S = sc.s;
+  const int C = n_channels(S.sh_degree);
+  const int L = S.n_levels;
+  const int W = S.width, H = S.height;
+  const int64_t npix = (int64_t)W * H;
+  std::vector<std::vector<Rec>> recs(V);
+  std::vector<Buckets> bks(V);
+  for (int b = 0; b < V; ++b) {
+    recs[b] = project_view(sc, b);
+    bks[b] = make_buckets(S, recs[b]);
+  }
+  // requests grouped by Gaussian
+  std::vector<int> order(m);
+  for (int64_t j = 0; j < m; ++j) order[j] = (int)j;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return gauss[a] < gauss[b]; });
+  std::vector<std::pair<int64_t, int64_t>> groups;
+  for (int64_t j = 0; j < m;) {
+    int64_t e = j;
+    while (e < m && gauss[order[e]] == gauss[order[j]]) ++e;
+    groups.push_back({j, e});
+    j = e;
+  }
+  const double steps[2] = {h, 0.1 * h};
+#pragma omp parallel
+  {
+    LazyKept lk;
+    std::vector<int> E;
+    std::vector<double> Tp, Cp, Ps, Ss;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t gi = 0; gi < (int64_t)groups.size(); ++gi) {
+      const int64_t j0 = groups[gi].first, j1 = groups[gi].second;
+      const int i = gauss[order[j0]];
+      const int nreq = (int)(j1 - j0);
+      std::vector<double> acc(nreq, 0.0);
+      std::vector<int32_t> st(nreq, 0);
+      std::vector<int64_t> skipped(nreq, 0);
+      if (i < 0 || i >= n) {
+        for (int r = 0; r < nreq; ++r) { fd_out[order[j0 + r]] = 0.0; status_out[order[j0 + r]] = 8; skipped_out[order[j0 + r]] = 0; }
+        continue;
+      }
+      double p0[kMaxC];
+      for (int c = 0; c < C; ++c) p0[c] = sc.P[(size_t)c * n + i];
+      for (int b = 0; b < V; ++b) {
+        const Cam& k = sc.cams[b];
+        // states: 0 = theta, then per request r: 1 + 4 r + {0: +h, 1: -h, 2: +h/10, 3: -h/10}
+        const int ns = 1 + 4 * nreq;
+        std::vector<Rec> srec(ns);
+        std::vector<char> svis(ns, 0);
+        double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
+        for (int q = 0; q < ns; ++q) {
+          double p[kMaxC];
+          std::memcpy(p, p0, sizeof(double) * C);
+          if (q > 0) {
+            const int r = (q - 1) / 4, v = (q - 1) % 4;
+            const int ch = chan[order[j0 + r]];
+            if (ch < 0 || ch >= C) continue;
+            p[ch] += (v % 2 == 0 ? 1.0 : -1.0) * steps[v / 2];
+          }
+          svis[q] = make_record(S, k, p, i, 0, srec[q]) ? 1 : 0;
+          if (svis[q]) {
+            const Rec& e = srec[q];
+            const double rad = e.radius + 2.0;
+            bx0 = std::min(bx0, e.mx - rad); bx1 = std::max(bx1, e.mx + rad);
+            by0 = std::min(by0, e.my - rad); by1 = std::max(by1, e.my + rad);
+          }
+        }
+        if (bx0 > bx1) continue;  // invisible in every state
+        const int u0 = std::max(0, (int)std::floor(bx0 - 0.5)), u1 = std::min(W - 1, (int)std::ceil(bx1 - 0.5));
+        const int v0 = std::max(0, (int)std::floor(by0 - 0.5)), v1 = std::min(H - 1, (int)std::ceil(by1 - 0.5));
+        const std::vector<Rec>& R = recs[b];
+        std::vector<PixOut> po(ns);
+        std::vector<char> have(ns);
+        for (int y = v0; y <= v1; ++y)
+          for (int x = u0; x <= u1; ++x) {
+            const double px = x + 0.5, py = y + 0.5;
+            const std::vector<int>& lst = bks[b].lists[(size_t)(y / kBucket) * bks[b].bw + x / kBucket];
+            lk.lst = &lst; lk.R = &R; lk.skip_idx = i; lk.px = px; lk.py = py; lk.amin = S.alpha_min; lk.pos = 0;
+            lk.kept.clear();
+            for (int l = 0; l < L; ++l) {
+              const int nl = S.level_counts[l];
+              if (i >= nl) continue;
+              double w[3];
+              bool any = false;
+              for (int c = 0; c < 3; ++c) {
+                w[c] = d_image[(((size_t)b * L + l) * 3 + c) * npix + (size_t)y * W + x];
+                any = any || w[c] != 0.0;
+              }
+              if (!any) continue;
+              std::fill(have.begin(), have.end(), 0);
+              // The level's kept entries E in order up to where the traversal without
+              // the perturbed Gaussian stops, with prefix transmittance and colour.
+              // Then for each state only the perturbed entry and the stop position
+              // behind it are evaluated: behind it the colour is T' times a suffix
+              // sum and the stop is where T' times a suffix product of (1 - alpha)
+              // falls below t_stop (a binary search: the product does not increase).
+              E.clear(); Tp.clear(); Cp.clear();
+              double T = 1.0, Cc[3] = {0.0, 0.0, 0.0};
+              int stop_pre = -1;
+              for (size_t k = 0;; ++k) {
+                if (k >= lk.kept.size() && !lk.extend()) break;
+                const Kept& e = lk.kept[k];
+                const Rec& r = R[e.rec];
+                if (r.idx >= nl) continue;
+                Tp.push_back(T);
+                for (int c = 0; c < 3; ++c) Cp.push_back(Cc[c]);
+                E.push_back((int)k);
+                const double a = std::min(S.alpha_max, e.araw);
+                const double Tn = T * (1.0 - a);
+                if (Tn < S.t_stop) { stop_pre = (int)E.size() - 1; break; }
+                for (int c = 0; c < 3; ++c) Cc[c] += r.rgb[c] * a * T;
+                T = Tn;
+              }
+              const int ne = (int)E.size();
+              Tp.push_back(T);
+              for (int c = 0; c < 3; ++c) Cp.push_back(Cc[c]);
+              const int end_pre = stop_pre >= 0 ? stop_pre : ne;  // entries composited without x
+              auto ip_of = [&](const Rec& x) {
+                int lo = 0, hi = ne;
+                while (lo < hi) {
+                  const int mid = (lo + hi) / 2;
+                  if (rec_before(R[lk.kept[E[mid]].rec], x)) lo = mid + 1; else hi = mid;
+                }
+                return lo;
+              };
+              const int ip0 = svis[0] ? ip_of(srec[0]) : 0;
+              // suffix products / sums from ip0 over E[ip0 .. end_pre]
+              Ps.clear(); Ss.clear();
+              {
+                double P = 1.0, Sr[3] = {0.0, 0.0, 0.0};
+                for (int k = ip0; k < ne; ++k) {
+                  const Kept& e = lk.kept[E[k]];
+                  const double a = std::min(S.alpha_max, e.araw);
+                  for (int c = 0; c < 3; ++c) Sr[c] += R[e.rec].rgb[c] * a * P;
+                  P *= 1.0 - a;
+                  Ps.push_back(P);
+                  for (int c = 0; c < 3; ++c) Ss.push_back(Sr[c]);
+                }
+              }
+              auto eval = [&](int q, PixOut& o) {
+                const Rec* x = svis[q] ? &srec[q] : nullptr;
+                const double ax = x ? kept_araw(*x, px, py) : 0.0;
+                const bool inc = x && ax >= S.alpha_min;
+                int ip = inc ? ip_of(*x) : ip0;
+                uint64_t h = 1469598103934665603ULL;
+                if (!inc || ip > end_pre) {  // x plays no part: the traversal without it
+                  for (int c = 0; c < 3; ++c) o.rgb[c] = Cp[3 * end_pre + c] + Tp[end_pre] * S.bg[c];
+                  o.sig = mix(h, 0x11ULL + (uint64_t)end_pre);
+                  return;
+                }
+                h = mix(h, 0x22ULL + (uint64_t)ip);
+                const double a = std::min(S.alpha_max, ax);
+                h = mix(h, (ax > S.alpha_max ? 1ULL : 0ULL) + 2ULL * (uint64_t)x->flags);
+                const double T0 = Tp[ip];
+                const double Tn = T0 * (1.0 - a);
+                if (Tn < S.t_stop) {
+                  for (int c = 0; c < 3; ++c) o.rgb[c] = Cp[3 * ip + c] + T0 * S.bg[c];
+                  o.sig = mix(h, 0x33ULL);
+                  return;
+                }
+                if (ip != ip0) {  // another order than at theta: a kink; the colour is not used
+                  o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0;
+                  o.sig = mix(h, 0x44ULL);
+                  return;
+                }
+                // first k in [ip, ne) with Tn * P(k) < t_stop (P(k) includes entry k)
+                int lo = ip, hi = ne;
+                while (lo < hi) {
+                  const int mid = (lo + hi) / 2;
+                  if (Tn * Ps[mid - ip0] < S.t_stop) hi = mid; else lo = mid + 1;
+                }
+                const int ks = lo;  // entries ip .. ks-1 are composited behind x
+                double Tf = Tn;
+                for (int c = 0; c < 3; ++c) o.rgb[c] = Cp[3 * ip + c] + x->rgb[c] * a * T0;
+                if (ks > ip) {
+                  for (int c = 0; c < 3; ++c) o.rgb[c] += Tn * Ss[3 * (ks - 1 - ip0) + c];
+                  Tf = Tn * Ps[ks - 1 - ip0];
+                }
+                for (int c = 0; c < 3; ++c) o.rgb[c] += Tf * S.bg[c];
+                o.sig = mix(h, 0x55ULL + (uint64_t)ks);
+              };
+              auto get = [&](int q) -> const PixOut& {
+                if (!have[q]) {
+                  eval(q, po[q]);
+                  have[q] = 1;
+                }
+                return po[q];
+              };
+              auto val = [&](int q) {
+                const PixOut& o = get(q);
+                return w[0] * o.rgb[0] + w[1] * o.rgb[1] + w[2] * o.rgb[2];
+              };
+              const uint64_t s0g = get(0).sig;
+              for (int r = 0; r < nreq; ++r) {
+                const int qb = 1 + 4 * r;
+                bool done = false;
+                for (int t = 0; t < 2 && !done; ++t) {
+                  const int qp = qb + 2 * t, qm = qb + 2 * t + 1;
+                  const bool okp = get(qp).sig == s0g, okm = get(qm).sig == s0g;
+                  if (okp && okm) {
+                    acc[r] += (val(qp) - val(qm)) / (2.0 * steps[t]);
+                  } else if (okp) {
+                    acc[r] += (val(qp) - val(0)) / steps[t];
+                    st[r] |= 1;
+                  } else if (okm) {
+                    acc[r] += (val(0) - val(qm)) / steps[t];
+                    st[r] |= 1;
+                  } else {
+                    continue;
+                  }
+                  if (t == 1) st[r] |= 2;
+                  done = true;
+                }
+                if (!done) { st[r] |= 4; skipped[r]++; }
+              }
+            }
+          }
+      }
+      for (int r = 0; r < nreq; ++r) {
+        const int j = order[j0 + r];
+        const int ch = chan[j];
+        fd_out[j] = acc[r];
+        status_out[j] = (ch < 0 || ch >= C) ? 8 : st[r];
+        skipped_out[j] = skipped[r];
+      }
+    }
+  }
+  return 0;
+}
+
 }  // extern "C"
+

@@ -198,12 +198,13 @@ def unpack(w_bf16_bits, b_f32, a, weights_f64=None):
 
 
 def rate_model(attrs, ctx, w_bf16_bits, b_f32, step, mode=0, seed=0, offset=0, sym_w=None, emulate_bf16=True,
-               want_grad=True, weights_f64=None, fit_scale=None):
+               want_grad=True, weights_f64=None, fit_scale=None, want_abs=False):
     """Learned rate. attrs [A][N] float32, ctx [16][N] (BF16 values as float64).
     Returns dict: bits [A] (unweighted per-attribute totals), loss (sum_i w_i sum_a bits),
     d_attrs [A][N] (train mode: dloss/dy through the additive noise), d_w [A][W_PER_ATTR],
     d_b [A][B_PER_ATTR] (gradients of fit_scale * sum_i sum_a bits, the maximum-likelihood fit of
-    the entropy model; of the loss itself when fit_scale is None), m, b [A][N]."""
+    the entropy model; of the loss itself when fit_scale is None), m, b [A][N]; with want_abs also
+    d_w_abs, d_b_abs: the same sums over symbols taken of the absolute values of their terms."""
     attrs = np.asarray(attrs, np.float32).astype(np.float64)
     A, N = attrs.shape
     q = float(np.float32(step))
@@ -216,6 +217,9 @@ def rate_model(attrs, ctx, w_bf16_bits, b_f32, step, mode=0, seed=0, offset=0, s
     X = np.asarray(ctx, np.float64).T  # [N][16]
     out = {"bits": np.zeros(A), "loss": 0.0, "d_attrs": np.zeros((A, N)), "d_w": np.zeros((A, W_PER_ATTR)),
            "d_b": np.zeros((A, B_PER_ATTR)), "m": np.zeros((A, N)), "b": np.zeros((A, N))}
+    if want_abs:
+        out["d_w_abs"] = np.zeros((A, W_PER_ATTR))
+        out["d_b_abs"] = np.zeros((A, B_PER_ATTR))
     for a in range(A):
         W1, b1, W2, b2, W3, b3 = unpack(w_bf16_bits, b_f32, a, weights_f64)
         z1 = X @ W1.T + b1
@@ -246,6 +250,11 @@ def rate_model(attrs, ctx, w_bf16_bits, b_f32, step, mode=0, seed=0, offset=0, s
         dW1 = dz1.T @ X
         out["d_w"][a] = np.concatenate([dW1.reshape(-1), dW2.reshape(-1), dW3.reshape(-1)])
         out["d_b"][a] = np.concatenate([dz1.sum(0), dz2.sum(0), do.sum(0)])
+        if want_abs:
+            ado, adz2, adz1 = np.abs(do), np.abs(dz2), np.abs(dz1)
+            out["d_w_abs"][a] = np.concatenate([(adz1.T @ np.abs(X)).reshape(-1), (adz2.T @ np.abs(h1)).reshape(-1),
+                                                (ado.T @ np.abs(h2)).reshape(-1)])
+            out["d_b_abs"][a] = np.concatenate([adz1.sum(0), adz2.sum(0), ado.sum(0)])
     return out
 
 

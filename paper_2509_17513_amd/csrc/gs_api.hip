@@ -76,8 +76,10 @@ int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap
     g_last_error = "only 16x16 tiles are implemented";
     return GS_ERR_UNSUPPORTED;
   }
-  if (!(s->alpha_min > 0.f) || !(s->alpha_max <= 1.f) || !(s->alpha_min <= s->alpha_max))
-    return fail_arg("need 0 < alpha_min <= alpha_max <= 1");
+  // alpha_max < 1: the backward recovers the transmittance in front of a
+  // Gaussian by dividing by 1 - alpha
+  if (!(s->alpha_min > 0.f) || !(s->alpha_max < 1.f) || !(s->alpha_min <= s->alpha_max))
+    return fail_arg("need 0 < alpha_min <= alpha_max < 1");
   if (!(s->t_stop >= 0.f) || !(s->near_plane > 0.f) || !(s->dilation >= 0.f))
     return fail_arg("need t_stop >= 0, near_plane > 0, dilation >= 0");
   if (cap < 0 || cap > 0xFFFFFFFFll) return fail_arg("pair_capacity must be in [0, 2^32)");
@@ -296,7 +298,7 @@ int gs_render_forward(const gs_settings* s, int32_t n, const float* params, int3
       return fail_hip(e, "compose_fwd");
   }
   if (n > 0) {
-    if ((e = launch_project_fwd(d, params, (const float*)(w + lo.composed), cams, w, lo, st)) != hipSuccess)
+    if ((e = launch_project_fwd(d, params, d.Rc > 0 ? residuals : nullptr, (const float*)(w + lo.composed), cams, w, lo, st)) != hipSuccess)
       return fail_hip(e, "project_fwd");
     uint32_t *sk, *sv;
     if ((e = launch_sort(d, w, lo, &sk, &sv, st)) != hipSuccess) return fail_hip(e, "sort");
@@ -345,7 +347,8 @@ int gs_render_backward(const gs_settings* s, int32_t n, const float* params, int
     return fail_hip(e, "zero");
   if ((e = launch_raster_bwd(d, w, lo, image, d_image, target, loss_out, st)) != hipSuccess)
     return fail_hip(e, "raster_bwd");
-  if ((e = launch_project_bwd(d, params, (const float*)(w + lo.composed), cams, w, lo, d_params, st)) != hipSuccess)
+  if ((e = launch_project_bwd(d, params, d.Rc > 0 ? residuals : nullptr, (const float*)(w + lo.composed), cams, w, lo, d_params,
+                              st)) != hipSuccess)
     return fail_hip(e, "project_bwd");
   if (d.Rc > 0) {
     if ((e = launch_compose_bwd(d, params, residuals, (const float*)(w + lo.composed),

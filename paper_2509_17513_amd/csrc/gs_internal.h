@@ -66,7 +66,7 @@ bool work_counting();
 // ---- launchers (gs_render.hip) ----
 hipError_t launch_compose_fwd(const RenderDims& d, const float* params, const float* res, float* composed,
                               hipStream_t st);
-hipError_t launch_project_fwd(const RenderDims& d, const float* params, const float* composed,
+hipError_t launch_project_fwd(const RenderDims& d, const float* params, const float* res, const float* composed,
                               const gs_camera* cams, char* ws, const Layout& lo, hipStream_t st);
 hipError_t launch_sort(const RenderDims& d, char* ws, const Layout& lo, uint32_t** keys_out, uint32_t** vals_out,
                        hipStream_t st);
@@ -75,7 +75,7 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
 hipError_t launch_raster_fwd(const RenderDims& d, char* ws, const Layout& lo, float* image, hipStream_t st);
 hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, const float* image,
                              const float* d_image, const float* target, float* loss_out, hipStream_t st);
-hipError_t launch_project_bwd(const RenderDims& d, const float* params, const float* composed,
+hipError_t launch_project_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,
                               const gs_camera* cams, char* ws, const Layout& lo, float* d_params, hipStream_t st);
 hipError_t launch_compose_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,
                               const float* d_composed, float* d_params, float* d_res, hipStream_t st);

@@ -103,16 +103,13 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const f
   g[0] = gx; g[1] = gy; g[2] = gz;
 }
 
-// Camera-space depth; the same float32 expression decides the depth order
-// and the near-plane test.
-__device__ __forceinline__ float cam_z(const gs_camera& c, float x, float y, float z) {
-  return fmaf(c.viewmat[10], z, fmaf(c.viewmat[9], y, fmaf(c.viewmat[8], x, c.viewmat[11])));
-}
-__device__ __forceinline__ float cam_x(const gs_camera& c, float x, float y, float z) {
-  return fmaf(c.viewmat[2], z, fmaf(c.viewmat[1], y, fmaf(c.viewmat[0], x, c.viewmat[3])));
-}
-__device__ __forceinline__ float cam_y(const gs_camera& c, float x, float y, float z) {
-  return fmaf(c.viewmat[6], z, fmaf(c.viewmat[5], y, fmaf(c.viewmat[4], x, c.viewmat[7])));
+// Row a of the camera transform t = W mu + t0, in FP64 from the FP64 frame
+// mean. The depth row decides the near-plane cull and, rounded once to
+// float32, the depth order; the other rows give the 2D mean, which is rounded
+// to float32 once.
+__device__ __forceinline__ double cam_row(const gs_camera& c, int a, const double* mu) {
+  const float* W = c.viewmat + 4 * a;
+  return fma((double)W[2], mu[2], fma((double)W[1], mu[1], fma((double)W[0], mu[0], (double)W[3])));
 }
 
 // Per-pixel Gaussian weight. Forward and backward call this one function on
@@ -210,6 +207,11 @@ __global__ __launch_bounds__(256) void k_compose_bwd(RenderDims d, const float* 
       a[c] = res[((size_t)f * Rc + 3 + c) * n + i];
       b[c] = f == 0 ? P[(size_t)(6 + c) * n + i] : comp[((size_t)(f - 1) * Rc + 3 + c) * n + i];
     }
+    if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f && g[3] == 0.f) {
+      // nothing flows back (a culled Gaussian): keep a non-finite delta from turning 0 into NaN
+      for (int c = 0; c < 4; ++c) carry[c] = 0.f;
+      continue;
+    }
     // p = a (x) b; gradients of <g, p> with respect to a and b
     const float ga0 = b[0] * g[0] + b[1] * g[1] + b[2] * g[2] + b[3] * g[3];
     const float ga1 = -b[1] * g[0] + b[0] * g[1] - b[3] * g[2] + b[2] * g[3];
@@ -260,24 +262,42 @@ __device__ __forceinline__ void load_frame(const RenderDims& d, const float* __r
   for (int c = 0; c < 3 * K; ++c) g.sh[c] = d.Rc > 11 ? cf[(11 + c) * n + i] : P[(11 + c) * n + i];
 }
 
+// The frame mean in FP64 (keyframe mean plus the translation deltas of
+// frames 0..f): the depth order and the 2D mean are taken from it.
+__device__ __forceinline__ void frame_mean64_init(const RenderDims& d, const float* __restrict__ P, int i,
+                                                  double* mu) {
+  for (int c = 0; c < 3; ++c) mu[c] = (double)P[(size_t)c * d.n + i];
+}
+__device__ __forceinline__ void frame_mean64_step(const RenderDims& d, const float* __restrict__ res, int f, int i,
+                                                  double* mu) {
+  if (d.Rc == 0) return;
+  for (int c = 0; c < 3; ++c) mu[c] += (double)res[((size_t)f * d.Rc + c) * d.n + i];
+}
+
 struct FrameGeom {
-  float R[9], s2[3], Sig[6];  // Sigma: xx, xy, xz, yy, yz, zz
+  float R[9], s[3], s2[3], Sig[6];  // Sigma: xx, xy, xz, yy, yz, zz
   float o, rf;                // opacity, sqrt(2 ln(o / alpha_min))
   float qinv;                 // 1 / |q|
   float qn[4];
   bool valid;
 };
 
+// A Gaussian with a zero quaternion or any non-finite parameter is culled.
 template <int DEG>
 __device__ __forceinline__ FrameGeom frame_geom(const GaussFrame<DEG>& g) {
   FrameGeom fg;
   const float qq = g.q[0] * g.q[0] + g.q[1] * g.q[1] + g.q[2] * g.q[2] + g.q[3] * g.q[3];
-  fg.valid = qq > 0.f;
+  bool fin = isfinite(g.logit);
+  for (int c = 0; c < 3; ++c) fin = fin && isfinite(g.mu[c]) && isfinite(g.ls[c]);
+#pragma unroll
+  for (int c = 0; c < 3 * (DEG + 1) * (DEG + 1); ++c) fin = fin && isfinite(g.sh[c]);
+  fg.valid = fin && qq > 0.f && isfinite(qq);
   fg.qinv = fg.valid ? 1.0f / sqrtf(qq) : 0.f;
   for (int c = 0; c < 4; ++c) fg.qn[c] = g.q[c] * fg.qinv;
   quat_rot(fg.qn[0], fg.qn[1], fg.qn[2], fg.qn[3], fg.R);
   for (int c = 0; c < 3; ++c) {
     const float s = expf(g.ls[c]);
+    fg.s[c] = s;
     fg.s2[c] = s * s;
   }
   const float* R = fg.R;
@@ -308,13 +328,24 @@ struct ViewProj {
   bool valid;
 };
 
-__device__ __forceinline__ ViewProj view_proj(const RenderDims& d, const gs_camera& cam, const float* mu,
+// a b - c d with one rounding error of the result (the fma recovers the
+// rounding error of c d exactly).
+__device__ __forceinline__ float diff_of_products(float a, float b, float c, float d) {
+  const float cd = c * d;
+  const float err = fmaf(-c, d, cd);
+  return fmaf(a, b, -cd) + err;
+}
+
+__device__ __forceinline__ ViewProj view_proj(const RenderDims& d, const gs_camera& cam, const double* mu,
                                               const FrameGeom& fg) {
   ViewProj v;
-  v.tz = cam_z(cam, mu[0], mu[1], mu[2]);
-  v.valid = fg.valid && (v.tz > d.near_plane);
-  v.tx = cam_x(cam, mu[0], mu[1], mu[2]);
-  v.ty = cam_y(cam, mu[0], mu[1], mu[2]);
+  const double tz = cam_row(cam, 2, mu);
+  const double tx = cam_row(cam, 0, mu);
+  const double ty = cam_row(cam, 1, mu);
+  v.valid = fg.valid && (tz > (double)d.near_plane);
+  v.tz = (float)tz;
+  v.tx = (float)tx;
+  v.ty = (float)ty;
   const float itz = 1.0f / v.tz;
   const float limx = 1.3f * (0.5f * (float)d.W / cam.fx);
   const float limy = 1.3f * (0.5f * (float)d.H / cam.fy);
@@ -330,25 +361,33 @@ __device__ __forceinline__ ViewProj view_proj(const RenderDims& d, const gs_came
     v.m0[k] = J00 * Wm[k] + J02 * Wm[8 + k];
     v.m1[k] = J11 * Wm[4 + k] + J12 * Wm[8 + k];
   }
-  const float* S = fg.Sig;
-  float s0[3], s1[3];  // Sigma m0, Sigma m1
-  s0[0] = S[0] * v.m0[0] + S[1] * v.m0[1] + S[2] * v.m0[2];
-  s0[1] = S[1] * v.m0[0] + S[3] * v.m0[1] + S[4] * v.m0[2];
-  s0[2] = S[2] * v.m0[0] + S[4] * v.m0[1] + S[5] * v.m0[2];
-  s1[0] = S[0] * v.m1[0] + S[1] * v.m1[1] + S[2] * v.m1[2];
-  s1[1] = S[1] * v.m1[0] + S[3] * v.m1[1] + S[4] * v.m1[2];
-  s1[2] = S[2] * v.m1[0] + S[4] * v.m1[1] + S[5] * v.m1[2];
-  v.a = v.m0[0] * s0[0] + v.m0[1] * s0[1] + v.m0[2] * s0[2] + d.dilation;
-  v.b = v.m0[0] * s1[0] + v.m0[1] * s1[1] + v.m0[2] * s1[2];
-  v.c = v.m1[0] * s1[0] + v.m1[1] * s1[1] + v.m1[2] * s1[2] + d.dilation;
-  const float det = v.a * v.c - v.b * v.b;
+  // Sigma2D = V V^T + dilation I with V = (J W) R diag(s) (2 x 3): the
+  // diagonal entries are sums of squares, and the determinant is the sum of
+  // the squared 2 x 2 minors of V plus positive dilation terms (the
+  // Cauchy-Binet form), so neither suffers cancellation.
+  const float* R = fg.R;
+  float V0[3], V1[3];
+  for (int j = 0; j < 3; ++j) {
+    V0[j] = (v.m0[0] * R[j] + v.m0[1] * R[3 + j] + v.m0[2] * R[6 + j]) * fg.s[j];
+    V1[j] = (v.m1[0] * R[j] + v.m1[1] * R[3 + j] + v.m1[2] * R[6 + j]) * fg.s[j];
+  }
+  const float a0 = V0[0] * V0[0] + V0[1] * V0[1] + V0[2] * V0[2];
+  const float c0 = V1[0] * V1[0] + V1[1] * V1[1] + V1[2] * V1[2];
+  v.a = a0 + d.dilation;
+  v.b = V0[0] * V1[0] + V0[1] * V1[1] + V0[2] * V1[2];
+  v.c = c0 + d.dilation;
+  const float n01 = diff_of_products(V0[0], V1[1], V0[1], V1[0]);
+  const float n02 = diff_of_products(V0[0], V1[2], V0[2], V1[0]);
+  const float n12 = diff_of_products(V0[1], V1[2], V0[2], V1[1]);
+  const float det = (n01 * n01 + n02 * n02 + n12 * n12) + d.dilation * (a0 + c0 + d.dilation);
   v.valid = v.valid && (det > 0.f);
   const float idet = 1.0f / det;
   v.A = v.c * idet;
   v.B = -v.b * idet;
   v.C = v.a * idet;
-  v.mx = cam.fx * v.tx * itz + cam.cx;
-  v.my = cam.fy * v.ty * itz + cam.cy;
+  const double iz = 1.0 / tz;
+  v.mx = (float)fma((double)cam.fx, tx * iz, (double)cam.cx);
+  v.my = (float)fma((double)cam.fy, ty * iz, (double)cam.cy);
   v.valid = v.valid && isfinite(v.mx) && isfinite(v.my) && isfinite(v.A) && isfinite(v.B) && isfinite(v.C);
   return v;
 }
@@ -380,7 +419,7 @@ __device__ __forceinline__ void view_color(const gs_camera& cam, const GaussFram
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_fwd(RenderDims d, const float* __restrict__ P,
-                                                     const float* __restrict__ comp,
+                                                     const float* __restrict__ res, const float* __restrict__ comp,
                                                      const gs_camera* __restrict__ cams, float4* __restrict__ rec,
                                                      uint2* __restrict__ rects, uint32_t* __restrict__ keys,
                                                      uint32_t* __restrict__ vals) {
@@ -388,8 +427,11 @@ __global__ __launch_bounds__(256) void k_project_fwd(RenderDims d, const float* 
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   GaussFrame<DEG> g;
+  double mu64[3];
+  frame_mean64_init(d, P, i, mu64);
   for (int f = 0; f < d.F; ++f) {
     load_frame<DEG>(d, P, comp, d.Rc ? f : -1, i, g);
+    frame_mean64_step(d, res, f, i, mu64);
     FrameGeom fg = frame_geom<DEG>(g);
     frame_footprint(fg, d.alpha_min);
     for (int v = 0; v < d.V; ++v) {
@@ -397,7 +439,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(RenderDims d, const float* 
       const gs_camera cam = cams[b];
       const size_t bi = (size_t)b * d.n + i;
       uint32_t key = 0xFFFFFFFFu;
-      const ViewProj vp = view_proj(d, cam, g.mu, fg);
+      const ViewProj vp = view_proj(d, cam, mu64, fg);
       if (vp.valid) {
         const float mid = 0.5f * (vp.a + vp.c);
         const float hd = 0.5f * (vp.a - vp.c);
@@ -426,7 +468,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(RenderDims d, const float* 
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(RenderDims d, const float* __restrict__ P,
-                                                     const float* __restrict__ comp,
+                                                     const float* __restrict__ res, const float* __restrict__ comp,
                                                      const gs_camera* __restrict__ cams,
                                                      const float* __restrict__ g2d, float* __restrict__ dP,
                                                      float* __restrict__ dcomp) {
@@ -439,8 +481,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(RenderDims d, const float* 
   float t_sh[3 * K];
 #pragma unroll
   for (int c = 0; c < 3 * K; ++c) t_sh[c] = 0.f;
+  double mu64[3];
+  frame_mean64_init(d, P, i, mu64);
   for (int f = 0; f < d.F; ++f) {
     load_frame<DEG>(d, P, comp, d.Rc ? f : -1, i, g);
+    frame_mean64_step(d, res, f, i, mu64);
     FrameGeom fg = frame_geom<DEG>(g);
     frame_footprint(fg, d.alpha_min);
     if (!fg.valid) continue;
@@ -463,7 +508,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(RenderDims d, const float* 
       for (int c = 0; c < 9; ++c) any = any || (gr[c] != 0.f);
       if (!any) continue;
       const gs_camera cam = cams[b];
-      const ViewProj vp = view_proj(d, cam, g.mu, fg);
+      const ViewProj vp = view_proj(d, cam, mu64, fg);
       if (!vp.valid) continue;
       // conic (A, B, C) -> covariance (a, b, c)
       const float A = vp.A, B = vp.B, C = vp.C;
@@ -1680,7 +1725,7 @@ hipError_t launch_compose_bwd(const RenderDims& d, const float* params, const fl
   return hipGetLastError();
 }
 
-hipError_t launch_project_fwd(const RenderDims& d, const float* params, const float* composed,
+hipError_t launch_project_fwd(const RenderDims& d, const float* params, const float* res, const float* composed,
                               const gs_camera* cams, char* ws, const Layout& lo, hipStream_t st) {
   dim3 grid((d.n + 255) / 256), block(256);
   float4* rec = (float4*)(ws + lo.records);
@@ -1689,25 +1734,25 @@ hipError_t launch_project_fwd(const RenderDims& d, const float* params, const fl
   uint32_t* vals = (uint32_t*)(ws + lo.vals0);
   ProfScope ps_(K_PROJECT_FWD, st);
   switch (d.deg) {
-    case 0: hipLaunchKernelGGL(k_project_fwd<0>, grid, block, 0, st, d, params, composed, cams, rec, rects, keys, vals); break;
-    case 1: hipLaunchKernelGGL(k_project_fwd<1>, grid, block, 0, st, d, params, composed, cams, rec, rects, keys, vals); break;
-    case 2: hipLaunchKernelGGL(k_project_fwd<2>, grid, block, 0, st, d, params, composed, cams, rec, rects, keys, vals); break;
-    default: hipLaunchKernelGGL(k_project_fwd<3>, grid, block, 0, st, d, params, composed, cams, rec, rects, keys, vals); break;
+    case 0: hipLaunchKernelGGL(k_project_fwd<0>, grid, block, 0, st, d, params, res, composed, cams, rec, rects, keys, vals); break;
+    case 1: hipLaunchKernelGGL(k_project_fwd<1>, grid, block, 0, st, d, params, res, composed, cams, rec, rects, keys, vals); break;
+    case 2: hipLaunchKernelGGL(k_project_fwd<2>, grid, block, 0, st, d, params, res, composed, cams, rec, rects, keys, vals); break;
+    default: hipLaunchKernelGGL(k_project_fwd<3>, grid, block, 0, st, d, params, res, composed, cams, rec, rects, keys, vals); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const RenderDims& d, const float* params, const float* composed,
+hipError_t launch_project_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,
                               const gs_camera* cams, char* ws, const Layout& lo, float* d_params, hipStream_t st) {
   dim3 grid((d.n + 255) / 256), block(256);
   const float* g2d = (const float*)(ws + lo.grad2d);
   float* dcomp = (float*)(ws + lo.d_composed);
   ProfScope ps_(K_PROJECT_BWD, st);
   switch (d.deg) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, st, d, params, composed, cams, g2d, d_params, dcomp); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, st, d, params, composed, cams, g2d, d_params, dcomp); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, st, d, params, composed, cams, g2d, d_params, dcomp); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, st, d, params, composed, cams, g2d, d_params, dcomp); break;
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, st, d, params, res, composed, cams, g2d, d_params, dcomp); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, st, d, params, res, composed, cams, g2d, d_params, dcomp); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, st, d, params, res, composed, cams, g2d, d_params, dcomp); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, st, d, params, res, composed, cams, g2d, d_params, dcomp); break;
   }
   return hipGetLastError();
 }

@@ -38,6 +38,26 @@ def gpu_settings(w, **kw):
                           res_channels=0 if w.residuals is None else w.residuals.shape[1], **kw)
 
 
+def ambiguity_report(gpu_img, ref, tol=IMG_TOL):
+    """Counts of the oracle's ambiguous pixel-levels (some decision inside its float32 accuracy
+    band): all of them, the material ones (an accepted alternative farther than tol from the FP64
+    colour), and the ones where the GPU took another outcome than the FP64 one (it is within tol of
+    an alternative but not of the FP64 colour)."""
+    nvar, var, main = ref["nvar"], ref["var"], ref["image"]
+    amb = nvar > 0
+    if not amb.any():
+        return {"ambiguous": 0, "material": 0, "flipped": 0, "total": int(nvar.size)}
+    g = np.moveaxis(gpu_img, 2, -1)[amb]
+    m = np.moveaxis(main, 2, -1)[amb]
+    v = var[amb]
+    k = nvar[amb]
+    valid = np.arange(v.shape[1])[None, :] < k[:, None]
+    spread = np.where(valid, np.abs(v - m[:, None, :]).max(axis=2), 0.0).max(axis=1)
+    off_main = np.abs(g - m).max(axis=1) > tol
+    return {"ambiguous": int(amb.sum()), "material": int((spread > tol).sum()), "flipped": int(off_main.sum()),
+            "total": int(nvar.size)}
+
+
 def image_mismatch(gpu_img, ref, tol=IMG_TOL):
     """gpu_img [B][L][3][H][W] (or [B][L][3][S]) vs oracle render with variants.
     Returns (n_bad, n_ambiguous, n_excluded, max_err over accepted pixels)."""

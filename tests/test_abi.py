@@ -67,6 +67,14 @@ def test_workspace_size_and_validation(L):
     st = _settings(1000)
     st.tile_w = st.tile_h = 8
     assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 1, 10, ctypes.byref(sz)) == -6
+    # alpha_max = 1 is rejected whatever t_stop is: the backward divides by 1 - alpha
+    for t_stop in (0.0, 1e-4):
+        st = _settings(1000)
+        st.alpha_max, st.t_stop = 1.0, t_stop
+        assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 1, 10, ctypes.byref(sz)) == -1
+    st = _settings(1000)
+    st.alpha_max = 0.999
+    assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 1, 10, ctypes.byref(sz)) == 0
     assert L.gs_error_string(-3) == b"pair list capacity exceeded"
     # launch shapes: only the listed values, and the workspace does not depend on them
     for field, value in (("bin_chunk", 300), ("bin_chunk", 4096), ("row_seg", 512), ("wave_layout", 3)):

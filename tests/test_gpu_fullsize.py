@@ -10,7 +10,8 @@ import torch
 import oracle
 import synth
 from oracle import rate
-from parity import gpu_settings, grad_mismatch, image_mismatch, oracle_settings, param_groups
+from parity import (ambiguity_report, gpu_settings, grad_mismatch, image_mismatch, l1_dimage, oracle_settings,
+                    param_groups)
 
 pytestmark = pytest.mark.gpu
 
@@ -47,10 +48,15 @@ def test_batched_300k_24views_sampled_pixels():
     img, _, _ = _forward(w)
     pix = _sample_pixels(w, 400, 101)
     ref = oracle.render(oracle_settings(w), w.params, w.cams, sample=pix, variants=True)
-    bad, amb, excl, err = image_mismatch(_gather(img, pix, w), ref)
-    print(f"bad={bad} ambiguous={amb} excluded={excl} of {ref['nvar'].size}; max_err={err:.3g}")
+    gi = _gather(img, pix, w)
+    bad, amb, excl, err = image_mismatch(gi, ref)
+    rep = ambiguity_report(gi, ref)
+    print(f"bad={bad} ambiguous={amb} excluded={excl} of {ref['nvar'].size}; max_err={err:.3g}; {rep}")
     assert bad == 0
-    assert excl <= 1e-3 * ref["nvar"].size
+    assert excl <= 1e-4 * ref["nvar"].size
+    # the oracle's float32 accuracy bands flag about 0.9% of these pixel-levels (half of them with
+    # alternatives farther apart than the tolerance); these bounds catch a band that widens
+    assert rep["ambiguous"] <= 0.015 * rep["total"] and rep["material"] <= 0.006 * rep["total"]
 
 
 def _window_dimage(w, img, views, x0, y0, size, seed):
@@ -90,69 +96,95 @@ def test_batched_300k_windowed_gradients_match_oracle():
     bad, worst = grad_mismatch(dp.cpu().numpy()[:, touched].astype(np.float64), dp_ref[:, touched],
                                param_groups(w.sh_degree))
     print(f"grad bad={bad} of {touched.sum() * 59} worst_ratio={worst:.3g}")
-    assert bad <= 1e-3 * touched.sum() * 59
+    assert bad == 0
     assert np.all(dp.cpu().numpy()[:, ~touched] == 0)
 
 
+def _fd_strata(pr, touched, w, rng, per=64):
+    """256 Gaussians in four strata of 64: front (smallest depth), deep (largest depth that still
+    gets a gradient), edge (footprint crossing the image border) and near-cutoff (lowest opacity,
+    so that most of the footprint lies near the 1/255 cut)."""
+    idx = np.nonzero(touched)[0]
+    tz, mx, my, rad, o = pr[idx, 1], pr[idx, 2], pr[idx, 3], pr[idx, 14], pr[idx, 10]
+    taken = np.zeros(len(idx), bool)
+    out = {}
+
+    def pick(name, order):
+        sel = [k for k in order if not taken[k]][:per]
+        taken[sel] = True
+        out[name] = idx[sel]
+
+    pick("front", np.argsort(tz, kind="stable"))
+    pick("deep", np.argsort(-tz, kind="stable"))
+    edge = np.nonzero((mx - rad < 0) | (mx + rad > w.width) | (my - rad < 0) | (my + rad > w.height))[0]
+    pick("edge", rng.permutation(edge))
+    pick("near_cutoff", np.argsort(o, kind="stable"))
+    return out
+
+
 def test_fwd_bwd_200k_1280x720_against_finite_differences():
-    _case("200k Gaussians SH3 1280x720: GPU gradients vs FP64 central differences (windowed loss)")
+    _case("200k Gaussians SH3 1280x720, L1 loss: GPU gradients vs the oracle's analytic backward (all "
+          "11.8M) and vs FP64 central differences (256 stratified Gaussians x 59 + 1000 random)")
     from paper_2509_17513_amd import render_backward
     w = synth.config_forward_backward()
     img, ws, (p, c, r, st) = _forward(w)
     ost = oracle_settings(w)
-    x0, y0, S = 620, 340, 40
-    d = _window_dimage(w, img, (0,), x0, y0, S, 103)
-    dimg = torch.from_numpy(d.astype(np.float32).reshape(img.shape)).to(p.device)
+    ref = oracle.render(ost, w.params, w.cams, variants=True)
+    gi_img = img.cpu().numpy().reshape(ref["image"].shape)
+    bad, amb, excl, err = image_mismatch(gi_img, ref)
+    print(f"image bad={bad} ambiguous={amb} excluded={excl} max_err={err:.3g}; {ambiguity_report(gi_img, ref)}",
+          flush=True)
+    assert bad == 0
+    d = l1_dimage(ref, w.target, w.level_weights).astype(np.float32)
+    dimg = torch.from_numpy(d.reshape(img.shape)).to(p.device)
     dp, _ = render_backward(st, p, c, ws, image=img, d_image=dimg)
     torch.cuda.synchronize()
     g = dp.cpu().numpy().astype(np.float64)
-    # the Gaussians whose conservative footprint reaches the window are the only ones that matter
+    d = d.astype(np.float64)
+    dp_ref, _, _ = oracle.backward(ost, w.params, w.cams, d)
+    groups = param_groups(w.sh_degree)
+    bad, worst = grad_mismatch(g, dp_ref, groups)
+    touched = np.abs(dp_ref).sum(axis=0) > 0
+    print(f"analytic: bad={bad} of {g.size} worst_ratio={worst:.3g}; Gaussians with gradient {touched.sum()}",
+          flush=True)
+    assert bad == 0
+    assert np.all(g[:, ~touched] == 0)
+    # finite differences of the same linear functional sum(d * image)
     pr = oracle.project(ost, w.params, w.cams)[0]
-    near = (pr[:, 0] == 1) & (pr[:, 2] + pr[:, 14] + 2 >= x0) & (pr[:, 2] - pr[:, 14] - 2 <= x0 + S) & \
-           (pr[:, 3] + pr[:, 14] + 2 >= y0) & (pr[:, 3] - pr[:, 14] - 2 <= y0 + S)
-    sub = np.nonzero(near)[0]
-    ps = np.ascontiguousarray(w.params[:, sub])
-    pix = np.array([(y * w.width + x) for y in range(y0, y0 + S) for x in range(x0, x0 + S)], np.int64)
-    dw = d.reshape(1, 1, 3, -1)[..., pix]
-    st_sub = oracle.Settings(w.width, w.height, 3, (len(sub),))
-
-    def loss(pp):
-        rr = oracle.render(st_sub, pp, w.cams, sample=pix, signature=True)
-        fl = oracle.project(st_sub, pp, w.cams)[0][:, [0, 15]]
-        return float((rr["image"] * dw).sum()), rr["sig"], fl
-
     rng = np.random.default_rng(104)
-    gsub = g[:, sub]
-    active = np.nonzero(np.abs(gsub).sum(axis=0) > 0)[0]
-    pick = rng.choice(active, min(10, len(active)), replace=False)
-    checked = skipped = bad = 0
-    worst = 0.0
-    rms = {gname: np.sqrt(np.mean(gsub[lo:hi, active] ** 2)) for gname, (lo, hi) in
-           zip("mslqda", param_groups(3))}
-    for j in pick:
-        for ch in range(ps.shape[0]):
-            grp = [k for k, (lo, hi) in zip("mslqda", param_groups(3)) if lo <= ch < hi][0]
-            ok = False
-            for h in (1e-3, 1e-4):
-                a, b = ps.copy(), ps.copy()
-                a[ch, j] = np.float32(ps[ch, j] + h)
-                b[ch, j] = np.float32(ps[ch, j] - h)
-                la, sa, fa = loss(a)
-                lb, sb, fb = loss(b)
-                if np.array_equal(sa, sb) and np.array_equal(fa, fb):
-                    ok = True
-                    break
-            if not ok:
-                skipped += 1
-                continue
-            fd = (la - lb) / (float(a[ch, j]) - float(b[ch, j]))
-            err = abs(gsub[ch, j] - fd) / (1e-3 * abs(fd) + 1e-3 * rms[grp] + 1e-12)
-            worst = max(worst, err)
-            bad += err > 1
-            checked += 1
-    print(f"FD checked={checked} skipped={skipped} bad={bad} worst_ratio={worst:.3g}")
-    assert checked >= 0.8 * len(pick) * ps.shape[0]
-    assert bad <= max(1, 0.01 * checked)
+    strata = _fd_strata(pr, touched, w, rng)
+    C = w.params.shape[0]
+    gi = np.concatenate([np.repeat(v, C) for v in strata.values()])
+    ci = np.concatenate([np.tile(np.arange(C), len(v)) for v in strata.values()])
+    rest = np.setdiff1d(np.nonzero(touched)[0], gi)
+    gi = np.concatenate([gi, rng.choice(rest, 1000)]).astype(np.int32)
+    ci = np.concatenate([ci, rng.integers(0, C, 1000)]).astype(np.int32)
+    labels = np.concatenate([np.repeat(k, len(v) * C) for k, v in strata.items()] + [np.repeat("random", 1000)])
+    fd, status, skipped = oracle.finite_differences(ost, w.params, w.cams, d, gi, ci, h=1e-5)
+    assert np.all(status & 8 == 0)
+    ok = (status & 4) == 0
+    grp = np.zeros(C, int)
+    for k, (lo, hi) in enumerate(groups):
+        grp[lo:hi] = k
+    # RMS of the oracle's gradient over the attribute group, over every Gaussian with a gradient
+    rms = np.array([np.sqrt(np.mean(dp_ref[lo:hi][:, touched] ** 2)) for lo, hi in groups])[grp[ci]]
+    got, ana = g[ci, gi], dp_ref[ci, gi]
+    ratio = np.abs(got - fd) / (1e-3 * np.abs(fd) + 1e-3 * rms)
+    rel = np.abs(got - fd) / np.maximum(np.abs(fd), 1e-300)
+    big = ok & (np.abs(fd) >= rms)  # far above the float32 noise of a sum of per-pixel terms
+    for k in list(strata) + ["random"]:
+        m = labels == k
+        print(f"  {k:12s} params={m.sum():5d} skipped={np.sum(m & ~ok):3d} one-sided={np.sum(m & (status & 1 > 0)):4d} "
+              f"h/10={np.sum(m & (status & 2 > 0)):3d} worst_ratio={ratio[m & ok].max():.3g} "
+              f"max_rel(|fd|>=rms)={rel[m & big].max() if np.any(m & big) else 0:.3g}")
+    for k, (lo, hi) in enumerate(groups):
+        m = (ci >= lo) & (ci < hi)
+        print(f"  group {lo}-{hi}: params={m.sum()} skipped={np.sum(m & ~ok)}")
+    print(f"FD checked={ok.sum()} of {len(ok)} worst_ratio={ratio[ok].max():.3g} "
+          f"oracle analytic vs FD worst={np.max(np.abs(ana - fd)[ok] / (1e-3 * np.abs(fd) + 1e-3 * rms)[ok]):.3g}")
+    assert np.all(ratio[ok] <= 1.0)
+    assert np.all(rel[big] <= 1e-3)
+    assert ok.mean() >= 0.98
 
 
 def test_group_150k_10frames_8views_sampled():
@@ -189,7 +221,7 @@ def test_group_150k_10frames_8views_sampled():
     b2, w2 = grad_mismatch(drn[:, :, touched].transpose(1, 0, 2).reshape(8, -1),
                            dr_ref[:, :, touched].transpose(1, 0, 2).reshape(8, -1), [(0, 3), (3, 7), (7, 8)])
     print(f"touched={touched.sum()} params bad={b1} worst={w1:.3g}; residuals bad={b2} worst={w2:.3g}")
-    assert b1 <= 1e-3 * touched.sum() * 59 and b2 <= 1e-3 * touched.sum() * 80
+    assert b1 == 0 and b2 == 0
 
 
 def test_rate_1M_x_56_histogram_and_sampled_symbols():

@@ -236,7 +236,7 @@ def test_render_with_dssim_gradients_match_oracle():
     dp_ref, _, _ = oracle.backward(ost, w.params, w.cams, dimg)
     bad, worst = grad_mismatch(dp.cpu().numpy().astype(np.float64), dp_ref, param_groups(w.sh_degree))
     print(f"grad bad={bad} of {dp.numel()} worst_ratio={worst:.3g}")
-    assert bad <= 1e-3 * dp.numel()
+    assert bad == 0
 
 
 def test_fullsize_24views_6layers_960x540_sampled():

@@ -149,19 +149,23 @@ def test_mlp_train_gradients_match_oracle():
     lam = 3.0
     g = _gpu_mlp(attrs, ctx, wbits, bf, lv, lw, 1, lam, seed=99, offset=12345)
     ref = rate.rate_model(attrs, ctx, wbits, bf, Q, mode=1, seed=99, offset=12345,
-                          sym_w=rate.symbol_weights(n, lv, lw, lam), fit_scale=1.0 / n)
+                          sym_w=rate.symbol_weights(n, lv, lw, lam), fit_scale=1.0 / n, want_abs=True)
     np.testing.assert_allclose(g["bits"], ref["bits"], rtol=1e-3)
     assert abs(g["loss"] - ref["loss"]) <= 1e-3 * abs(ref["loss"])
     da, rda = g["d_attrs"], ref["d_attrs"]
     rms = np.sqrt(np.mean(rda ** 2))
     bad = np.abs(da - rda) > 2e-2 * np.abs(rda) + 1e-2 * rms
-    assert bad.mean() < 2e-3, bad.mean()
+    assert bad.sum() == 0, bad.sum()
     for k in ("d_w", "d_b"):
-        x, r = g[k], ref[k]
+        x, r, ra = g[k], ref[k], ref[k + "_abs"]
         for a in range(A):
             rms = np.sqrt(np.mean(r[a] ** 2)) + 1e-30
-            err = np.abs(x[a] - r[a]) / (2e-2 * np.abs(r[a]) + 2e-2 * rms)
-            assert np.mean(err > 1) < 1e-2, (k, a, np.mean(err > 1), err.max())
+            # each term of these sums over symbols is a product of two BF16-rounded factors; where the
+            # float32 and FP64 values straddle a BF16 rounding boundary the two sides round a factor to
+            # neighbouring BF16 values, so a term may differ by up to 2^-7 of itself: the bar adds 2^-7
+            # of the sum of the absolute terms to the relative bar
+            err = np.abs(x[a] - r[a]) / (2e-2 * np.abs(r[a]) + 2e-2 * rms + 2.0 ** -7 * ra[a])
+            assert np.all(err <= 1), (k, a, np.mean(err > 1), err.max())
             np.testing.assert_allclose(np.linalg.norm(x[a]), np.linalg.norm(r[a]), rtol=2e-2)
 
 

@@ -187,7 +187,7 @@ def test_backward_l1_matches_oracle_ring():
     torch.cuda.synchronize()
     bad, worst = grad_mismatch(dp.cpu().numpy().astype(np.float64), dp_ref, param_groups(w.sh_degree))
     print(f"grad bad={bad} of {dp.numel()} worst_ratio={worst:.3g}")
-    assert bad <= 1e-3 * dp.numel()
+    assert bad == 0
 
 
 def _extreme_scene(seed=77, w=100, h=150):
@@ -337,7 +337,7 @@ def test_frames_forward_backward_match_oracle():
     b2, w2 = grad_mismatch(dr.cpu().numpy().astype(np.float64).transpose(1, 0, 2),
                            dr_ref.transpose(1, 0, 2), residual_groups(8))
     print(f"params bad={b1} worst={w1:.3g}; residuals bad={b2} worst={w2:.3g}")
-    assert b1 <= 1e-3 * dp.numel() and b2 <= 1e-3 * dr.numel()
+    assert b1 == 0 and b2 == 0
 
 
 def test_autograd_function_matches_direct_backward():
@@ -378,3 +378,110 @@ def test_work_counters_count_only_when_enabled():
     L = len(w.level_counts)
     assert 0 < s1["fwd_contribs"] <= L * s1["fwd_evals"]
     assert 0 < s1["bwd_contribs"] <= L * s1["bwd_evals"]
+
+
+# ------------------------------------------------------ closed forms on the GPU
+_Y00 = 0.28209479177387814
+
+
+def _explicit(items, deg=0):
+    """Explicit Gaussians (mean, log-scales, quaternion, logit, rgb) -> params [C][N] float32."""
+    import math
+    n = len(items)
+    p = np.zeros((11 + 3 * (deg + 1) ** 2, n), np.float32)
+    for i, (m, ls, q, lg, rgb) in enumerate(items):
+        p[0:3, i], p[3:6, i], p[6:10, i], p[10, i] = m, ls, q, lg
+        p[11:14, i] = (np.asarray(rgb, np.float64) - 0.5) / _Y00
+    del math
+    return p
+
+
+def _big(z, o, rgb):
+    import math
+    return [0, 0, z], [math.log(1e4)] * 3, [1, 0, 0, 0], math.log(o / (1 - o)), rgb
+
+
+def _explicit_workload(p, w=64, h=48, levels=None):
+    cams = synth.identity_camera(w, h, float(w))[None]
+    n = p.shape[1]
+    lv = levels or [n]
+    return synth.Workload("explicit", p, cams, w, h, 0, lv, [1.0] * len(lv))
+
+
+def test_full_occlusion_closed_form():
+    _case("full occlusion: alpha 0.99 (clamped) then 0.98 -> T = 2e-4; everything behind contributes 0")
+    from paper_2509_17513_amd import render_backward
+    p = _explicit([_big(2.0, 0.999, [0.8, 0.1, 0.3]), _big(3.0, 0.98, [0.2, 0.9, 0.5]),
+                   _big(4.0, 0.9, [0.4, 0.4, 0.9]), _big(5.0, 0.7, [1.0, 1.0, 1.0])])
+    w = _explicit_workload(p)
+    img, ws, (pt, ct, _, st) = _gpu_forward(w)
+    pr = oracle.project(oracle_settings(w), p, w.cams)[0]
+    a = img.cpu().numpy()[0, 0, 0]
+    for ch in range(3):
+        a1 = float(np.float32(0.99))  # clamped
+        exp = a1 * pr[0, 11 + ch] + (1 - a1) * min(a1, pr[1, 10]) * pr[1, 11 + ch]
+        assert np.abs(a[ch] - exp).max() <= 1e-6, (ch, np.abs(a[ch] - exp).max())
+    d_image = torch.randn_like(img)
+    dp, _ = render_backward(st, pt, ct, ws, image=img, d_image=d_image)
+    torch.cuda.synchronize()
+    g = dp.cpu().numpy()
+    assert np.all(g[:, 2:] == 0.0)
+    assert np.abs(g[:, :2]).max() > 0
+
+
+def test_transmittance_stop_thirteen_layers_closed_form():
+    _case("20 nested full-screen layers with alpha 0.5: exactly 13 included, C = c (1 - 2^-13)")
+    c = [0.3, 0.6, 0.9]
+    p = _explicit([_big(2.0 + 0.1 * k, 0.5, c) for k in range(20)])
+    w = _explicit_workload(p)
+    img, _, _ = _gpu_forward(w)
+    pr = oracle.project(oracle_settings(w), p, w.cams)[0]
+    a = img.cpu().numpy()[0, 0, 0]
+    for ch in range(3):
+        # 13 and 14 layers differ by c 2^-14 >= 1.8e-5 here; float32 keeps the sum within 1e-6
+        assert np.abs(a[ch] - pr[0, 11 + ch] * (1 - 2.0 ** -13)).max() <= 1e-6
+
+
+def test_sub_cutoff_opacity_leaves_image_bit_identical_with_zero_gradient():
+    _case("a Gaussian with o < 1/255: image bit-identical without it, zero gradient")
+    from paper_2509_17513_amd import render_backward
+    w0 = synth.config_plain_forward(seed=5, n=64, width=32, height=32)
+    p = w0.params.copy()
+    p[10, 63] = np.log((0.9 / 255) / (1 - 0.9 / 255))  # last index: the others keep their indices
+    w = _explicit_workload(p, 32, 32)
+    img, ws, (pt, ct, _, st) = _gpu_forward(w)
+    img2, _, _ = _gpu_forward(_explicit_workload(np.ascontiguousarray(p[:, :63]), 32, 32))
+    assert np.array_equal(img.cpu().numpy(), img2.cpu().numpy())
+    dp, _ = render_backward(st, pt, ct, ws, image=img, d_image=torch.randn_like(img))
+    torch.cuda.synchronize()
+    assert np.all(dp.cpu().numpy()[:, 63] == 0.0)
+
+
+def test_nan_and_zero_quaternion_gaussians_are_culled_with_zero_gradient():
+    _case("NaN in each parameter group and zero quaternions: culled, zero gradient, image unchanged")
+    from paper_2509_17513_amd import render_backward
+    w0 = _small_ring(n=1500, seed=91, w=96, h=64, views=(0, 5), deg=3, levels=False)
+    base = w0.params
+    extra = base[:, :8].copy()
+    for k, ch in enumerate([0, 4, 7, 10, 11, 40]):   # mean, log-scale, quaternion, logit, SH DC, SH rest
+        extra[ch, k] = np.nan
+    extra[6:10, 6] = 0.0                               # zero quaternion
+    extra[2, 7] = np.inf
+    p = np.ascontiguousarray(np.concatenate([base, extra], axis=1))
+    n0 = base.shape[1]
+    bad_cols = list(range(n0, p.shape[1]))
+    mk = lambda q: synth.Workload("deg", q, w0.cams, w0.width, w0.height, 3, [q.shape[1]], [1.0])  # noqa: E731
+    img, ws, (pt, ct, _, st) = _gpu_forward(mk(p))
+    img0, ws0, (pt0, ct0, _, st0) = _gpu_forward(mk(np.ascontiguousarray(base)))
+    assert np.array_equal(img.cpu().numpy(), img0.cpu().numpy())
+    d_image = torch.randn_like(img)
+    dp, _ = render_backward(st, pt, ct, ws, image=img, d_image=d_image)
+    dp0, _ = render_backward(st0, pt0, ct0, ws0, image=img0, d_image=d_image)
+    torch.cuda.synchronize()
+    g = dp.cpu().numpy()
+    assert np.all(g[:, bad_cols] == 0.0)
+    ok, worst = atomic_order_close(g[:, :n0], dp0.cpu().numpy())
+    assert ok, worst
+    ref = oracle.render(oracle_settings(mk(p)), p, w0.cams, variants=True)
+    bad, amb, excl, err = image_mismatch(_flat(img), ref)
+    assert bad == 0

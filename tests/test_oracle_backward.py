@@ -136,3 +136,54 @@ def test_single_gaussian_closed_form_gradients():
     np.testing.assert_allclose(dp[10, 0], pr[11] * G * s * (1 - s), rtol=1e-12)
     np.testing.assert_allclose(dp[11, 0], s * G * Y00, rtol=1e-12)
     assert dp[12, 0] == 0.0 and dp[13, 0] == 0.0
+
+
+def test_footprint_local_fd_equals_analytic_and_full_render_fd():
+    """O8's footprint-local differences (only the pixels the perturbed Gaussian can reach are
+    re-composited, kinks handled per pixel-level) agree with the analytic backward on every
+    parameter of a tiny scene, and with differences of full re-renders where those are smooth."""
+    p, cams = _tiny(31, n=14, deg=3)
+    st = oracle.Settings(24, 20, 3, (5, 14), dilation=0.3)
+    w = np.random.default_rng(32).standard_normal((2, 2, 3, 20, 24))
+    dp, _, _ = oracle.backward(st, p, cams, w)
+    C, n = p.shape
+    gi, ci = np.meshgrid(np.arange(n), np.arange(C))
+    fd, status, skipped = oracle.finite_differences(st, p, cams, w, gi.ravel(), ci.ravel(), h=1e-5)
+    fd = fd.reshape(C, n)
+    assert np.all(status & 8 == 0)
+    ok = (status.reshape(C, n) & 4) == 0
+    assert ok.mean() > 0.95
+    scale = np.sqrt(np.mean(dp ** 2))
+    err = np.abs(fd - dp) / (np.abs(dp) + 1e-3 * scale)
+    assert err[ok].max() < 1e-5, err[ok].max()
+    # full-render differences of a few smooth parameters (float32 steps, so the step is the
+    # float32 difference of the perturbed values)
+    for ch, i in ((0, 3), (4, 5), (7, 8), (10, 2), (20, 9)):
+        ap, am = p.copy(), p.copy()
+        ap[ch, i] = np.float32(p[ch, i] + 1e-3)
+        am[ch, i] = np.float32(p[ch, i] - 1e-3)
+        lp = float((oracle.render(st, ap, cams)["image"] * w).sum())
+        lm = float((oracle.render(st, am, cams)["image"] * w).sum())
+        full = (lp - lm) / (float(ap[ch, i]) - float(am[ch, i]))
+        assert abs(full - fd[ch, i]) <= 1e-3 * abs(fd[ch, i]) + 1e-4 * scale, (ch, i, full, fd[ch, i])
+
+
+def test_footprint_local_fd_kinks_fall_back_to_one_sided_differences():
+    """A Gaussian whose alpha crosses alpha_min at some pixel between theta - h and theta + h:
+    that pixel-level uses the side that keeps its events, so the difference still matches the
+    analytic gradient (which differentiates the smooth part)."""
+    p, cams = _tiny(33, n=10, deg=0)
+    st = oracle.Settings(24, 20, 0, (10,), dilation=0.3)
+    w = np.random.default_rng(34).standard_normal((2, 1, 3, 20, 24))
+    dp, _, _ = oracle.backward(st, p, cams, w)
+    C, n = p.shape
+    gi, ci = np.meshgrid(np.arange(n), np.arange(C))
+    fd, status, _ = oracle.finite_differences(st, p, cams, w, gi.ravel(), ci.ravel(), h=3e-2)
+    fd, status = fd.reshape(C, n), status.reshape(C, n)
+    one_sided = (status & 1) != 0
+    assert one_sided.any()  # a large step makes kinks common
+    ok = (status & 4) == 0
+    scale = np.sqrt(np.mean(dp ** 2))
+    # one-sided differences at a large step carry an O(h) error: compare loosely
+    err = np.abs(fd - dp) / (np.abs(dp) + 1e-2 * scale)
+    assert np.median(err[ok]) < 2e-2

@@ -355,3 +355,122 @@ def test_frame_composition_equals_plain_render():
         diff = np.abs(r[f * 2:(f + 1) * 2, 0] - ref["image"][:, 0]).max(axis=1)
         assert ok.mean() > 0.95
         assert diff[ok].max() < 1e-4
+
+
+# ------------------------------------------------ order, near plane, ambiguity
+def _pair_image(p, st, cam, px, py):
+    r = oracle.render(st, p, cam, variants=True)
+    return r["image"][0, 0, :, py, px], r["nvar"][0, 0, py, px]
+
+
+def test_equal_depth_keys_composite_in_index_order():
+    """Eq. 2 composites N ordered Gaussians. Reading: the order key is the float32 rounding of the
+    exact camera depth, equal keys in index order. A camera turned by 1e-4 rad about y gives
+    depth t_z = z - 1e-4 x, so a Gaussian at x = 1e-3 sits 1e-7 nearer than one at x = 0 with
+    the same z = 3, and both depths round to the key 3.0f: the lower index is in front even
+    where it is the deeper one. The two-layer closed form fixes the colour."""
+    th = 1e-4
+    cam = synth.identity_camera(W, H, FOC)[None].copy()
+    cam[0, 0:3] = [math.cos(th), 0.0, math.sin(th)]
+    cam[0, 8:11] = [-math.sin(th), 0.0, math.cos(th)]
+    items = [([0, 0, 3.0], [math.log(0.2)] * 3, [1, 0, 0, 0], logit(0.6), [0.9, 0.1, 0.2]),
+             ([1e-3, 0, 3.0], [math.log(0.2)] * 3, [1, 0, 0, 0], logit(0.5), [0.1, 0.7, 0.9])]
+    st = oracle.Settings(W, H, 0, (2,), dilation=0.0)
+    px, py = W // 2, H // 2
+    for order in ([0, 1], [1, 0]):
+        p = _stack([items[k] for k in order])
+        pr = oracle.project(st, p, cam)[0]
+        assert pr[0, 1] != pr[1, 1] and np.float32(pr[0, 1]) == np.float32(pr[1, 1]) == np.float32(3.0)
+        c, nv = _pair_image(p, st, cam, px, py)
+        a = []
+        for k in range(2):
+            dx, dy = px + 0.5 - pr[k, 2], py + 0.5 - pr[k, 3]
+            g = math.exp(-0.5 * (pr[k, 7] * dx * dx + 2 * pr[k, 8] * dx * dy + pr[k, 9] * dy * dy))
+            a.append(min(f32(0.99), pr[k, 10] * g))
+        exp = pr[0, 11:14] * a[0] + pr[1, 11:14] * a[1] * (1 - a[0])
+        np.testing.assert_allclose(c, exp, atol=1e-12)
+        assert nv == 0
+
+
+def test_near_plane_cull_is_exact_and_a_tie_is_explored():
+    """A Gaussian with depth one float32 step beyond the near plane is rendered; one exactly on
+    it is culled (t_z <= near), and because a depth that equals near cannot be settled by an
+    evaluation with rounding error, the oracle also offers the outcome that keeps it."""
+    near = np.float32(0.2)
+    st = oracle.Settings(W, H, 0, (1,), near_plane=float(near), dilation=0.0)
+    for z, culled in ((float(np.nextafter(near, np.float32(1.0))), False), (float(near), True)):
+        p = scene([[0, 0, z]], [[math.log(0.002)] * 3], [[1, 0, 0, 0]], [logit(0.7)], [[0.8, 0.3, 0.5]])
+        pr = oracle.project(st, p, cam0())[0]
+        assert (pr[0, 0] == 0) == culled
+        r = oracle.render(st, p, cam0(), variants=True)
+        c = r["image"][0, 0, :, H // 2, W // 2]
+        nv = r["nvar"][0, 0, H // 2, W // 2]
+        if culled:
+            assert np.all(c == 0.0) and nv == 2
+            alts = r["var"][0, 0, H // 2, W // 2, :2]
+            assert np.any(np.all(alts == 0.0, axis=1)) and np.any(alts.max(axis=1) > 0.1)
+        else:
+            assert c.max() > 0.1 and nv == 0
+
+
+def test_alpha_cut_inside_its_band_offers_both_outcomes():
+    """A candidate whose o G is within the float32 accuracy band of alpha_min is explored both
+    ways (kept and cut); one well outside the band is not."""
+    amin = f32(1.0 / 255.0)
+    x = 0.5 * 3.0 / FOC  # projects to the centre of pixel (W/2, H/2): G = 1 there
+    for rel, amb in ((2e-7, True), (1e-3, False)):
+        o = amin * (1.0 + rel)
+        p = scene([[x, x, 3.0]], [[math.log(0.05)] * 3], [[1, 0, 0, 0]], [logit(o)], [[0.8, 0.3, 0.5]])
+        st = oracle.Settings(W, H, 0, (1,), dilation=0.0)
+        pr = oracle.project(st, p, cam0())[0]
+        assert pr[0, 2] == W // 2 + 0.5 and pr[0, 3] == H // 2 + 0.5
+        assert abs(pr[0, 10] / amin - 1.0) < max(2 * rel, 5e-7)  # the float32 logit keeps o near the target
+        r = oracle.render(st, p, cam0(), variants=True)
+        nv = r["nvar"][0, 0, H // 2, W // 2]  # the mean sits on this pixel centre: G = 1
+        if amb:
+            assert nv == 2
+            alts = r["var"][0, 0, H // 2, W // 2, :2]
+            np.testing.assert_allclose(np.sort(alts[:, 0]), [0.0, pr[0, 11] * pr[0, 10]], atol=1e-15)
+        else:
+            assert nv == 0
+
+
+def test_transmittance_stop_inside_its_band_offers_both_outcomes():
+    """Two clamped layers (alpha = 0.99f each) leave T' = (1 - 0.99f)^2. With t_stop set to the
+    float32 nearest T', the stop test is inside the accuracy band of the product: the oracle
+    offers the colour with and without the second layer. With t_stop = 1e-4 it is settled."""
+    items = [_big(2.0, 0.9995, [0.8, 0.1, 0.3]), _big(3.0, 0.9995, [0.2, 0.9, 0.5])]
+    p = _stack(items)
+    one_minus = 1.0 - f32(0.99)
+    T2 = one_minus * one_minus
+    for t_stop, amb in ((f32(T2), True), (1e-4, False)):
+        st = oracle.Settings(W, H, 0, (2,), t_stop=t_stop)
+        pr = oracle.project(st, p, cam0())[0]
+        r = oracle.render(st, p, cam0(), variants=True)
+        nv = r["nvar"][0, 0, H // 2, W // 2]
+        if amb:
+            assert nv == 2
+            alts = np.sort(r["var"][0, 0, H // 2, W // 2, :2, 0])
+            one = f32(0.99) * pr[0, 11]
+            np.testing.assert_allclose(alts, [one, one + f32(0.99) * one_minus * pr[1, 11]], atol=1e-12)
+        else:
+            assert nv == 0
+            assert r["ncontrib"][0, 0, H // 2, W // 2] == 1
+
+
+def test_non_finite_and_zero_quaternion_gaussians_are_culled():
+    """Reading: a Gaussian with a zero quaternion or any non-finite parameter is culled: the image
+    equals the render without it and its gradient is zero."""
+    w = synth.config_plain_forward(seed=13, n=120, width=40, height=32)
+    cams = synth.identity_camera(40, 32, 40.0)[None]
+    extra = w.params[:, :6].copy()
+    for k, ch in enumerate([0, 4, 7, 10, 12]):
+        extra[ch, k] = np.nan
+    extra[6:10, 5] = 0.0
+    p = np.ascontiguousarray(np.concatenate([w.params, extra], axis=1))
+    st = oracle.Settings(40, 32, 0, (126,))
+    a = oracle.render(st, p, cams)["image"]
+    b = oracle.render(oracle.Settings(40, 32, 0, (120,)), w.params, cams)["image"]
+    assert np.array_equal(a, b)
+    dp, _, _ = oracle.backward(st, p, cams, np.random.default_rng(5).standard_normal(a.shape))
+    assert np.all(dp[:, 120:] == 0.0) and np.isfinite(dp).all()
