@@ -636,14 +636,11 @@ int gs_rate_histogram_workspace_size(int32_t n_attr, size_t* bytes_out) {
   return GS_OK;
 }
 
-int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out, void* ws,
-                      size_t ws_bytes, void* stream) {
-  size_t need = 0;
-  if (n < 0 || n_attr < 1 || !attrs || !bits_out || !ws || !(step > 0.f)) return GS_ERR_INVALID_ARG;
-  gs_rate_histogram_workspace_size(n_attr, &need);
-  if (ws_bytes < need) return GS_ERR_WORKSPACE;
-  hipStream_t st = (hipStream_t)stream;
-  char* w = (char*)ws;
+namespace {
+// The histogram rate on a workspace w laid out as gs_rate_histogram_workspace_size states:
+// status word, per-attribute symbol range, per-attribute bins.
+int hist_launch(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out, char* w,
+                hipStream_t st) {
   uint32_t* err = (uint32_t*)w;
   int* mm = (int*)(w + 256);
   uint32_t* hist = (uint32_t*)(w + 256 + (size_t)n_attr * 8);
@@ -666,6 +663,16 @@ int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step,
     hipLaunchKernelGGL(k_hist_bits, dim3(n_attr), dim3(256), 0, st, n, mm, hist, bits_out);
   }
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+}  // namespace
+
+int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  if (n < 0 || n_attr < 1 || !attrs || !bits_out || !ws || !(step > 0.f)) return GS_ERR_INVALID_ARG;
+  gs_rate_histogram_workspace_size(n_attr, &need);
+  if (ws_bytes < need) return GS_ERR_WORKSPACE;
+  return hist_launch(n, n_attr, attrs, step, bits_out, (char*)ws, (hipStream_t)stream);
 }
 
 
