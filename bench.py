@@ -28,13 +28,23 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd ms/view (300k Gaussians, 960x540), batched vs per-view; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# unpacked FP32 VALU lane operations per second: 256 CUs x 64 lanes x 2.4 GHz
+# MI355X published dense FP32 vector peak (packed FP32: 256 CUs x 128 FMA lanes x 2 flops x 2.4 GHz)
+FP32_PEAK_FLOPS = 157.3e12
+# the same without packed FP32 forms, which this build does not emit: 256 CUs x 64 lanes x 2 x 2.4 GHz
+FP32_UNPACKED_FLOPS = 78.6e12
+# unpacked FP32 VALU lane operations per second (any VALU instruction counts once): 256 x 64 x 2.4 GHz
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
-# algorithmic VALU operations (an FMA counts once) of the raster passes:
-# evaluating one Gaussian at one pixel (offset, quadratic form, exp, opacity, cut-off test),
-# and one compositing update of one layer (forward) or its gradient (backward)
-FWD_OPS_EVAL, FWD_OPS_CONTRIB = 12, 8
-BWD_OPS_EVAL, BWD_OPS_CONTRIB = 12, 30
+# Algorithmic FP32 flops (an FMA counts 2, exp2 and a reciprocal 1) of the raster passes.
+#  evaluation of one Gaussian at one pixel: offset (2), quadratic form u = a dx + b dy, v = c dy,
+#  u dx + v dy (7), exp2 (1), times the opacity (1)                                      = 11
+#  forward compositing update of one layer: 1 - alpha, T (1 - alpha), alpha T, C += c alpha T (3 FMA) = 9
+#  backward, per (pixel, entry) walked: the evaluation (11), 1 - alpha and its reciprocal (2), the
+#  mean / conic / opacity gradient terms formed once from the layers' sum (14) and their addition
+#  into the entry's nine sums (9)                                                         = 36
+#  backward, per (pixel, entry, layer) contribution: T in front (1), alpha T (1), colour gradient
+#  (3 FMA), w . c (2 FMA + 1), the alpha gradient (2 FMA), the colour behind (1 FMA)      = 19
+FWD_FLOP_EVAL, FWD_FLOP_CONTRIB = 11, 9
+BWD_FLOP_EVAL, BWD_FLOP_CONTRIB = 36, 19
 # algorithmic VALU operations per image element (pixel, channel, layer) of the D-SSIM kernels:
 # forward = two 11-tap passes of x, x^2, x y (66) + the two products + the per-pixel SSIM value and
 # derivatives (30), plus the target's two moments shared by the L layers; backward = two passes of
@@ -113,7 +123,6 @@ def significance_sorted(torch, dev, p_host):
 # backward (data path and weight gradients, each as large as the forward's products)
 MOTION_FLOP_FWD = 2 * (2 * (32 * 64 + 64 * 64) + 64 * 3 + 64 * 4)
 MOTION_FLOP_BWD = 2 * MOTION_FLOP_FWD
-FP32_PEAK_FLOPS = 157.3e12
 
 
 def bench_motion(torch, dev, p, steps, st=None, cams=None, targets=None):
@@ -215,6 +224,43 @@ def bench_bitstream(torch, dev, w, p, steps, capture, time_graph):
                               "psnr_decoded_vs_original_db": 10 * math.log10(1.0 / mse) if mse > 0 else None}}
 
 
+def measure_peaks(torch, dev, L):
+    """Attainable FP32 FMA rate and copy bandwidth on this GPU, from the library's measurement
+    kernels (median of 10 launches each)."""
+    import ctypes
+
+    from paper_2509_17513_amd import _lib
+    s = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+    def med(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        ts = sorted(a.elapsed_time(b) for a, b in evs)
+        return ts[len(ts) // 2]
+
+    blocks, iters = 256 * 32, 4096
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    ms_fma = med(lambda: _lib.check(L.gs_peak_fma(blocks, iters, ctypes.c_float(0.999), ctypes.c_float(1e-3),
+                                                  ctypes.c_void_p(out.data_ptr()), s), "gs_peak_fma"))
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms_copy = med(lambda: _lib.check(L.gs_peak_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                                    nbytes, s), "gs_peak_copy"))
+    del src, dst, out
+    return {"fma_tflops": blocks * 256 * iters * 16 / (ms_fma * 1e-3) / 1e12,
+            "fma_frac_of_published": blocks * 256 * iters * 16 / (ms_fma * 1e-3) / FP32_PEAK_FLOPS,
+            "copy_gbs": 2 * nbytes / (ms_copy * 1e-3) / 1e9,
+            "copy_frac_of_published": 2 * nbytes / (ms_copy * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "fma_kernel": f"{blocks} x 256 threads x 8 chains x {iters} FMA", "copy_bytes": nbytes}
+
+
 def cpu_baseline(w, target_s=25.0):
     """The FP64 oracle (as it stands) on a band of rows of view 0, all six layers, forward +
     analytic backward of the same layer-weighted L1 loss; scaled to ms per view."""
@@ -271,7 +317,7 @@ def bench_rate(torch, dev, L, steps, n=1_000_000, tune=True):
     p = torch.from_numpy(p_host).to(dev)
     lv = synth.nested_levels(n)
     lw = synth.paper_level_weights(6)
-    rm = RateModel(56, dev, seed=5, attrs_host=p_host[3:59])
+    rm = RateModel(56, dev, seed=5, attrs=p[3:59])
     ctx = context(p, 1.0, lv)
     da = torch.zeros((56, n), dtype=torch.float32, device=dev)
     attrs = ctypes.c_void_p(p.data_ptr() + 4 * 3 * n)
@@ -389,7 +435,7 @@ def bench_train(torch, dev, steps, n=1_000_000, views=8):
     p = torch.from_numpy(p_host).to(dev)
     lv = synth.nested_levels(n)
     st = RenderSettings(960, 540, 3, tuple(lv), tuple(synth.paper_level_weights(6)))
-    tr = JointTrainer(p, cams, targets, st, RateModel(56, dev, seed=5, attrs_host=p_host[3:59]),
+    tr = JointTrainer(p, cams, targets, st, RateModel(56, dev, seed=5, attrs=p[3:59]),
                       lambda_rate=1e-3, extent=1.0, seed=5)
     tr.step(check_overflow=True)
     torch.cuda.synchronize()
@@ -405,9 +451,9 @@ def bench_train(torch, dev, steps, n=1_000_000, views=8):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--per-view-steps", type=int, default=2)
+    ap.add_argument("--per-view-steps", type=int, default=20)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=300_000)
@@ -507,23 +553,36 @@ def main():
             fn()
         return g
 
-    def time_graph(g, steps):
+    replay_stats = {}
+
+    def time_graph(g, steps, key=None):
+        """Median over `steps` graph replays, each bracketed by events on the replay stream; the
+        replays run back to back between two synchronisations (their mean is kept in replay_stats)."""
         g.replay()
         torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for a, b in evs:
+            a.record()
             g.replay()
+            b.record()
         torch.cuda.synchronize()
-        return 1e3 * (time.perf_counter() - t0) / steps
+        mean = 1e3 * (time.perf_counter() - t0) / steps
+        ts = sorted(a.elapsed_time(b) for a, b in evs)
+        med = ts[len(ts) // 2] if len(ts) % 2 else 0.5 * (ts[len(ts) // 2 - 1] + ts[len(ts) // 2])
+        if key:
+            replay_stats[key] = {"replays": steps, "median_ms": med, "mean_ms": mean, "min_ms": ts[0],
+                                 "max_ms": ts[-1]}
+        return med
 
     graph = capture(step)
-    ms_step_graph = time_graph(graph, args.steps)
+    ms_step_graph = time_graph(graph, args.steps, "batched")
     # forward only (what a decoder renders per frame), same workload and shapes
     graph_fwd = capture(lambda: render_forward(st, p, c, ws=ws, image=img, check_overflow=False))
     ms_fwd = time_graph(graph_fwd, args.steps)
     del graph_fwd
-    ms_step = min(ms_step_eager, ms_step_graph)
-    log(f"[bench] batched eager {ms_step_eager:.3f} ms/step, graph replay {ms_step_graph:.3f} ms/step")
+    ms_step = ms_step_graph
+    log(f"[bench] batched eager {ms_step_eager:.3f} ms/step, graph replay median {ms_step_graph:.3f} ms/step")
     # work counts of one more step, outside the timed region, by the counting variant of the
     # raster kernels (the timed launches do not count)
     from paper_2509_17513_amd import work_counters
@@ -537,17 +596,22 @@ def main():
     Lv = len(w.level_counts)
     dom = max(kernels.items(), key=lambda kv: kv[1]["ms_total"])[0]
     per_launch_s = kernels[dom]["ms_per_launch"] * 1e-3
+    peaks = measure_peaks(torch, dev, L)
+    log(f"[bench] attainable peaks {peaks}")
     if dom in ("raster_fwd", "raster_bwd"):
         if dom == "raster_fwd":
-            ops = stats.fwd_evals * FWD_OPS_EVAL + stats.fwd_contribs * FWD_OPS_CONTRIB
+            flop = stats.fwd_evals * FWD_FLOP_EVAL + stats.fwd_contribs * FWD_FLOP_CONTRIB
         else:
-            ops = stats.bwd_evals * BWD_OPS_EVAL + stats.bwd_contribs * BWD_OPS_CONTRIB
-        ach = ops / per_launch_s
-        roof = {"bound": "alu", "achieved": ach / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                "frac": ach / ALU_PEAK_OPS, "traffic": read_traffic(dom), "kernel": dom,
+            flop = stats.bwd_evals * BWD_FLOP_EVAL + stats.bwd_contribs * BWD_FLOP_CONTRIB
+        ach = flop / per_launch_s
+        roof = {"bound": "alu", "achieved": ach / 1e12, "peak": FP32_PEAK_FLOPS / 1e12, "unit": "TFLOP/s",
+                "frac": ach / FP32_PEAK_FLOPS, "traffic": read_traffic(dom), "kernel": dom,
+                "frac_of_unpacked_peak": ach / FP32_UNPACKED_FLOPS,
+                "frac_of_measured_fma": ach / (peaks["fma_tflops"] * 1e12),
                 "work_per_launch": {"evals": stats.fwd_evals if dom == "raster_fwd" else stats.bwd_evals,
                                     "contribs": stats.fwd_contribs if dom == "raster_fwd" else stats.bwd_contribs,
-                                    "ops": ops}}
+                                    "flop": flop},
+                "ms_per_launch": per_launch_s * 1e3}
     else:
         by = kernel_bytes(dom, w.n, B, pairs, Lv, HW)
         ach = by / per_launch_s / 1e9
@@ -560,11 +624,12 @@ def main():
         if by:
             gbs = by / (v["ms_per_launch"] * 1e-3) / 1e9
             hbm_kernels[k] = {"GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    for k, ev, co, oe, oc in (("raster_fwd", stats.fwd_evals, stats.fwd_contribs, FWD_OPS_EVAL, FWD_OPS_CONTRIB),
-                              ("raster_bwd", stats.bwd_evals, stats.bwd_contribs, BWD_OPS_EVAL, BWD_OPS_CONTRIB)):
+    for k, ev, co, oe, oc in (("raster_fwd", stats.fwd_evals, stats.fwd_contribs, FWD_FLOP_EVAL, FWD_FLOP_CONTRIB),
+                              ("raster_bwd", stats.bwd_evals, stats.bwd_contribs, BWD_FLOP_EVAL, BWD_FLOP_CONTRIB)):
         if k in kernels:
             t = kernels[k]["ms_per_launch"] * 1e-3
-            kernels[k]["alu_frac"] = (ev * oe + co * oc) / t / ALU_PEAK_OPS
+            kernels[k]["flop_frac"] = (ev * oe + co * oc) / t / FP32_PEAK_FLOPS
+            kernels[k]["tflops"] = (ev * oe + co * oc) / t / 1e12
             kernels[k]["evals"] = ev
             kernels[k]["contribs"] = co
     # step-level algorithmic HBM bytes (sum over the HBM-bound kernels' algorithmic bytes plus the
@@ -585,6 +650,8 @@ def main():
                    "sh_degree": w.sh_degree, "levels": list(w.level_counts), "pairs": pairs,
                    "loss": "sum_l lambda^l mean L1 vs uniform-noise targets"},
         "roofline": roof,
+        "peaks": peaks,
+        "replays": replay_stats,
         "autotune": tune,
         "forward_only": {"ms_per_step": ms_fwd, "ms_per_view": ms_fwd / B},
         "step_hbm": step_hbm,
@@ -675,13 +742,38 @@ def main():
             step_pv()
         torch.cuda.synchronize()
         ms_pv_eager = 1e3 * (time.perf_counter() - t0) / args.per_view_steps
-        ms_pv_graph = time_graph(capture(step_pv), args.per_view_steps)
-        ms_pv = min(ms_pv_eager, ms_pv_graph)
+        g_pv = capture(step_pv)
+        ms_pv = time_graph(g_pv, args.per_view_steps, "per_view")
+        del g_pv
         out["per_view"] = {"ms_per_step": ms_pv, "ms_per_view": ms_pv / B, "ms_per_step_eager": ms_pv_eager,
-                           "ms_per_step_graph": ms_pv_graph, "launch_sequences": B * len(lvl) * 2,
-                           "speedup_batched": ms_pv / ms_step}
-        log(f"[bench] per-view eager {ms_pv_eager:.2f}, graph {ms_pv_graph:.2f} ms/step; batched speedup "
+                           "launch_sequences": B * len(lvl) * 2, "speedup_batched": ms_pv / ms_step,
+                           "timing": "median of graph replays (ms_per_step); eager mean (ms_per_step_eager)"}
+        log(f"[bench] per-view eager {ms_pv_eager:.2f}, graph median {ms_pv:.2f} ms/step; batched speedup "
             f"{ms_pv / ms_step:.2f}x")
+        del lvl
+        torch.cuda.empty_cache()
+        # intermediate: one launch sequence per view with the six layers batched (separates the
+        # gain of batching the layers from that of batching the views)
+        st1 = RenderSettings(w.width, w.height, w.sh_degree, tuple(w.level_counts), tuple(w.level_weights),
+                             bin_chunk=st.bin_chunk, row_seg=st.row_seg, wave_layout=st.wave_layout)
+        img1, ws1 = render_forward(st1, p, cams1[0], ws=Workspace(st1, w.n, 1, 1, dev, pair_capacity=60 * w.n))
+        for v in range(B):
+            render_forward(st1, p, cams1[v], ws=ws1, image=img1)
+        dp1 = torch.zeros_like(p)
+
+        def step_iv():
+            for v in range(B):
+                render_forward(st1, p, cams1[v], ws=ws1, image=img1, check_overflow=False)
+                render_backward(st1, p, cams1[v], ws1, image=img1, target=tg1[v], d_params=dp1, loss=loss)
+
+        step_iv()
+        torch.cuda.synchronize()
+        g_iv = capture(step_iv)
+        ms_iv = time_graph(g_iv, args.per_view_steps, "per_view_levels_batched")
+        del g_iv, ws1, img1, dp1
+        out["per_view_levels_batched"] = {"ms_per_step": ms_iv, "ms_per_view": ms_iv / B,
+                                          "launch_sequences": B * 2, "speedup_batched": ms_iv / ms_step}
+        log(f"[bench] per-view with layers batched: graph median {ms_iv:.2f} ms/step")
 
     if not args.no_rate:
         out["rate"] = bench_rate(torch, dev, L, args.steps, tune=not args.no_autotune)

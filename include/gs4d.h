@@ -403,6 +403,15 @@ int gs_rate_autotune(const gs_rate_desc* desc, const float* attrs, const uint16_
                      const float* b_f32, double* bits_scratch, float* d_attrs, float* d_w, float* d_b, void* stream,
                      int32_t* best_blocks, float* times_ms);
 
+/* Initial output bias of the learned rate's Laplace head from the attributes themselves (a
+ * starting point for training, Sec. 3.3 fits the entropy model jointly): for each attribute a,
+ * b[a][128] = mean(y) and b[a][129] = softplus^-1(max(MAD - step/16, step/4)) with MAD the mean
+ * absolute deviation, so that the untrained network starts at the context-free Laplace fit.
+ * Other entries of b are left as they are. attrs [n_attr][n] float32, b_f32 [n_attr][130],
+ * acc [2 n_attr] float64 device scratch (overwritten). n >= 1. */
+int gs_rate_init_output_bias(int32_t n, int32_t n_attr, const float* attrs, float step, float* b_f32, double* acc,
+                             void* stream);
+
 /* Empirical-histogram rate (the reference the learned rate is checked against): per attribute
  * bits = -sum_i log2(count(k_i) / n) = n H over its symbol histogram, in FP64.
  * bits_out [n_attr] float64 (overwritten). The symbol range of one attribute
@@ -421,6 +430,14 @@ int gs_adam_step(int64_t n, float* params, float* grads, float* m, float* v, uin
 /* Zero-fills bytes (a multiple of 4) of device memory with a kernel (no memset node, so it is
  * safe inside captured graphs). */
 int gs_zero(void* p, size_t bytes, void* stream);
+
+/* Measurement kernels for the attainable peaks the hot kernels are compared with (not part of
+ * the method). gs_peak_fma: blocks x 256 threads, each running 8 independent float32 FMA chains
+ * of iters rounds (16 iters flops per thread), writing one float per thread to out [blocks x 256].
+ * gs_peak_copy: a plain copy of bytes (a multiple of 16) from src to dst in 16-byte vectors
+ * (also the reference kernel for calibrating HBM byte counters). Both asynchronous. */
+int gs_peak_fma(int32_t blocks, int32_t iters, float x, float y, float* out, void* stream);
+int gs_peak_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Per-kernel timing. While enabled, every kernel launch of the library is
  * bracketed by HIP events recorded on its launch stream (do not enable it

@@ -58,6 +58,8 @@ def lib():
         L.oc_backward.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P, P, P]
         L.oc_fd.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, ctypes.c_double, P, P, P]
         L.oc_fd.restype = ctypes.c_int
+        L.oc_set_threads.argtypes = [ctypes.c_int]
+        L.oc_set_threads.restype = ctypes.c_int
         L.oc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
         L.oc_quat_rot.argtypes = [P, P]
         L.oc_quat_mul.argtypes = [P, P, P]
@@ -211,6 +213,11 @@ def finite_differences(st: Settings, params, cams, d_image, gauss, chan, h=1e-5)
                      float(h), _ptr(fd), _ptr(status), _ptr(skipped))
     assert rc == 0
     return fd, status, skipped
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the C++ oracle's following calls; returns the previous count."""
+    return int(lib().oc_set_threads(int(n)))
 
 
 def sh_basis(deg: int, d) -> np.ndarray:

@@ -708,6 +708,18 @@ extern "C" {
 
 int oc_n_channels(int deg) { return n_channels(deg); }
 
+// OpenMP threads of the following calls (n >= 1); returns the previous maximum.
+int oc_set_threads(int n) {
+#ifdef _OPENMP
+  const int prev = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return prev;
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 void oc_sh_basis(int deg, double x, double y, double z, double* Y) { sh_basis(deg, x, y, z, Y); }
 
 void oc_quat_rot(const double* q, double* R) {

@@ -275,3 +275,41 @@ def init_weights(n_attr, seed, attrs=None, step=1.0 / 64):
         target = np.maximum(mad - step / 16, step / 4)
         Bv[:, B3_OFF + 1] = np.log(np.expm1(target))  # softplus^-1
     return f64_to_bf16_bits(W), Bv
+
+
+# ------------------------------------------------------- context-free baselines
+def laplace_fit_bits(attrs, step):
+    """Context-free baseline of the learned rate (the method without its context): per attribute a
+    Laplace with the maximum-likelihood location (median) and scale (mean absolute deviation), bits
+    of the rint-quantised symbols under its PMF (CDF differences one step apart, floor 1e-9)."""
+    out = np.zeros(attrs.shape[0])
+    for a in range(attrs.shape[0]):
+        y = np.rint(attrs[a].astype(np.float64) / step) * step
+        m = np.median(y)
+        b = max(np.abs(y - m).mean(), step / 16)
+        t = np.abs(y - m)
+        h = step / 2
+        with np.errstate(divide="ignore", over="ignore"):
+            far = math.log(0.5) - (t - h) / b + math.log(-math.expm1(-step / b))
+            near = np.log(np.maximum(1 - 0.5 * np.exp(-(h + t) / b) - 0.5 * np.exp(-(h - t) / b), 1e-300))
+        lp = np.maximum(np.where(t >= h, far, near), math.log(1e-9))
+        out[a] = -lp.sum() / math.log(2)
+    return out
+
+
+def gaussian_fit_bits(attrs, step):
+    """The paper's entropy model for residuals (Sec. 3.3, inter-frame optimisation), used as a
+    context-free baseline: per attribute a Gaussian with the symbols' mean and standard deviation,
+    bits of the rint-quantised symbols under its PMF (CDF differences one step apart, floor 1e-9)."""
+    from math import erf, sqrt
+    out = np.zeros(attrs.shape[0])
+    verf = np.vectorize(erf)
+    for a in range(attrs.shape[0]):
+        y = np.rint(attrs[a].astype(np.float64) / step) * step
+        mu, sd = y.mean(), max(y.std(), step / 16)
+        ks, cnt = np.unique(y, return_counts=True)
+        hi = 0.5 * (1 + verf((ks + step / 2 - mu) / (sd * sqrt(2))))
+        lo = 0.5 * (1 + verf((ks - step / 2 - mu) / (sd * sqrt(2))))
+        P = np.maximum(hi - lo, 1e-9)
+        out[a] = -(cnt * np.log2(P)).sum()
+    return out

@@ -235,6 +235,30 @@ void set_capacity(RenderDims& d, const Layout& lo0, size_t ws_bytes) {
 
 using namespace gs;
 
+// ------------------------------------------------------ attainable peaks
+// Eight independent FMA chains per thread (enough to hide the FMA latency),
+// iters rounds each; the result is stored so that nothing is dead code.
+__global__ __launch_bounds__(256) void k_peak_fma(int iters, float x, float y, float* __restrict__ out) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  float a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = (float)(gid + k) * 1e-7f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = fmaf(a[k], x, y);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += a[k];
+  out[gid] = s;
+}
+
+// A plain device copy in 16-byte vectors (grid-stride).
+__global__ __launch_bounds__(256) void k_peak_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 extern "C" {
 
 int gs_workspace_size(const gs_settings* s, int32_t n, int32_t n_frames, int32_t n_views, int64_t pair_capacity,
@@ -538,6 +562,24 @@ int gs_profile_collect(int32_t max_ids, double* total_ms, int32_t* counts) {
 }
 
 const char* gs_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "?"; }
+
+int gs_peak_fma(int32_t blocks, int32_t iters, float x, float y, float* out, void* stream) {
+  if (blocks < 1 || iters < 1 || !out) return fail_arg("gs_peak_fma: need blocks >= 1, iters >= 1, out");
+  hipLaunchKernelGGL(k_peak_fma, dim3(blocks), dim3(256), 0, (hipStream_t)stream, iters, x, y, out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GS_OK : fail_hip(e, "peak_fma");
+}
+
+int gs_peak_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst || bytes % 16) return fail_arg("gs_peak_copy: need src, dst and bytes a multiple of 16");
+  const size_t n = bytes / 16;
+  if (n == 0) return GS_OK;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(k_peak_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const float4*)src, (float4*)dst,
+                     n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GS_OK : fail_hip(e, "peak_copy");
+}
 
 
 }  // extern "C"

@@ -157,6 +157,32 @@ __global__ __launch_bounds__(256) void k_hist_bits(int n, const int* __restrict_
 }
 
 
+// ------------------------------------------------------- output-bias initialisation
+// Per attribute: sum of y (pass 0) and of |y - mean| (pass 1) in FP64, then the
+// output bias of the Laplace head set to (mean, softplus^-1(max(MAD - step/16, step/4))).
+__global__ __launch_bounds__(256) void k_rate_init_sum(int n, const float* __restrict__ attrs,
+                                                       double* __restrict__ acc, int pass) {
+  const int a = blockIdx.y;
+  const float* y = attrs + (size_t)a * n;
+  const double mean = pass ? acc[2 * a] / (double)n : 0.0;
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    s += pass ? fabs((double)y[i] - mean) : (double)y[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&acc[2 * a + pass], s);
+}
+
+__global__ void k_rate_init_bias(int n, int n_attr, const double* __restrict__ acc, float step,
+                                 float* __restrict__ b) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_attr) return;
+  const double mean = acc[2 * a] / (double)n, mad = acc[2 * a + 1] / (double)n;
+  const double target = fmax(mad - step / 16.0, step / 4.0);
+  float* ba = b + (size_t)a * kBPerAttr + 2 * kHid;
+  ba[0] = (float)mean;
+  ba[1] = (float)log(expm1(target));
+}
+
 // ---------------------------------------------------------------------- MLP
 // One wave handles 32 symbols of one attribute at a time. MFMA operand layout
 // (v_mfma_f32_32x32x16_bf16): lane l holds row / column (l & 31) and 8 values
@@ -614,29 +640,8 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
 
 using namespace gs;
 
-extern "C" {
-
-int gs_rate_context(int32_t n, const float* means, float extent, int32_t n_levels, const int32_t* level_counts,
-                    uint16_t* ctx_out, void* stream) {
-  if (n < 0 || !means || !ctx_out || !(extent > 0.f) || n_levels < 1 || n_levels > 8 || !level_counts)
-    return GS_ERR_INVALID_ARG;
-  if (n == 0) return GS_OK;
-  int lv[8];
-  for (int l = 0; l < 8; ++l) lv[l] = l < n_levels ? level_counts[l] : n;
-  hipStream_t st = (hipStream_t)stream;
-  ProfScope ps_(K_RATE_CTX, st);
-  hipLaunchKernelGGL(k_rate_ctx, dim3((n + 255) / 256), dim3(256), 0, st, n, means, extent, n_levels,
-                     make_int4(lv[0], lv[1], lv[2], lv[3]), make_int4(lv[4], lv[5], lv[6], lv[7]), ctx_out);
-  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
-}
-
-int gs_rate_histogram_workspace_size(int32_t n_attr, size_t* bytes_out) {
-  if (n_attr < 1 || !bytes_out) return GS_ERR_INVALID_ARG;
-  *bytes_out = 256 + (size_t)n_attr * 8 + (size_t)n_attr * kHistBins * 4;
-  return GS_OK;
-}
-
 namespace {
+
 // The histogram rate on a workspace w laid out as gs_rate_histogram_workspace_size states:
 // status word, per-attribute symbol range, per-attribute bins.
 int hist_launch(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out, char* w,
@@ -666,6 +671,30 @@ int hist_launch(int32_t n, int32_t n_attr, const float* attrs, float step, doubl
 }
 }  // namespace
 
+
+extern "C" {
+
+int gs_rate_context(int32_t n, const float* means, float extent, int32_t n_levels, const int32_t* level_counts,
+                    uint16_t* ctx_out, void* stream) {
+  if (n < 0 || !means || !ctx_out || !(extent > 0.f) || n_levels < 1 || n_levels > 8 || !level_counts)
+    return GS_ERR_INVALID_ARG;
+  if (n == 0) return GS_OK;
+  int lv[8];
+  for (int l = 0; l < 8; ++l) lv[l] = l < n_levels ? level_counts[l] : n;
+  hipStream_t st = (hipStream_t)stream;
+  ProfScope ps_(K_RATE_CTX, st);
+  hipLaunchKernelGGL(k_rate_ctx, dim3((n + 255) / 256), dim3(256), 0, st, n, means, extent, n_levels,
+                     make_int4(lv[0], lv[1], lv[2], lv[3]), make_int4(lv[4], lv[5], lv[6], lv[7]), ctx_out);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_rate_histogram_workspace_size(int32_t n_attr, size_t* bytes_out) {
+  if (n_attr < 1 || !bytes_out) return GS_ERR_INVALID_ARG;
+  *bytes_out = 256 + (size_t)n_attr * 8 + (size_t)n_attr * kHistBins * 4;
+  return GS_OK;
+}
+
+
 int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out, void* ws,
                       size_t ws_bytes, void* stream) {
   size_t need = 0;
@@ -675,6 +704,17 @@ int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step,
   return hist_launch(n, n_attr, attrs, step, bits_out, (char*)ws, (hipStream_t)stream);
 }
 
+
+int gs_rate_init_output_bias(int32_t n, int32_t n_attr, const float* attrs, float step, float* b_f32, double* acc,
+                             void* stream) {
+  if (n < 1 || n_attr < 1 || !attrs || !b_f32 || !acc || !(step > 0.f)) return GS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_zero(acc, (size_t)n_attr * 2 * sizeof(double), st) != hipSuccess) return GS_ERR_HIP;
+  const dim3 grid(std::min(64, (n + 255) / 256), n_attr);
+  for (int pass = 0; pass < 2; ++pass) hipLaunchKernelGGL(k_rate_init_sum, grid, dim3(256), 0, st, n, attrs, acc, pass);
+  hipLaunchKernelGGL(k_rate_init_bias, dim3((n_attr + 63) / 64), dim3(64), 0, st, n, n_attr, acc, step, b_f32);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
 
 int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
                   const float* b_f32, double* bits_out, double* loss_out, float* sym_bits, float* d_attrs, float* d_w,

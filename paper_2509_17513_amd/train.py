@@ -14,7 +14,6 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-import math
 
 import numpy as np
 import torch
@@ -75,21 +74,17 @@ def _bf16_bits(x: np.ndarray) -> np.ndarray:
 class RateModel:
     """Per-attribute Laplace MLP (16 -> 64 -> 64 -> 2): FP32 masters, BF16 copies, Adam state."""
 
-    def __init__(self, n_attr: int, device, seed: int = 0, attrs_host: np.ndarray | None = None,
+    def __init__(self, n_attr: int, device, seed: int = 0, attrs: torch.Tensor | None = None,
                  step: float = 1.0 / 64):
+        """Seeded random weights (scaled by 1/sqrt(fan-in), the output layer 10x smaller) and zero
+        biases; with attrs [n_attr][n] (device) the output bias starts at the context-free Laplace
+        fit of each attribute (gs_rate_init_output_bias)."""
         rng = np.random.default_rng(seed)
         w = np.zeros((n_attr, W_PER_ATTR))
         w[:, :1024] = rng.standard_normal((n_attr, 1024)) * 0.25
         w[:, 1024:5120] = rng.standard_normal((n_attr, 4096)) * 0.125
         w[:, 5120:] = rng.standard_normal((n_attr, 128)) * 0.0125
         b = np.zeros((n_attr, B_PER_ATTR), np.float32)
-        if attrs_host is not None:
-            a64 = attrs_host.astype(np.float64)
-            mu = a64.mean(axis=1)
-            mad = np.abs(a64 - mu[:, None]).mean(axis=1)
-            b[:, 128] = mu
-            target = np.maximum(mad - step / 16, step / 4)
-            b[:, 129] = np.log(np.expm1(target))
         self.n_attr, self.step_size = n_attr, step
         self.w = torch.from_numpy(w.astype(np.float32)).to(device)
         self.w16 = torch.from_numpy(_bf16_bits(w).view(np.int16)).to(device)
@@ -102,6 +97,15 @@ class RateModel:
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
         self.t = 0
         self.blocks = 0  # launch blocks per attribute; 0 = library default (see autotune)
+        if attrs is not None:
+            self.init_output_bias(attrs)
+
+    def init_output_bias(self, attrs: torch.Tensor):
+        if tuple(attrs.shape[:1]) != (self.n_attr,) or not attrs.is_contiguous() or attrs.dtype != torch.float32:
+            raise ValueError("attrs must be a contiguous float32 [n_attr][n] tensor")
+        acc = torch.empty(2 * self.n_attr, dtype=torch.float64, device=self.b.device)
+        check(lib().gs_rate_init_output_bias(attrs.shape[1], self.n_attr, _p(attrs), ctypes.c_float(self.step_size),
+                                             _p(self.b), _p(acc), _s(self.b.device)), "gs_rate_init_output_bias")
 
     def desc(self, n, mode, level_counts, level_weights, lambda_rate, seed=0, offset=0, fit_scale=None):
         d = _lib.GsRateDesc()
@@ -268,41 +272,6 @@ class JointTrainer:
         hb = histogram_bits(attrs, self.rate.step_size)
         torch.cuda.synchronize()
         return self.rate.bits.cpu().numpy(), hb.cpu().numpy()
-
-
-def laplace_fit_bits(attrs: np.ndarray, step: float) -> np.ndarray:
-    """Context-free baseline: per-attribute Laplace with the maximum-likelihood location (median)
-    and scale (mean absolute deviation), bits of the rint-quantised symbols (host, float64)."""
-    out = np.zeros(attrs.shape[0])
-    for a in range(attrs.shape[0]):
-        y = np.rint(attrs[a].astype(np.float64) / step) * step
-        m = np.median(y)
-        b = max(np.abs(y - m).mean(), step / 16)
-        t = np.abs(y - m)
-        h = step / 2
-        with np.errstate(divide="ignore", over="ignore"):
-            far = math.log(0.5) - (t - h) / b + math.log(-math.expm1(-step / b))
-            near = np.log(np.maximum(1 - 0.5 * np.exp(-(h + t) / b) - 0.5 * np.exp(-(h - t) / b), 1e-300))
-        lp = np.maximum(np.where(t >= h, far, near), math.log(1e-9))
-        out[a] = -lp.sum() / math.log(2)
-    return out
-
-
-def gaussian_fit_bits(attrs: np.ndarray, step: float) -> np.ndarray:
-    """The paper's residual entropy model (Sec. 3.3, inter-frame stage): a Gaussian with the
-    attribute's mean and variance, bits of the rint-quantised symbols (host, float64)."""
-    from math import erf, sqrt
-    out = np.zeros(attrs.shape[0])
-    verf = np.vectorize(erf)
-    for a in range(attrs.shape[0]):
-        y = np.rint(attrs[a].astype(np.float64) / step) * step
-        mu, sd = y.mean(), max(y.std(), step / 16)
-        ks, cnt = np.unique(y, return_counts=True)
-        hi = 0.5 * (1 + verf((ks + step / 2 - mu) / (sd * sqrt(2))))
-        lo = 0.5 * (1 + verf((ks - step / 2 - mu) / (sd * sqrt(2))))
-        P = np.maximum(hi - lo, 1e-9)
-        out[a] = -(cnt * np.log2(P)).sum()
-    return out
 
 
 class RigidTrainer:

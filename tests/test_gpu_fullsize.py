@@ -239,7 +239,7 @@ def test_rate_1M_x_56_histogram_and_sampled_symbols():
     np.testing.assert_allclose(hb, rate.hist_bits(p_host[3:59], 1 / 64), rtol=1e-12)
     lv = synth.nested_levels(n)
     lw = synth.paper_level_weights(6)
-    rm = RateModel(56, dev, seed=5, attrs_host=p_host[3:59])
+    rm = RateModel(56, dev, seed=5, attrs=attrs)
     ctx = context(p, 1.0, lv)
     sym = torch.zeros((56, n), dtype=torch.float32, device=dev)
     rm.reset()

@@ -232,3 +232,23 @@ def test_adam_step_matches_reference():
     assert torch.all(g == 0)
     np.testing.assert_array_equal(rate.bf16_bits_to_f64(cp.cpu().numpy().view(np.uint16)),
                                   rate.bf16_round(p.cpu().numpy().astype(np.float64)))
+
+
+def test_initial_output_bias_is_the_context_free_laplace_fit():
+    _case("gs_rate_init_output_bias: mean and mean absolute deviation per attribute, on the device")
+    from paper_2509_17513_amd.train import RateModel
+    dev = torch.device("cuda:0")
+    n, A = 100_003, 7
+    rng = np.random.default_rng(61)
+    y = np.stack([rng.laplace(0.05 * a, 0.02 + 0.01 * a, n) for a in range(A)]).astype(np.float32)
+    y[3] = 0.25  # a constant attribute: MAD 0 -> the scale floor step / 4
+    rm = RateModel(A, dev, seed=3, attrs=torch.from_numpy(y).to(dev))
+    torch.cuda.synchronize()
+    b = rm.b.cpu().numpy()
+    y64 = y.astype(np.float64)
+    mean = y64.mean(axis=1)
+    mad = np.abs(y64 - mean[:, None]).mean(axis=1)
+    target = np.maximum(mad - Q / 16, Q / 4)
+    np.testing.assert_allclose(b[:, 128], mean.astype(np.float32), rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(b[:, 129], np.log(np.expm1(target)).astype(np.float32), rtol=1e-6, atol=1e-6)
+    assert np.all(b[:, :128] == 0.0)

@@ -34,7 +34,7 @@ def _setup(lam, seed=91, n=20000, W=240, H=136, views=(0, 6, 12, 18)):
     p = torch.from_numpy(p_host).to(dev)
     lv = synth.nested_levels(n)
     st = RenderSettings(W, H, 3, tuple(lv), tuple(synth.paper_level_weights(6)))
-    rate = RateModel(56, dev, seed=seed, attrs_host=p_host[3:])
+    rate = RateModel(56, dev, seed=seed, attrs=p[3:])
     return JointTrainer(p, cams, targets, st, rate, lambda_rate=lam, extent=1.0, seed=seed)
 
 
@@ -49,7 +49,7 @@ def _train(tr, steps):
 
 def test_joint_training_and_rate_network_gain():
     print("\n[case] joint training lambda_rate = 0 and > 0, 20k Gaussians, 4 views 240x136", flush=True)
-    from paper_2509_17513_amd.train import gaussian_fit_bits, laplace_fit_bits
+    from oracle.rate import gaussian_fit_bits, laplace_fit_bits
     steps = 120
     tr0 = _setup(0.0)
     l0 = _train(tr0, steps)

@@ -155,3 +155,37 @@ def test_symbol_weights_and_layers():
     w = rate.symbol_weights(10, [2, 5, 10], [0.5, 0.25, 1.0], 2.0)
     np.testing.assert_allclose(w[:2], 0.5), np.testing.assert_allclose(w[2:5], 2 * 0.25 / 3)
     np.testing.assert_allclose(w[5:], 2 * 1.0 / 5)
+
+
+def test_context_features_by_hand():
+    """The 16 context features of the learned rate model (a reading: the MLP inputs are not given
+    by the paper) at points whose sines and cosines are known exactly: u = mean / extent, then
+    sin(pi u), cos(pi u), sin(2 pi u), cos(2 pi u) per axis, then (layer - 1) / 5, each rounded to
+    BF16 (sqrt(2)/2 -> 0.70703125, 0.4 -> 0.400390625, 0.2 -> 0.2001953125)."""
+    r = 0.70703125
+    means = np.array([[0.5, 1.0], [-0.25, 0.0], [1.0, -0.5]])  # two Gaussians, columns
+    layer = np.array([3, 2])
+    got = rate.context(means, 1.0, layer)
+    exp0 = [0.5, -0.25, 1.0,  1.0, -r, 0.0,  0.0, r, -1.0,  0.0, -1.0, 0.0,  -1.0, 0.0, 1.0,  0.400390625]
+    exp1 = [1.0, 0.0, -0.5,  0.0, 0.0, -1.0,  -1.0, 1.0, 0.0,  0.0, 0.0, 0.0,  1.0, 1.0, -1.0,  0.2001953125]
+    np.testing.assert_allclose(got[:, 0], exp0, atol=1e-15)
+    np.testing.assert_allclose(got[:, 1], exp1, atol=1e-15)
+    # the extent scales the positions: extent 2 halves u
+    g2 = rate.context(2.0 * means, 2.0, layer)
+    np.testing.assert_array_equal(g2, got)
+    # layers from the nested level counts: Gaussian i belongs to the first level whose count exceeds i
+    np.testing.assert_array_equal(rate.layer_of(10, [2, 5, 10]), [1, 1, 2, 2, 2, 3, 3, 3, 3, 3])
+
+
+def test_context_free_fits_match_the_histogram_on_their_own_distributions():
+    """The two context-free baselines of the gain test reach the empirical entropy (histogram bits)
+    on data drawn from their own family and lose to it on the other family (Gibbs' inequality: the
+    histogram is the least rate any context-free model can assign)."""
+    rng = np.random.default_rng(0)
+    y = np.stack([rng.laplace(0.1, 0.05, 200_000), rng.normal(-0.2, 0.07, 200_000)]).astype(np.float32)
+    h = rate.hist_bits(y, 1 / 64)
+    lap = rate.laplace_fit_bits(y, 1 / 64)
+    gau = rate.gaussian_fit_bits(y, 1 / 64)
+    assert abs(lap[0] / h[0] - 1) < 5e-3 and abs(gau[1] / h[1] - 1) < 5e-3
+    assert lap[1] > 1.01 * h[1] and gau[0] > 1.01 * h[0]
+    assert np.all(lap >= h) and np.all(gau >= h)
