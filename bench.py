@@ -261,43 +261,117 @@ def measure_peaks(torch, dev, L):
             "fma_kernel": f"{blocks} x 256 threads x 8 chains x {iters} FMA", "copy_bytes": nbytes}
 
 
-def cpu_baseline(w, target_s=25.0):
-    """The FP64 oracle (as it stands) on a band of rows of view 0, all six layers, forward +
-    analytic backward of the same layer-weighted L1 loss; scaled to ms per view."""
+def _band_fit(run, rows_a, rows_b, height):
+    """Seconds per full image from two centred bands of rows: fixed (projection of every Gaussian)
+    plus per-row cost, fitted on the two band timings."""
+    ta, tb = run(rows_a), run(rows_b)
+    per_row = max(0.0, (tb - ta) / (rows_b - rows_a))
+    fixed = max(0.0, ta - per_row * rows_a)
+    return fixed + per_row * height, f"bands of {rows_a} and {rows_b} rows ({ta:.2f} s, {tb:.2f} s)"
+
+
+def _oracle_fwd_bwd(w, view, rows=None, backward=True):
+    """One view of workload w, every layer: the oracle's forward render, then its analytic backward
+    of the layer-weighted L1 against the view's target (rows: a centred band, or the whole image)."""
     import numpy as np
 
     import oracle
     st = oracle.Settings(w.width, w.height, w.sh_degree, tuple(w.level_counts))
-    cams = w.cams[0:1]
-    tgt = w.target[0:1]
-
-    def run(rows):
-        y0 = (w.height - rows) // 2
-        pix = np.arange(y0 * w.width, (y0 + rows) * w.width, dtype=np.int64)
-        t0 = time.perf_counter()
-        r = oracle.render(st, w.params, cams, sample=pix)
-        img = np.zeros((1, len(w.level_counts), 3, w.height * w.width))
-        img[..., pix] = r["image"]
-        tg = tgt.reshape(1, 3, -1)
+    cams = w.cams[view:view + 1]
+    L = len(w.level_counts)
+    HW = w.width * w.height
+    rows = w.height if rows is None else rows
+    y0 = (w.height - rows) // 2
+    pix = np.arange(y0 * w.width, (y0 + rows) * w.width, dtype=np.int64)
+    t0 = time.perf_counter()
+    r = oracle.render(st, w.params, cams, sample=None if rows == w.height else pix)
+    if backward:
+        img = np.zeros((1, L, 3, HW))
+        img[..., pix] = r["image"].reshape(1, L, 3, -1)
+        tg = w.target[view].reshape(1, 3, HW).astype(np.float64)
         d = np.zeros_like(img)
         lw = np.asarray(w.level_weights).reshape(1, -1, 1, 1)
-        d[..., pix] = lw * np.sign(img[..., pix] - tg[:, None, :, pix]) / (3.0 * w.width * w.height)
-        oracle.backward(st, w.params, cams, d.reshape(1, len(w.level_counts), 3, w.height, w.width))
-        return time.perf_counter() - t0
+        d[..., pix] = lw * np.sign(img[..., pix] - tg[:, None, :, pix]) / (3.0 * HW)
+        oracle.backward(st, w.params, cams, d.reshape(1, L, 3, w.height, w.width))
+    return time.perf_counter() - t0
 
-    # two band sizes: the per-view cost is fitted as fixed (projection of all Gaussians) + per row
-    r1 = 8
-    t1 = run(r1)
-    r2 = int(min(w.height, max(2 * r1, r1 * target_s / max(t1, 1e-3))))
-    t2 = run(r2)
-    per_row = (t2 - t1) / (r2 - r1) if r2 > r1 else t2 / r2
-    fixed = max(0.0, t1 - per_row * r1)
-    full_s = fixed + per_row * w.height if per_row > 0 else t2 * w.height / r2
-    return {"value": 1e3 * full_s, "unit": "ms/view", "cores": os.cpu_count(), "kind": "oracle",
-            "sample": f"view 0 of the 24, all 6 layers, forward + analytic backward of the layer-weighted L1 "
-                      f"(FP64 C++/OpenMP) on two bands of {r1} and {r2} of the {w.height} rows "
-                      f"({t1:.1f} s + {t2:.1f} s); per-view time = fixed {fixed:.2f} s + {per_row:.3f} s/row x "
-                      f"{w.height} rows"}
+
+def cpu_baselines(w3):
+    """The FP64 oracle as it stands, on the host's cores and on one thread, on bounded samples of
+    the workloads: 300k x 24 views (view 0 in full; one thread: two row bands), the plain 4,096-
+    Gaussian render (in full), the 200k SH-3 1280x720 forward + backward (row bands), and the
+    rate terms at 1M x 56 (histogram in full, the FP64 MLP on a 4k-Gaussian sample)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    import synth
+    from oracle import rate as orate
+    cores = oracle.set_threads(0)
+    out = {}
+
+    def both(fn):
+        oracle.set_threads(cores)
+        a = fn()
+        oracle.set_threads(1)
+        b = fn()
+        oracle.set_threads(cores)
+        return a, b
+
+    # 300k Gaussians, 24 views 960x540, 6 layers: ms per view
+    t_all = _oracle_fwd_bwd(w3, 0)
+    oracle.set_threads(1)
+    t_one, how = _band_fit(lambda r: _oracle_fwd_bwd(w3, 0, r), 4, 12, w3.height)
+    oracle.set_threads(cores)
+    out["batched_300000_24v_960x540_L6"] = {
+        "ms_per_view": 1e3 * t_all, "ms_per_view_1thread": 1e3 * t_one, "cores": cores,
+        "sample": f"view 0 of 24 in full (all cores); one thread: {how}, fitted to 540 rows"}
+    # plain forward, 4,096 Gaussians 128x128 (in full)
+    w1 = synth.config_plain_forward()
+    w1.target = synth.target_images(1, w1.width, w1.height, 11)
+    f_all, f_one = both(lambda: _oracle_fwd_bwd(w1, 0, backward=False))
+    fb_all, fb_one = both(lambda: _oracle_fwd_bwd(w1, 0))
+    out["plain_4096_128x128"] = {"ms_fwd": 1e3 * f_all, "ms_fwd_1thread": 1e3 * f_one, "ms_fwd_bwd": 1e3 * fb_all,
+                                 "ms_fwd_bwd_1thread": 1e3 * fb_one, "cores": cores, "sample": "the whole image"}
+    del w1
+    # forward + analytic backward, 200k SH 3 at 1280x720
+    w2 = synth.config_forward_backward()
+    t2_all, how_all = _band_fit(lambda r: _oracle_fwd_bwd(w2, 0, r), 16, 48, w2.height)
+    oracle.set_threads(1)
+    t2_one, how_one = _band_fit(lambda r: _oracle_fwd_bwd(w2, 0, r), 4, 12, w2.height)
+    oracle.set_threads(cores)
+    out["fwd_bwd_200000_1280x720_sh3"] = {"ms": 1e3 * t2_all, "ms_1thread": 1e3 * t2_one, "cores": cores,
+                                          "sample": f"all cores: {how_all}; one thread: {how_one}; fitted to 720 rows"}
+    del w2
+    # rate terms at 1M Gaussians x 56 attributes
+    n = 1_000_000
+    attrs = synth.cube_scene(n, 5, 3)[3:59]
+    t0 = time.perf_counter()
+    orate.hist_bits(attrs, 1 / 64)
+    t_hist = time.perf_counter() - t0
+    m = 4_000
+    cols = np.random.default_rng(5).choice(n, m, replace=False)
+    wb, bb = orate.init_weights(56, 5)
+    ctx = orate.context(synth.cube_scene(n, 5, 3)[0:3, cols], 1.0, orate.layer_of(n, synth.nested_levels(n))[cols])
+
+    def mlp():
+        t = time.perf_counter()
+        orate.rate_model(attrs[:, cols], ctx, wb, bb, 1 / 64, mode=1, seed=1)
+        return (time.perf_counter() - t) * n / m
+
+    t_mlp_all = mlp()
+    with threadpool_limits(1):
+        t_mlp_one = mlp()
+    out["rate_1000000x56"] = {"ms_histogram": 1e3 * t_hist, "ms_mlp_train_fwd_bwd": 1e3 * t_mlp_all,
+                              "ms_mlp_train_fwd_bwd_1thread": 1e3 * t_mlp_one,
+                              "sample": f"histogram of all 56M symbols (NumPy, one thread); the FP64 MLP forward + "
+                                        f"backward on {m} Gaussians x 56 attributes, scaled to 1M"}
+    head = out["batched_300000_24v_960x540_L6"]
+    baseline = {"value": head["ms_per_view"], "unit": "ms/view", "cores": cores, "kind": "oracle",
+                "sample": "view 0 of the 24 in full, all 6 layers, forward + analytic backward of the layer-weighted "
+                          "L1 (FP64 C++/OpenMP) on all host cores",
+                "value_1thread": head["ms_per_view_1thread"]}
+    return baseline, out
 
 
 MLP_FLOP_FWD = 2 * (16 * 64 + 64 * 64 + 64 * 2)                  # per symbol
@@ -374,7 +448,6 @@ def bench_rate(torch, dev, L, steps, n=1_000_000, tune=True):
     return {"workload": "rate_1000000x56_train_fwd_bwd", "mlp_ms": ms, "mlp_flop": flop,
             "mlp_tflops": flop / (ms * 1e-3) / 1e12, "mfma_frac": flop / (ms * 1e-3) / BF16_PEAK_FLOPS,
             "histogram_ms": hist_ms, "histogram_GB/s": n * 56 * 4 * 2 / (hist_ms * 1e-3) / 1e9,
-            "mlp_bits": float(rm.bits.sum().item()), "hist_bits": float(hb.sum().item()),
             "kernels_ms": times, "autotune": {"blocks_per_attr": blocks,
                                                "candidates": dict(zip((16, 32, 64, 128, 256), cand_ms or ()))},
             "entropy_models": entropy}
@@ -448,6 +521,58 @@ def bench_train(torch, dev, steps, n=1_000_000, views=8):
             "l1": float(tr.loss.item())}
 
 
+def bench_rate_judge(torch, dev, steps=300, n=1_000_000, views=8, lambdas=(0.0, 1e-4, 1e-3, 1e-2)):
+    """The learned rate judged at the rate-model scale: a 1M-Gaussian student fitted to renders of
+    a 1M-Gaussian teacher (seed 15) at 960x540 x 8 ring views, `steps` joint training steps per
+    rate weight, then on the final attributes (symbols rint(y/q)) the learned rate in evaluation
+    mode against the empirical histogram (the judge, within 2 %), and the paper's own entropy
+    models (KDE for keyframe attributes, Gaussian for residuals) beside it."""
+    import numpy as np
+
+    import synth
+    from paper_2509_17513_amd import RenderSettings, render_forward
+    from paper_2509_17513_amd.train import JointTrainer, RateModel
+    idx = list(range(0, 24, 24 // views))
+    cams = torch.from_numpy(synth.ring_cameras(idx, 24, 4.0, 960, 540)).to(dev)
+    teacher = torch.from_numpy(synth.cube_scene(n, 15, 3)).to(dev)
+    timg, _ = render_forward(RenderSettings(960, 540, 3, (n,), (1.0,)), teacher, cams)
+    targets = timg[0, :, 0].contiguous()
+    del teacher, timg
+    p0 = torch.from_numpy(significance_sorted(torch, dev, synth.cube_scene(n, 5, 3))).to(dev)
+    lv = synth.nested_levels(n)
+    st = RenderSettings(960, 540, 3, tuple(lv), tuple(synth.paper_level_weights(6)))
+    runs = []
+    for lam in lambdas:
+        p = p0.clone()
+        tr = JointTrainer(p, cams, targets, st, RateModel(56, dev, seed=5, attrs=p[3:59]), lambda_rate=lam,
+                          extent=1.0, seed=5)
+        t0 = time.perf_counter()
+        l1 = []
+        for t in range(steps):
+            tr.step()
+            if t == 0 or t == steps - 1:
+                l1.append(float(tr.loss.item()))
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        b = tr.eval_models()
+        R = {k: float(np.sum(v)) for k, v in b.items()}
+        err = {k: (R[k] - R["hist"]) / R["hist"] for k in ("mlp", "kde", "gaussian")}
+        runs.append({"lambda_rate": lam, "l1_first": l1[0], "l1_last": l1[-1], "ms_per_step": ms,
+                     "bits": R, "bits_per_gaussian_hist": R["hist"] / n, "vs_hist": err,
+                     "mlp_within_2pct": abs(err["mlp"]) <= 0.02,
+                     "closest_to_hist": min(err, key=lambda k: abs(err[k]))})
+        log(f"[bench] judge lambda_rate={lam}: L1 {l1[0]:.4f} -> {l1[-1]:.4f}, bits/Gaussian {R['hist'] / n:.2f}, "
+            f"vs hist mlp {err['mlp']:+.4f} kde {err['kde']:+.4f} gaussian {err['gaussian']:+.4f}")
+        del tr, p
+        torch.cuda.empty_cache()
+    base = runs[0]
+    for r in runs[1:]:
+        r["hist_bits_vs_lambda0"] = r["bits"]["hist"] / base["bits"]["hist"] - 1
+        r["l1_vs_lambda0"] = r["l1_last"] / base["l1_last"] - 1
+    return {"workload": f"judge_{n}x56_{views}v_960x540_L6", "steps": steps, "runs": runs,
+            "judge": "eval-mode (rint) learned bits within 2 % of the empirical-histogram bits"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,6 +585,8 @@ def main():
     ap.add_argument("--views", type=int, default=24)
     ap.add_argument("--no-rate", action="store_true", help="skip the learned-rate measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the group and training-step measurements")
+    ap.add_argument("--no-judge", action="store_true", help="skip the learned-rate judge (trains 4 x judge-steps)")
+    ap.add_argument("--judge-steps", type=int, default=300)
     ap.add_argument("--no-dssim", action="store_true", help="skip the D-SSIM colour-loss measurement")
     ap.add_argument("--no-motion", action="store_true", help="skip the rigid-motion module measurement")
     ap.add_argument("--no-bitstream", action="store_true",
@@ -784,6 +911,10 @@ def main():
         out["group"] = bench_group(torch, dev, args.steps)
         torch.cuda.empty_cache()
         out["train"] = bench_train(torch, dev, args.steps)
+        if not args.no_judge:
+            log("[bench] learned-rate judge at 1M Gaussians")
+            torch.cuda.empty_cache()
+            out["rate_judge"] = bench_rate_judge(torch, dev, args.judge_steps)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -793,8 +924,8 @@ def main():
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(w)
+        log("[bench] CPU oracle baselines")
+        out["cpu_baseline"], out["cpu_baselines"] = cpu_baselines(w)
     print(json.dumps(out), flush=True)
 
 

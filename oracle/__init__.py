@@ -56,6 +56,8 @@ def lib():
         L.oc_render.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int,
                                 ctypes.c_int64, P, P, P, P, P, P, P]
         L.oc_backward.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P, P, P]
+        L.oc_backward_abs.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P, P]
+        L.oc_backward_abs.restype = ctypes.c_int
         L.oc_fd.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, ctypes.c_double, P, P, P]
         L.oc_fd.restype = ctypes.c_int
         L.oc_set_threads.argtypes = [ctypes.c_int]
@@ -190,6 +192,26 @@ def backward(st: Settings, params, cams, d_image, n_frames=1, residuals=None, mo
                            _ptr(d_image), _ptr(dp), _ptr(dr), _ptr(g2))
     assert rc == 0
     return dp, dr, g2
+
+
+def backward_abs(st: Settings, params, cams, d_image, mode="bucket"):
+    """(d_params, d_params_abs) for one frame without residuals: the analytic gradient of
+    sum(d_image * image) and the same sums taken of the absolute values of their terms (per-pixel
+    terms, then the projection Jacobian), the scale of the float32 rounding error of a gradient
+    whose terms cancel."""
+    params, cams = _f32(params), _f32(cams)
+    n = params.shape[1]
+    V = cams.shape[0]
+    s = st.c_struct(n)
+    d_image = np.ascontiguousarray(d_image, dtype=np.float64)
+    assert d_image.size == V * s.n_levels * 3 * st.width * st.height
+    C = params.shape[0]
+    dp = np.zeros((C, n), np.float64)
+    da = np.zeros((C, n), np.float64)
+    m = {"bucket": 0, "brute": 1}[mode]
+    rc = lib().oc_backward_abs(ctypes.byref(s), n, _ptr(params), V, _ptr(cams), m, _ptr(d_image), _ptr(dp), _ptr(da))
+    assert rc == 0
+    return dp, da
 
 
 def finite_differences(st: Settings, params, cams, d_image, gauss, chan, h=1e-5):

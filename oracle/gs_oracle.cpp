@@ -823,18 +823,19 @@ int oc_render(const oc_settings* s, int n, const float* params, int F, const flo
   return 0;
 }
 
-// Analytic FP64 backward (O7) of  L = sum d_image * image  over all
-// frame-views, levels, channels and pixels.
-//   d_image  [B][L][3][H][W]
-//   d_params [C][n]             (overwritten)
-//   d_res    [F][R][n]          (overwritten; may be NULL)
-//   grad2d   [B][n][9]          (overwritten; may be NULL): dL / (mx, my, A, B, C, o, r, g, b)
-// Pixel-level compositing gradients come from Eq. 2 written out; the
-// projection Jacobian comes from dual numbers through the projection code.
-int oc_backward(const oc_settings* s, int n, const float* params, int F, const float* res, int V, const float* cams,
-                int mode, const double* d_image, double* d_params, double* d_res, double* grad2d_out) {
+}  // extern "C"
+
+namespace {
+
+// The analytic FP64 backward (O7). Pixel-level compositing gradients come from
+// Eq. 2 written out; the projection Jacobian comes from dual numbers through the
+// projection code. d_params_abs (or NULL) receives the absolute-term sums.
+int backward_impl(const oc_settings* s, int n, const float* params, int F, const float* res, int V,
+                  const float* cams, int mode, const double* d_image, double* d_params, double* d_res,
+                  double* grad2d_out, double* d_params_abs) {
   Scene sc;
   if (!load_scene(sc, s, n, params, F, res, V, cams)) return -1;
+  if (d_params_abs && (F != 1 || sc.s.res_channels > 0)) return -1;
   const oc_settings& S = sc.s;
   const int C = n_channels(S.sh_degree);
   const int L = S.n_levels;
@@ -846,7 +847,7 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
 #endif
   // dL / d(composed params of frame f) for every Gaussian
   std::vector<double> dcomp((size_t)F * n * C, 0.0);
-  std::vector<double> g2((size_t)n * 9);
+  std::vector<double> dabs(d_params_abs ? (size_t)n * C : 0, 0.0);
   for (int b = 0; b < B; ++b) {
     const int f = b / V;
     std::vector<Rec> recs = project_view(sc, b);
@@ -855,6 +856,7 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
     std::vector<int> all;
     if (mode == 1) { all.resize(recs.size()); for (size_t j = 0; j < recs.size(); ++j) all[j] = (int)j; }
     std::vector<std::vector<double>> part(nt, std::vector<double>(recs.size() * 9, 0.0));
+    std::vector<std::vector<double>> part_abs(d_params_abs ? nt : 0, std::vector<double>(recs.size() * 9, 0.0));
 #pragma omp parallel
     {
       int tid = 0;
@@ -862,6 +864,7 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
       tid = omp_get_thread_num();
 #endif
       std::vector<double>& acc = part[tid];
+      double* accabs = d_params_abs ? part_abs[tid].data() : nullptr;
       std::vector<Kept> kept;
       std::vector<int> contrib;
 #pragma omp for schedule(dynamic, 64)
@@ -901,12 +904,16 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
             const Rec& r = recs[e.rec];
             const double a = std::min(S.alpha_max, e.araw);
             double* g = acc.data() + (size_t)e.rec * 9;
-            double dLda = 0.0;
+            double dLda = 0.0, dLda_abs = 0.0;
             for (int c = 0; c < 3; ++c) {
               g[6 + c] += w[c] * a * Tb[j];                               // dC/dc_i = alpha_i T_i
               dLda += w[c] * (r.rgb[c] * Tb[j] - Sfx[c] / (1.0 - a));    // dC/dalpha_i
+              dLda_abs += std::fabs(w[c]) * (std::fabs(r.rgb[c]) * Tb[j] + std::fabs(Sfx[c]) / (1.0 - a));
               Sfx[c] += r.rgb[c] * a * Tb[j];
             }
+            double* ga = accabs ? accabs + (size_t)e.rec * 9 : nullptr;
+            if (ga)
+              for (int c = 0; c < 3; ++c) ga[6 + c] += std::fabs(w[c]) * a * Tb[j];
             if (e.araw > S.alpha_max) continue;  // clamped: alpha does not depend on o, G
             g[5] += dLda * e.G;                    // d alpha / d o
             const double dpow = dLda * e.araw;    // d alpha / d power = o G
@@ -916,14 +923,25 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
             g[2] += dpow * (-0.5 * dx * dx);
             g[3] += dpow * (-dx * dy);
             g[4] += dpow * (-0.5 * dy * dy);
+            if (ga) {  // the same sums of the absolute values of their terms
+              const double pa = dLda_abs * e.araw;
+              ga[5] += dLda_abs * e.G;
+              ga[0] += pa * (std::fabs(r.A * dx) + std::fabs(r.B * dy));
+              ga[1] += pa * (std::fabs(r.B * dx) + std::fabs(r.C * dy));
+              ga[2] += pa * 0.5 * dx * dx;
+              ga[3] += pa * std::fabs(dx * dy);
+              ga[4] += pa * 0.5 * dy * dy;
+            }
           }
         }
       }
     }
     // reduce thread partials
-    std::vector<double> gsum(recs.size() * 9, 0.0);
+    std::vector<double> gsum(recs.size() * 9, 0.0), gabs(d_params_abs ? recs.size() * 9 : 0, 0.0);
     for (int t = 0; t < nt; ++t)
       for (size_t j = 0; j < gsum.size(); ++j) gsum[j] += part[t][j];
+    for (size_t t = 0; t < part_abs.size(); ++t)
+      for (size_t j = 0; j < gabs.size(); ++j) gabs[j] += part_abs[t][j];
     if (grad2d_out) {
       double* go = grad2d_out + (size_t)b * n * 9;
       std::memset(go, 0, sizeof(double) * n * 9);
@@ -951,6 +969,12 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
         double v = 0.0;
         for (int m = 0; m < 9; ++m) v += g[m] * outs[m]->d[c];
         dc[c] += v;  // each (f, i) is written by one thread per view
+      }
+      if (d_params_abs) {
+        const double* ga = gabs.data() + (size_t)j * 9;
+        double* da = dabs.data() + (size_t)i * C;
+        for (int c = 0; c < C; ++c)
+          for (int m = 0; m < 9; ++m) da[c] += ga[m] * std::fabs(outs[m]->d[c]);
       }
     }
   }
@@ -1010,7 +1034,35 @@ int oc_backward(const oc_settings* s, int n, const float* params, int F, const f
     // sum over frames; the quaternion receives the chain-rule carry.
     for (int c = 0; c < 4; ++c) d_params[(size_t)(6 + c) * n + i] = carry_q[c];
   }
+  if (d_params_abs)
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < C; ++c) d_params_abs[(size_t)c * n + i] = dabs[(size_t)i * C + c];
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Analytic FP64 backward (O7) of  L = sum d_image * image  over all
+// frame-views, levels, channels and pixels.
+//   d_image  [B][L][3][H][W]
+//   d_params [C][n]             (overwritten)
+//   d_res    [F][R][n]          (overwritten; may be NULL)
+//   grad2d   [B][n][9]          (overwritten; may be NULL): dL / (mx, my, A, B, C, o, r, g, b)
+int oc_backward(const oc_settings* s, int n, const float* params, int F, const float* res, int V, const float* cams,
+                int mode, const double* d_image, double* d_params, double* d_res, double* grad2d_out) {
+  return backward_impl(s, n, params, F, res, V, cams, mode, d_image, d_params, d_res, grad2d_out, nullptr);
+}
+
+// The same sums over pixels and views as oc_backward's d_params (one frame, no
+// residuals), taken of the absolute values of their terms: the scale against
+// which the float32 rounding error of a gradient is bounded where its terms
+// cancel.
+int oc_backward_abs(const oc_settings* s, int n, const float* params, int V, const float* cams, int mode,
+                    const double* d_image, double* d_params, double* d_params_abs) {
+  if (!d_params_abs) return -1;
+  return backward_impl(s, n, params, 1, nullptr, V, cams, mode, d_image, d_params, nullptr, nullptr, d_params_abs);
 }
 
 // Central finite differences (O8) of  L = sum d_image * image  (one frame,

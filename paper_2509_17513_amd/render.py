@@ -66,15 +66,19 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def _check_tensor(t, name, shape=None, dtype=torch.float32, device=None):
+def _check_tensor(t, name, shape=None, dtype=torch.float32, device=None, min_numel=None):
+    """Raises ValueError unless t is None or a contiguous CUDA tensor of this dtype, device and
+    shape (the shape is checked first: the C ABI cannot see a tensor's extent)."""
     if t is None:
         return
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name} needs at least {min_numel} elements")
     if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
     if device is not None and t.device != device:
         raise ValueError(f"{name} is on {t.device}, expected {device}")
-    if shape is not None and tuple(t.shape) != tuple(shape):
-        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
 class Workspace:
@@ -184,15 +188,30 @@ def render_backward(settings: RenderSettings, params: torch.Tensor, cams: torch.
                     loss: torch.Tensor | None = None):
     """Accumulates into d_params [C][n] (and d_residuals); returns (d_params, d_residuals)."""
     dev = params.device
+    C = 11 + 3 * (settings.sh_degree + 1) ** 2
+    if params.dim() != 2 or params.shape[0] != C:
+        raise ValueError(f"params must be [{C}][n]")
     n = params.shape[1]
+    if cams.dim() != 2 or cams.shape[1] != 16 or cams.shape[0] % n_frames:
+        raise ValueError("cams must be [n_frames * n_views][16]")
     V = cams.shape[0] // n_frames
+    H, W, L = settings.height, settings.width, settings.n_levels
+    img_shape = (n_frames, V, L, 3, H, W)
+    checks = ((d_image, "d_image", img_shape, None), (image, "image", img_shape, None),
+              (target, "target", (n_frames * V, 3, H, W), None), (d_params, "d_params", (C, n), None),
+              (residuals, "residuals", (n_frames, settings.res_channels, n), None),
+              (d_residuals, "d_residuals", (n_frames, settings.res_channels, n), None), (loss, "loss", None, 1))
+    for t, nm, shp, mn in checks:  # every extent first, then dtype, layout and device
+        if t is not None and shp is not None and tuple(t.shape) != tuple(shp):
+            raise ValueError(f"{nm} has shape {tuple(t.shape)}, expected {tuple(shp)}")
+        if t is not None and mn is not None and t.numel() < mn:
+            raise ValueError(f"{nm} needs at least {mn} elements")
+    for t, nm, shp, mn in checks:
+        _check_tensor(t, nm, shp, device=dev, min_numel=mn)
     if d_params is None:
         d_params = torch.zeros_like(params)
     if residuals is not None and d_residuals is None:
         d_residuals = torch.zeros_like(residuals)
-    for t, nm in ((d_image, "d_image"), (target, "target"), (image, "image"), (d_params, "d_params"),
-                  (d_residuals, "d_residuals"), (loss, "loss")):
-        _check_tensor(t, nm, device=dev)
     s = settings.c_struct(n)
     check(lib().gs_render_backward(ctypes.byref(s), n, _ptr(params), n_frames, _ptr(residuals), V, _ptr(cams),
                                    _ptr(image), _ptr(d_image), _ptr(target), _ptr(d_params), _ptr(d_residuals),

@@ -196,8 +196,13 @@ class JointTrainer:
 
     def __init__(self, params: torch.Tensor, cams: torch.Tensor, targets: torch.Tensor, settings: RenderSettings,
                  rate: RateModel | None, lambda_rate: float = 0.0, extent: float = 1.0,
-                 lrs: LearningRates | None = None, seed: int = 0, lambda_ssim: float = 0.0, kde_rate: bool = False):
+                 lrs: LearningRates | None = None, seed: int = 0, lambda_ssim: float = 0.0, kde_rate: bool = False,
+                 check_every: int = 1):
         self.p, self.cams, self.tgt, self.st = params, cams, targets, settings
+        # the pair-list status is read after the forward every check_every steps: an overflow grows
+        # the workspace and redoes the forward before any gradient is taken (1 = every step; with
+        # more, a step between two checks may compute its colour gradient from a stale image)
+        self.check_every = max(1, int(check_every))
         self.n = params.shape[1]
         self.rate, self.lam, self.extent = rate, lambda_rate, extent
         self.lrs = lrs or LearningRates()
@@ -221,9 +226,11 @@ class JointTrainer:
             self.d_img = torch.empty_like(self.img)
             self.loss_ws = LossWorkspace(settings, cams.shape[0], params.device)
 
-    def step(self, check_overflow: bool = False):
+    def step(self, check_overflow: bool | None = None):
         n = self.n
         zero(self.loss)
+        if check_overflow is None:
+            check_overflow = self.t % self.check_every == 0
         render_forward(self.st, self.p, self.cams, ws=self.ws, image=self.img, check_overflow=check_overflow)
         if self.lambda_ssim > 0:
             color_loss(self.st, self.img, self.tgt, self.lambda_ssim, d_image=self.d_img, loss=self.loss,
@@ -261,6 +268,21 @@ class JointTrainer:
         torch.cuda.synchronize()
         return hb.cpu().numpy()
 
+    def eval_models(self):
+        """Bits per attribute (float64 numpy) of the current attributes, symbols rint(y/q): the
+        learned rate in evaluation mode, the empirical histogram (the judge), and the paper's own
+        entropy models in evaluation mode (Sec. 3.3: the KDE of keyframe attributes and the Gaussian
+        of residual attributes, each fitted per layer)."""
+        from .entropy import GAUSSIAN, KDE, EntropyModel
+        mlp, hist = self.eval_rate()
+        A = self.p.shape[0] - 3
+        out = {"mlp": mlp, "hist": hist}
+        for name, kind in (("kde", KDE), ("gaussian", GAUSSIAN)):
+            em = EntropyModel(A, self.n, kind, self.p.device, 1.0 / 64, self.levels, self.level_w, 1.0)
+            out[name] = em.run(self.p[3:3 + A], 0).cpu().numpy()
+            del em
+        return out
+
     def eval_rate(self):
         """(MLP bits per attribute in evaluation mode, histogram bits per attribute), float64 numpy."""
         n = self.n
@@ -287,7 +309,7 @@ class RigidTrainer:
 
     def __init__(self, keyframe: torch.Tensor, cams: torch.Tensor, targets: torch.Tensor, settings: RenderSettings,
                  box_lo, box_hi, table: torch.Tensor, weights: torch.Tensor, lr_table: float = 1e-2,
-                 lr_mlp: float = 1e-3):
+                 lr_mlp: float = 1e-3, check_every: int = 1):
         from .motion import MotionModule
         dev = keyframe.device
         self.p, self.cams, self.tgt = keyframe, cams, targets
@@ -303,11 +325,14 @@ class RigidTrainer:
         self.mm = MotionModule(self.n, box_lo, box_hi, dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.t = 0
+        self.check_every = max(1, int(check_every))  # pair-list status cadence, as in JointTrainer
         self.mm.forward(self.p, self.table, self.weights, self.res[0])
         self.img, self.ws = render_forward(self.st, self.p, cams, 1, self.res)  # sizes the workspace
 
-    def step(self, check_overflow: bool = False):
+    def step(self, check_overflow: bool | None = None):
         zero(self.loss)
+        if check_overflow is None:
+            check_overflow = self.t % self.check_every == 0
         self.mm.forward(self.p, self.table, self.weights, self.res[0])
         render_forward(self.st, self.p, self.cams, 1, self.res, ws=self.ws, image=self.img,
                        check_overflow=check_overflow)
@@ -339,7 +364,7 @@ class ResidualTrainer:
 
     def __init__(self, keyframe: torch.Tensor, residuals: torch.Tensor, cams: torch.Tensor, targets: torch.Tensor,
                  settings: RenderSettings, lambda_rate: float = 1e-4, lambda_reg: float = 1e-3, lr: float = 1e-3,
-                 seed: int = 0):
+                 seed: int = 0, check_every: int = 1):
         from .entropy import GAUSSIAN, EntropyModel
         dev = keyframe.device
         C, n = keyframe.shape
@@ -358,11 +383,14 @@ class ResidualTrainer:
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.rate_loss = torch.zeros(1, dtype=torch.float64, device=dev)
         self.t = 0
+        self.check_every = max(1, int(check_every))  # pair-list status cadence, as in JointTrainer
         self.img, self.ws = render_forward(self.st, keyframe, cams, 1, residuals)  # sizes the workspace
 
-    def step(self, check_overflow: bool = False):
+    def step(self, check_overflow: bool | None = None):
         zero(self.loss)
         zero(self.rate_loss)
+        if check_overflow is None:
+            check_overflow = self.t % self.check_every == 0
         render_forward(self.st, self.p, self.cams, 1, self.res, ws=self.ws, image=self.img,
                        check_overflow=check_overflow)
         zero(self.d_res)

@@ -187,3 +187,33 @@ def test_work_counter_switch_is_host_only_and_returns_previous(L):
         assert L.gs_set_work_counters(0) == 1
     finally:
         L.gs_set_work_counters(prev)
+
+
+def test_render_backward_checks_every_shape_on_the_host():
+    """The C ABI cannot see a tensor's extent, so the binding checks the shape of every buffer
+    render_backward passes: a d_image shaped like the target, a narrower d_params or a wrong
+    residual block would be read or written out of bounds by the kernels."""
+    import torch
+
+    from paper_2509_17513_amd import RenderSettings, render_backward
+    n, W, H, L, V = 50, 32, 24, 3, 2
+    st = RenderSettings(W, H, 0, (10, 30, 50), (0.5, 0.25, 1.0))
+    p = torch.zeros((14, n))
+    cams = torch.zeros((V, 16))
+    good_img = torch.zeros((1, V, L, 3, H, W))
+    cases = [
+        dict(image=good_img, d_image=torch.zeros((V, 3, H, W))),                  # d_image shaped like the target
+        dict(image=torch.zeros((1, V, 1, 3, H, W)), target=torch.zeros((V, 3, H, W))),  # image with one layer
+        dict(image=good_img, target=torch.zeros((1, 3, H, W))),                    # target of one view
+        dict(image=good_img, target=torch.zeros((V, 3, H, W)), d_params=torch.zeros((14, n - 1))),
+        dict(image=good_img, target=torch.zeros((V, 3, H, W)), loss=torch.zeros(0)),
+    ]
+    for kw in cases:
+        with pytest.raises(ValueError, match="shape|elements"):
+            render_backward(st, p, cams, None, **kw)
+    st8 = RenderSettings(W, H, 0, (10, 30, 50), (0.5, 0.25, 1.0), res_channels=8)
+    with pytest.raises(ValueError, match="shape"):
+        render_backward(st8, p, cams, None, 1, torch.zeros((1, 8, n)), image=good_img,
+                        target=torch.zeros((V, 3, H, W)), d_residuals=torch.zeros((1, 7, n)))
+    with pytest.raises(ValueError, match=r"params must be"):
+        render_backward(st, torch.zeros((13, n)), cams, None, image=good_img, target=torch.zeros((V, 3, H, W)))

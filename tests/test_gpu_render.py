@@ -243,29 +243,33 @@ def test_degenerate_and_extreme_gaussians_match_oracle():
     assert bad == 0
     assert amb <= 0.02 * ref["nvar"].size  # the comparison is not vacuous
     dimg = l1_dimage(ref, w.target, w.level_weights)
-    dp_ref, _, _ = oracle.backward(ost, w.params, w.cams, dimg)
+    dp_ref, dp_abs = oracle.backward_abs(ost, w.params, w.cams, dimg)
     d_image = torch.from_numpy(dimg.astype(np.float32).reshape(img.shape)).to(p.device)
     dp, _ = render_backward(st, p, c, ws, image=img, d_image=d_image)
     torch.cuda.synchronize()
     got = dp.cpu().numpy().astype(np.float64)
     assert np.abs(dp_ref).max() > 0
     assert np.all(got[:, 1:7] == 0.0)  # culled Gaussians get no gradient
-    # the 100:1 needles (13..15) are held to a looser bar: their exponent is a small difference of
-    # large terms far along the axis, and its FP32 rounding grows with the aspect ratio (measured:
-    # rotation-gradient error ~1e-5 relative at 4:1, ~1e-4 at 10:1, ~2e-3 at 40:1, ~1.6e-2 at 100:1)
-    needles = np.zeros(got.shape[1], bool)
-    needles[13:16] = True
-    bad, worst = grad_mismatch(got, dp_ref, param_groups(0))
-    for lo, hi in param_groups(0):  # name the values outside the standard bar
-        r = dp_ref[lo:hi]
+    # The 100:1 needles (13..15): their rotation gradient is a sum of terms up to 1e5 times larger
+    # than itself (the conic gradient of an elongated footprint, taken back to its rotation). A
+    # float32 evaluation of such a sum is off by a few dozen roundings of its absolute terms, so
+    # every gradient is held to the standard bar plus 64 u times the sum of the absolute values of
+    # its terms (oracle.backward_abs), which for ordinary Gaussians is far below the 1e-3 bar.
+    u = 2.0 ** -24
+    groups = param_groups(0)
+    bad = 0
+    worst = 0.0
+    for lo, hi in groups:
+        r, x, ab = dp_ref[lo:hi], got[lo:hi], dp_abs[lo:hi]
         rms = np.sqrt(np.mean(r ** 2))
-        for ch, i in zip(*np.nonzero(np.abs(got[lo:hi] - r) > 1e-3 * np.abs(r) + 1e-3 * rms)):
-            print(f"  channel {lo + ch} Gaussian {i}: gpu {got[lo + ch, i]:.6g} oracle {r[ch, i]:.6g}")
-    b_other, w_other = grad_mismatch(got[:, ~needles], dp_ref[:, ~needles], param_groups(0))
-    print(f"grad bad={bad} of {dp.numel()} worst_ratio={worst:.3g}; without the needles bad={b_other} "
-          f"worst={w_other:.3g}")
-    assert b_other == 0
-    assert np.allclose(got[:, needles], dp_ref[:, needles], rtol=3e-2, atol=3e-2 * np.abs(dp_ref[:, needles]).max())
+        ratio = np.abs(x - r) / (1e-3 * np.abs(r) + 1e-3 * rms + 64 * u * ab + 1e-30)
+        bad += int((ratio > 1).sum())
+        worst = max(worst, float(ratio.max()))
+        for ch, i in zip(*np.nonzero(ratio > 0.25)):
+            print(f"  channel {lo + ch} Gaussian {i}: gpu {x[ch, i]:.6g} oracle {r[ch, i]:.6g} "
+                  f"|terms| {ab[ch, i]:.3g} ratio {ratio[ch, i]:.3g}")
+    print(f"grad bad={bad} of {dp.numel()} worst_ratio={worst:.3g}")
+    assert bad == 0
 
 
 def test_launch_shapes_give_identical_renders_and_autotune():

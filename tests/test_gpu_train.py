@@ -197,3 +197,19 @@ def test_residual_phase_fits_and_the_rate_terms_shrink_residuals():
     free, reg = out[(0.0, 0.0)], out[(1e-4, 1e-3)]
     assert free[0][-1] < 0.7 * free[0][0] and reg[0][-1] < 0.8 * reg[0][0]
     assert reg[1] < free[1]
+
+
+def test_trainer_grows_an_overflowing_pair_list_instead_of_training_on_a_stale_image():
+    print("\n[case] joint training started with a pair list far too small: the trainer grows it", flush=True)
+    tr = _setup(1e-3)
+    ref = _setup(1e-3)
+    tr.ws.allocate(4096)  # far fewer (tile, Gaussian) pairs than the scene needs
+    cap0 = tr.ws.pair_capacity
+    for _ in range(3):
+        tr.step()
+        ref.step()
+    losses = float(tr.loss.item()), float(ref.loss.item())
+    print(f"capacity {cap0} -> {tr.ws.pair_capacity}; loss {losses[0]:.6f} (vs {losses[1]:.6f} sized up front)",
+          flush=True)
+    assert tr.ws.pair_capacity > cap0
+    assert losses[0] > 0.1 and abs(losses[0] - losses[1]) <= 1e-4 * losses[1]

@@ -187,3 +187,20 @@ def test_footprint_local_fd_kinks_fall_back_to_one_sided_differences():
     # one-sided differences at a large step carry an O(h) error: compare loosely
     err = np.abs(fd - dp) / (np.abs(dp) + 1e-2 * scale)
     assert np.median(err[ok]) < 2e-2
+
+
+def test_absolute_term_sums_bound_the_gradient_and_match_its_value():
+    """backward_abs returns the analytic gradient unchanged and, beside it, the same sums taken of
+    the absolute values of their terms, which bound it (|sum| <= sum |terms|) and equal it where
+    no term can be negative (a one-pixel red weight on a single Gaussian's colour: dC/df_dc)."""
+    p, cams = _tiny(41, n=9, deg=1)
+    st = oracle.Settings(24, 20, 1, (9,), dilation=0.3)
+    w = np.random.default_rng(42).standard_normal((2, 1, 3, 20, 24))
+    dp, da = oracle.backward_abs(st, p, cams, w)
+    dp2, _, _ = oracle.backward(st, p, cams, w)
+    np.testing.assert_allclose(dp, dp2, rtol=1e-12, atol=1e-15)  # thread partial sums may add in another order
+    assert np.all(da >= np.abs(dp) * (1 - 1e-12))
+    w1 = np.zeros_like(w)
+    w1[0, 0, 0] = 1.0  # red channel of view 0, every pixel, positive
+    dp1, da1 = oracle.backward_abs(st, p, cams, w1)
+    np.testing.assert_allclose(da1[11], np.abs(dp1[11]), rtol=1e-12)  # dC_r / df_dc,r = alpha T Y00 >= 0
