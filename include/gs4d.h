@@ -421,6 +421,18 @@ int gs_rate_histogram_workspace_size(int32_t n_attr, size_t* bytes_out);
 int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* gs_rate_histogram for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same kernels and result,
+ * with the workspace in a fixed scratch array of the library (16.8 MB per GPU, held until the
+ * process ends) instead of a caller's buffer. The caller passes device attrs [n_attr][n] and
+ * bits_out [n_attr] float64 (overwritten). n_attr may be at most 64, else GS_ERR_INVALID_ARG;
+ * the symbol range rule of gs_rate_histogram applies. The call allocates nothing and does not
+ * synchronise. Every call on one GPU shares that GPU's scratch (it starts each call by clearing
+ * it): calls that overlap on one GPU, on different streams or threads, race. Returns
+ * GS_ERR_NO_DEVICE without a current device, GS_ERR_HIP on a launch error. */
+int gs_rate_histogram_noalloc(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out,
+                              void* stream);
+
 /* Adam step on float32 masters (bias-corrected, t = step >= 1); grads are
  * zeroed after use; bf16_copy (or NULL) receives the BF16 rounding of the
  * updated parameters (the MFMA copy of the MLP weights). */

@@ -112,6 +112,7 @@ SIGNATURES = {
     "gs_rate_init_output_bias": ([I32, I32, P, ctypes.c_float, P, P, P], ctypes.c_int),
     "gs_peak_fma": ([I32, I32, ctypes.c_float, ctypes.c_float, P, P], ctypes.c_int),
     "gs_peak_copy": ([P, P, SZ, P], ctypes.c_int),
+    "gs_rate_histogram_noalloc": ([I32, I32, P, ctypes.c_float, P, P], ctypes.c_int),
     "gs_rate_context": ([I32, P, ctypes.c_float, I32, P, P, P], ctypes.c_int),
     "gs_adam_step": ([I64, P, P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                       I32, P], ctypes.c_int),

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include <stdint.h>
@@ -640,6 +641,39 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
 
 using namespace gs;
 
+// ------------------------------------------------ histogram without allocation
+// Scratch for gs_rate_histogram_noalloc: the same layout as the workspace of
+// gs_rate_histogram for up to kNoAllocMaxAttr attributes. Each GPU the library
+// runs on holds its own copy until the process ends. Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in): it uses
+// the device address hipGetSymbolAddress returns, looked up once per device
+// with that device current and kept in g_noalloc_ptr.
+constexpr int kNoAllocMaxAttr = 64;
+constexpr size_t kNoAllocBytes = 256 + (size_t)kNoAllocMaxAttr * 8 + (size_t)kNoAllocMaxAttr * kHistBins * 4;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch, set up on the first call on the device.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return GS_ERR_NO_DEVICE;
+  if (dev >= kMaxDevices) return GS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GS_ERR_HIP;
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = g_noalloc_ptr[dev];
+  return GS_OK;
+}
+}  // namespace
+
 namespace {
 
 // The histogram rate on a workspace w laid out as gs_rate_histogram_workspace_size states:
@@ -702,6 +736,17 @@ int gs_rate_histogram(int32_t n, int32_t n_attr, const float* attrs, float step,
   gs_rate_histogram_workspace_size(n_attr, &need);
   if (ws_bytes < need) return GS_ERR_WORKSPACE;
   return hist_launch(n, n_attr, attrs, step, bits_out, (char*)ws, (hipStream_t)stream);
+}
+
+
+int gs_rate_histogram_noalloc(int32_t n, int32_t n_attr, const float* attrs, float step, double* bits_out,
+                              void* stream) {
+  if (n < 0 || n_attr < 1 || !attrs || !bits_out || !(step > 0.f)) return GS_ERR_INVALID_ARG;
+  if (n_attr > kNoAllocMaxAttr) return GS_ERR_INVALID_ARG;
+  void* w = nullptr;
+  const int rc = noalloc_scratch(&w);
+  if (rc != GS_OK) return rc;
+  return hist_launch(n, n_attr, attrs, step, bits_out, (char*)w, (hipStream_t)stream);
 }
 
 
