@@ -517,8 +517,28 @@ def bench_train(torch, dev, steps, n=1_000_000, views=8):
         tr.step()
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / steps
+    # the same step captured (forward graph, status check, rest-of-step graph) and replayed
+    tr.capture()
+    tr.step_graph()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step_graph()
+    torch.cuda.synchronize()
+    ms_graph = 1e3 * (time.perf_counter() - t0) / steps
+    tr.check_every = 1 << 30  # no status read between the two graphs
+    tr.step_graph()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step_graph()
+    torch.cuda.synchronize()
+    ms_graph_nocheck = 1e3 * (time.perf_counter() - t0) / steps
     return {"workload": f"train_{n}_{views}v_960x540_L6_rate56", "ms_per_step": ms, "ms_per_view": ms / views,
-            "l1": float(tr.loss.item())}
+            "ms_per_step_captured": ms_graph, "ms_per_step_captured_unchecked": ms_graph_nocheck,
+            "l1": float(tr.loss.item()),
+            "timing": "eager steps with the pair-list status read after every forward; the captured step "
+                      "(two graphs) with and without that read"}
 
 
 def bench_rate_judge(torch, dev, steps=300, n=1_000_000, views=8, lambdas=(0.0, 1e-4, 1e-3, 1e-2)):
@@ -631,12 +651,14 @@ def main():
     if args.shapes:
         bc, rs, wl = (int(x) for x in args.shapes.split(","))
         st = dataclasses.replace(st, bin_chunk=bc, row_seg=rs, wave_layout=wl)
-        tune = {"bin_chunk": bc, "row_seg": rs, "wave_layout": wl, "trial_ms": None}
+        tune = {"bin_chunk": bc, "row_seg": rs, "wave_layout": wl, "lds_batch": st.lds_batch, "trial_ms": None}
     if not args.no_autotune:
-        from paper_2509_17513_amd import autotune
-        st, tune_ms = autotune(st, p, c, ws, image=img)
+        from paper_2509_17513_amd import autotune_cached
+        from paper_2509_17513_amd.render import tune_cache_path
+        st, tune_ms, hit = autotune_cached(st, p, c, ws, image=img)
         tune = {"bin_chunk": st.bin_chunk, "row_seg": st.row_seg, "wave_layout": st.wave_layout,
-                "trial_ms": tune_ms}
+                "lds_batch": st.lds_batch, "bwd_pixels": st.bwd_pixels, "trial_ms": tune_ms, "from_cache": hit,
+                "cache": tune_cache_path()}
         log(f"[bench] autotuned launch shapes {tune}")
 
     def step():
@@ -847,7 +869,8 @@ def main():
         for li, nl in enumerate(w.level_counts):
             pl = p[:, :nl].contiguous()
             stl = RenderSettings(w.width, w.height, w.sh_degree, (nl,), (w.level_weights[li],),
-                                 bin_chunk=st.bin_chunk, row_seg=st.row_seg, wave_layout=st.wave_layout)
+                                 bin_chunk=st.bin_chunk, row_seg=st.row_seg, wave_layout=st.wave_layout,
+                                 lds_batch=st.lds_batch, bwd_pixels=st.bwd_pixels)
             imgl, wsl = render_forward(stl, pl, c[0:1].contiguous(),
                                        ws=Workspace(stl, nl, 1, 1, dev, pair_capacity=60 * nl))
             for v in range(B):  # size each layer's workspace for its worst view
@@ -882,7 +905,8 @@ def main():
         # intermediate: one launch sequence per view with the six layers batched (separates the
         # gain of batching the layers from that of batching the views)
         st1 = RenderSettings(w.width, w.height, w.sh_degree, tuple(w.level_counts), tuple(w.level_weights),
-                             bin_chunk=st.bin_chunk, row_seg=st.row_seg, wave_layout=st.wave_layout)
+                             bin_chunk=st.bin_chunk, row_seg=st.row_seg, wave_layout=st.wave_layout,
+                             lds_batch=st.lds_batch, bwd_pixels=st.bwd_pixels)
         img1, ws1 = render_forward(st1, p, cams1[0], ws=Workspace(st1, w.n, 1, 1, dev, pair_capacity=60 * w.n))
         for v in range(B):
             render_forward(st1, p, cams1[v], ws=ws1, image=img1)

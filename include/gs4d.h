@@ -83,6 +83,10 @@ typedef struct {
  *    row_seg     row-list entries per tile-binning wave: 0 (= 2048), 1024, 2048, 4096
  *    wave_layout pixels of the four waves of a 16 x 16 tile: 0 or 1 = 8 x 8 quadrants,
  *                2 = 16 x 4 strips
+ *    lds_batch   list entries the raster passes stage in LDS per round: 0 (= 256), 64, 128, 256
+ *    bwd_pixels  pixels per lane of the backward raster: 0 or 1 (a 256-thread block per 16 x 16
+ *                tile), 2 (a 128-thread block, two rows apart per lane); gradients agree up to
+ *                the order of float additions
  *                The workspace size does not depend on them. */
 typedef struct {
   int32_t width, height;
@@ -95,6 +99,8 @@ typedef struct {
   float bg[3];
   int32_t tile_w, tile_h;
   int32_t bin_chunk, row_seg, wave_layout;
+  int32_t lds_batch;
+  int32_t bwd_pixels;
 } gs_settings;
 
 /* Bytes of workspace needed for a render of n Gaussians, n_frames frames of
@@ -293,15 +299,16 @@ int gs_motion_backward(const gs_motion_desc* desc, const float* means, int32_t r
                        const float* weights, const float* d_out, float* d_table, float* d_weights, void* ws,
                        size_t ws_bytes, void* stream);
 
-/* Autotuner of the render launch shapes (bin_chunk, row_seg, wave_layout of gs_settings) for
- * one workload: the a10 step of the hot path, with shapes picked by timed trials that must pass
- * parity. Starting from *s, it tries the wave layouts, then the binning chunk sizes, then the
- * row-segment sizes, keeping the best of each before moving on (8 trials). A trial renders the
+/* Autotuner of the render launch shapes (bin_chunk, row_seg, wave_layout, lds_batch, bwd_pixels
+ * of gs_settings) for one workload: shapes picked by timed trials that must pass parity. Starting
+ * from *s, it tries the wave layouts, then the binning chunk sizes, then the row-segment sizes,
+ * then the LDS batch sizes, then the backward's pixels per lane, keeping the best of each before
+ * moving on (13 trials). A trial renders the
  * forward once, requires an image bit-identical to the first trial's (checksum on the device)
  * and no pair-list overflow, then times two forward + backward passes between HIP events on
  * `stream` (the backward takes the image itself as dL/dC and accumulates into the scratch
  * d_params [C][n] and d_residuals [F][R][n] or NULL). Synchronises the stream.
- * *best receives *s with the three fields set; times_ms[8] (or NULL) each trial's time per
+ * *best receives *s with the five fields set; times_ms[13] (or NULL) each trial's time per
  * forward + backward, or -1 for a rejected trial. Returns GS_ERR_PAIR_OVERFLOW if the workspace
  * is too small for the pairs (grow it first: render once and check gs_check_status), and the
  * errors of gs_render_forward otherwise. */
@@ -384,6 +391,9 @@ typedef struct {
   float fit_scale;
   int32_t blocks_per_attr; /* launch blocks per attribute; 0 = the library default (64, fewer when
                               n is small); gs_rate_autotune picks one for a given workload */
+  const uint64_t* offset_dev; /* device word holding the noise counter offset, read when the kernel
+                                 runs (then `offset` is ignored), or NULL: lets a captured graph
+                                 draw new noise on every replay (gs_advance_counters) */
 } gs_rate_desc;
 int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* ctx, const uint16_t* w_bf16,
                   const float* b_f32, double* bits_out, double* loss_out, float* sym_bits, float* d_attrs, float* d_w,
@@ -438,6 +448,14 @@ int gs_rate_histogram_noalloc(int32_t n, int32_t n_attr, const float* attrs, flo
  * updated parameters (the MFMA copy of the MLP weights). */
 int gs_adam_step(int64_t n, float* params, float* grads, float* m, float* v, uint16_t* bf16_copy, float lr,
                  float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* gs_adam_step with the step number read from the device word step_dev when the kernel runs,
+ * so that a captured training step replays with the right bias corrections; and the kernel that
+ * advances such counters (step_dev += 1, offset_dev += offset_delta; either may be NULL) at the
+ * end of a captured step. */
+int gs_adam_step_dev(int64_t n, float* params, float* grads, float* m, float* v, uint16_t* bf16_copy, float lr,
+                     float beta1, float beta2, float eps, const int32_t* step_dev, void* stream);
+int gs_advance_counters(int32_t* step_dev, uint64_t* offset_dev, uint64_t offset_delta, void* stream);
 
 /* Zero-fills bytes (a multiple of 4) of device memory with a kernel (no memset node, so it is
  * safe inside captured graphs). */

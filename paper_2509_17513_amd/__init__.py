@@ -5,8 +5,8 @@ The compute runs in the HIP library ``libgs4d.so`` behind the C ABI of
 package does not require a GPU; calling a render entry point does, and fails
 loudly if the library has not been built.
 """
-from .render import (LossWorkspace, RenderFunction, RenderSettings, Workspace, autotune, color_loss, render,
-                     render_backward, render_forward, work_counters)
+from .render import (LossWorkspace, RenderFunction, RenderSettings, Workspace, autotune, autotune_cached, color_loss,
+                     render, render_backward, render_forward, work_counters)
 
-__all__ = ["LossWorkspace", "RenderFunction", "RenderSettings", "Workspace", "autotune", "color_loss", "render",
-           "render_backward", "render_forward", "work_counters"]
+__all__ = ["LossWorkspace", "RenderFunction", "RenderSettings", "Workspace", "autotune", "autotune_cached", "color_loss",
+           "render", "render_backward", "render_forward", "work_counters"]

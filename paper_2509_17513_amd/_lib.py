@@ -24,6 +24,7 @@ class GsSettings(ctypes.Structure):
         ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_stop", ctypes.c_float),
         ("bg", ctypes.c_float * 3), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
         ("bin_chunk", ctypes.c_int32), ("row_seg", ctypes.c_int32), ("wave_layout", ctypes.c_int32),
+        ("lds_batch", ctypes.c_int32), ("bwd_pixels", ctypes.c_int32),
     ]
 
 
@@ -44,7 +45,7 @@ class GsRateDesc(ctypes.Structure):
         ("n", ctypes.c_int32), ("n_attr", ctypes.c_int32), ("step", ctypes.c_float), ("mode", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("offset", ctypes.c_uint64), ("n_levels", ctypes.c_int32),
         ("level_counts", ctypes.c_int32 * 8), ("level_weights", ctypes.c_float * 8), ("lambda_rate", ctypes.c_float),
-        ("fit_scale", ctypes.c_float), ("blocks_per_attr", ctypes.c_int32),
+        ("fit_scale", ctypes.c_float), ("blocks_per_attr", ctypes.c_int32), ("offset_dev", ctypes.c_void_p),
     ]
 
 
@@ -111,6 +112,9 @@ SIGNATURES = {
     "gs_rate_histogram": ([I32, I32, P, ctypes.c_float, P, P, SZ, P], ctypes.c_int),
     "gs_rate_init_output_bias": ([I32, I32, P, ctypes.c_float, P, P, P], ctypes.c_int),
     "gs_peak_fma": ([I32, I32, ctypes.c_float, ctypes.c_float, P, P], ctypes.c_int),
+    "gs_adam_step_dev": ([I64, P, P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P],
+                         ctypes.c_int),
+    "gs_advance_counters": ([P, P, ctypes.c_uint64, P], ctypes.c_int),
     "gs_peak_copy": ([P, P, SZ, P], ctypes.c_int),
     "gs_rate_histogram_noalloc": ([I32, I32, P, ctypes.c_float, P, P], ctypes.c_int),
     "gs_rate_context": ([I32, P, ctypes.c_float, I32, P, P, P], ctypes.c_int),

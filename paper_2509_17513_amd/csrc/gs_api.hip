@@ -109,6 +109,10 @@ int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap
   if (d.row_seg != 1024 && d.row_seg != 2048 && d.row_seg != 4096)
     return fail_arg("row_seg must be 0, 1024, 2048 or 4096");
   if (d.wave_layout != 1 && d.wave_layout != 2) return fail_arg("wave_layout must be 0, 1 or 2");
+  d.batch = s->lds_batch == 0 ? kTilePix : s->lds_batch;
+  if (d.batch != 64 && d.batch != 128 && d.batch != 256) return fail_arg("lds_batch must be 0, 64, 128 or 256");
+  d.bwd_pixels = s->bwd_pixels == 0 ? 1 : s->bwd_pixels;
+  if (d.bwd_pixels != 1 && d.bwd_pixels != 2) return fail_arg("bwd_pixels must be 0, 1 or 2");
   d.n_sort_chunks = (n + kSortChunk - 1) / kSortChunk;
   d.n_bin_chunks = (n + d.bin_chunk - 1) / d.bin_chunk;
   d.n_row_segs = (n + d.row_seg - 1) / d.row_seg;
@@ -425,6 +429,8 @@ int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int
   cur.bin_chunk = d.bin_chunk;
   cur.row_seg = d.row_seg;
   cur.wave_layout = d.wave_layout;
+  cur.lds_batch = d.batch;
+  cur.bwd_pixels = d.bwd_pixels;
   unsigned long long ref = 0;
   bool have_ref = false;
   // one trial: forward, parity check of the image against the first trial, then two timed
@@ -461,17 +467,24 @@ int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int
     *ms = 0.5f * el;
     return GS_OK;
   };
-  // greedy: the wave layout, then the binning chunk, then the row segment
-  static const int32_t kLayouts[2] = {1, 2}, kChunks[3] = {512, 1024, 2048}, kSegs[3] = {1024, 2048, 4096};
+  // greedy: the wave layout, then the binning chunk, then the row segment, then the LDS batch, then
+  // the backward's pixels per lane
+  static const int32_t kLayouts[2] = {1, 2}, kChunks[3] = {512, 1024, 2048}, kSegs[3] = {1024, 2048, 4096},
+                       kBatches[3] = {64, 128, 256}, kBwdPix[2] = {1, 2};
   int ti = 0;
-  for (int phase = 0; phase < 3 && rc == GS_OK; ++phase) {
-    const int32_t* vals = phase == 0 ? kLayouts : phase == 1 ? kChunks : kSegs;
-    const int nv = phase == 0 ? 2 : 3;
+  auto field = [](gs_settings& g, int phase) -> int32_t& {
+    return phase == 0 ? g.wave_layout : phase == 1 ? g.bin_chunk : phase == 2 ? g.row_seg
+                      : phase == 3 ? g.lds_batch : g.bwd_pixels;
+  };
+  for (int phase = 0; phase < 5 && rc == GS_OK; ++phase) {
+    const int32_t* vals = phase == 0 ? kLayouts : phase == 1 ? kChunks : phase == 2 ? kSegs
+                        : phase == 3 ? kBatches : kBwdPix;
+    const int nv = (phase == 0 || phase == 4) ? 2 : 3;
     float best_ms = -1.f;
-    int32_t best_v = phase == 0 ? cur.wave_layout : phase == 1 ? cur.bin_chunk : cur.row_seg;
+    int32_t best_v = field(cur, phase);
     for (int k = 0; k < nv && rc == GS_OK; ++k) {
       gs_settings t = cur;
-      (phase == 0 ? t.wave_layout : phase == 1 ? t.bin_chunk : t.row_seg) = vals[k];
+      field(t, phase) = vals[k];
       float ms = -1.f;
       rc = trial(t, &ms);
       if (times_ms) times_ms[ti] = ms;
@@ -481,7 +494,7 @@ int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int
         best_v = vals[k];
       }
     }
-    (phase == 0 ? cur.wave_layout : phase == 1 ? cur.bin_chunk : cur.row_seg) = best_v;
+    field(cur, phase) = best_v;
   }
   // clean-up of the timing events; the trials' own status is what this call reports
   (void)hipEventDestroy(e0);

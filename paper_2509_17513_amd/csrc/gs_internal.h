@@ -47,6 +47,8 @@ struct RenderDims {
   int n_sort_chunks, n_bin_chunks, n_row_segs;
   int bin_chunk, row_seg;             // launch shapes of the binning
   int wave_layout;                    // 1: 8x8 quadrant per wave, 2: 16x4 strip per wave
+  int batch;                          // list entries staged in LDS per round of the raster passes
+  int bwd_pixels;                     // pixels per lane of the backward raster: 1 or 2
   int n_bin_chunks_max, n_row_segs_max;  // at the smallest shapes (workspace sizing)
   unsigned long long capacity;      // (tile, Gaussian) pairs
   unsigned long long row_capacity;  // (tile row, Gaussian) pairs

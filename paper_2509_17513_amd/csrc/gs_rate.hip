@@ -202,6 +202,7 @@ struct RateArgs {
   int n, n_attr, mode, n_levels;
   float step;
   unsigned long long seed, offset;
+  const unsigned long long* offset_dev;  // if set, the counter offset is read here at run time
   int lv[8];
   float wsym[8];  // per-symbol loss weight of each layer: lambda_rate lambda^l / |G^l|
   float wfit;     // per-symbol weight of the maximum-likelihood fit of the MLP weights
@@ -437,7 +438,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       if (ra.mode == 0) {
         yh = rintf(y / q) * q;
       } else {
-        const unsigned long long ctr = ra.offset + (unsigned long long)a * (unsigned long long)n +
+        const unsigned long long off = ra.offset_dev ? *ra.offset_dev : ra.offset;
+        const unsigned long long ctr = off + (unsigned long long)a * (unsigned long long)n +
                                        (unsigned long long)sidx + 1ull;
         const unsigned long long zz = splitmix64(ra.seed + ctr * 0x9E3779B97F4A7C15ull);
         const float u = (float)(uint32_t)(zz >> 40) * (1.0f / 16777216.0f) - 0.5f;
@@ -622,7 +624,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p, float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v,
                                               uint16_t* __restrict__ bf16_copy, float lr, float b1, float b2,
-                                              float eps, float c1, float c2) {
+                                              float eps, float c1, float c2, const int* __restrict__ step_dev) {
+  if (step_dev) {  // the bias corrections of the step number held on the device
+    const float t = (float)*step_dev;
+    c1 = 1.f - powf(b1, t);
+    c2 = 1.f - powf(b2, t);
+  }
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
@@ -633,6 +640,14 @@ __global__ __launch_bounds__(256) void k_adam(long long n, float* __restrict__ p
     p[i] = pi;
     g[i] = 0.f;
     if (bf16_copy) bf16_copy[i] = f32_to_bf16(pi);
+  }
+}
+
+// Step number += 1 and noise counter offset += delta, on the device (for captured steps).
+__global__ void k_advance(int* __restrict__ step, unsigned long long* __restrict__ offset, unsigned long long delta) {
+  if (threadIdx.x == 0) {
+    if (step) *step += 1;
+    if (offset) *offset += delta;
   }
 }
 
@@ -773,7 +788,7 @@ int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* 
   if (d.n == 0) return GS_OK;
   RateArgs ra;
   ra.n = d.n; ra.n_attr = d.n_attr; ra.mode = d.mode; ra.n_levels = d.n_levels; ra.step = d.step;
-  ra.seed = d.seed; ra.offset = d.offset;
+  ra.seed = d.seed; ra.offset = d.offset; ra.offset_dev = (const unsigned long long*)d.offset_dev;
   ra.wfit = d.fit_scale;
   int prev = 0;
   for (int l = 0; l < 8; ++l) {
@@ -807,7 +822,26 @@ int gs_adam_step(int64_t n, float* params, float* grads, float* m, float* v, uin
   const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
   ProfScope ps_(K_ADAM, st);
   hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, st, (long long)n, params, grads, m, v, bf16_copy, lr, beta1,
-                     beta2, eps, c1, c2);
+                     beta2, eps, c1, c2, (const int*)nullptr);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_adam_step_dev(int64_t n, float* params, float* grads, float* m, float* v, uint16_t* bf16_copy, float lr,
+                     float beta1, float beta2, float eps, const int32_t* step_dev, void* stream) {
+  if (n < 0 || !params || !grads || !m || !v || !step_dev) return GS_ERR_INVALID_ARG;
+  if (n == 0) return GS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  ProfScope ps_(K_ADAM, st);
+  hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, st, (long long)n, params, grads, m, v, bf16_copy, lr, beta1,
+                     beta2, eps, 1.f, 1.f, (const int*)step_dev);
+  return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_advance_counters(int32_t* step_dev, uint64_t* offset_dev, uint64_t offset_delta, void* stream) {
+  if (!step_dev && !offset_dev) return GS_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, (hipStream_t)stream, (int*)step_dev,
+                     (unsigned long long*)offset_dev, (unsigned long long)offset_delta);
   return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 

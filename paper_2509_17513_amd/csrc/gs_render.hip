@@ -1311,10 +1311,13 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
   const size_t recbase = (size_t)c.b * d.n;
   uint32_t n_eval = 0, n_contrib = 0;
   // the list entry of the next batch is read while this batch is walked
-  uint32_t gnext = c.range.x + t < c.range.y ? lists[c.range.x + t] : 0xFFFFFFFFu;
-  for (uint32_t base = c.range.x; base < c.range.y; base += kTilePix) {
+  // entries staged per round (d.batch <= kTilePix, threads t < d.batch stage one each)
+  const uint32_t nb = (uint32_t)d.batch;
+  const bool stager = (uint32_t)t < nb;
+  uint32_t gnext = stager && c.range.x + t < c.range.y ? lists[c.range.x + t] : 0xFFFFFFFFu;
+  for (uint32_t base = c.range.x; base < c.range.y; base += nb) {
     const uint32_t gi = gnext;
-    gnext = base + kTilePix + t < c.range.y ? lists[base + kTilePix + t] : 0xFFFFFFFFu;
+    gnext = stager && base + nb + t < c.range.y ? lists[base + nb + t] : 0xFFFFFFFFu;
     open_state<MAXL>(d, Tr, nlhi, wopen, whi);
     // entries of index >= every pixel's highest open layer bound are useless to the whole tile
     if (t == 0) s_hi = 0;
@@ -1548,15 +1551,16 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
     reduce_scatter9(pr, lane);
     vid = (int)(pr[0] * (1.f / 64.f) + 0.5f);
   }
-  for (int top = (int)ktop; top > 0; top -= kTilePix) {
-    const int lo = max(0, top - kTilePix);
+  const int nb = d.batch;  // entries staged per round (<= kTilePix, threads t < nb stage one each)
+  for (int top = (int)ktop; top > 0; top -= nb) {
+    const int lo = max(0, top - nb);
     __syncthreads();
     // stage the entries some pixel of the tile still needs (position before that layer's last
     // contributor, index inside the layer), keeping their order
     const uint32_t k = (uint32_t)(lo + t);
     uint32_t gi = 0xFFFFFFFFu;
     bool need = false;
-    if ((int)k < top) {
+    if (t < nb && (int)k < top) {
       gi = lists[c.range.x + k];
 #pragma unroll
       for (int l = 0; l < MAXL; ++l) need = need || (k < lmax[l] && gi < (uint32_t)d.lv[l]);
@@ -1661,6 +1665,256 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
         if (x != 0.f) {
           unsafeAtomicAdd(dst + v, x * kGradScale[v]);
           s_g[t][v] = 0.f;
+        }
+      }
+    }
+  }
+  if (COUNT) flush_counters(n_eval, n_contrib, &st->bwd_evals, &st->bwd_contribs);
+}
+
+// Block-wide stable compaction for a block of NW waves (see compact_slot).
+template <int NW>
+__device__ __forceinline__ int compact_slot_w(bool keep, uint32_t* s_wcnt, int* total) {
+  const int t = threadIdx.x, w = t >> 6;
+  const unsigned long long m = __ballot(keep);
+  if ((t & 63) == 0) s_wcnt[w] = (uint32_t)__popcll(m);
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const int c = (int)s_wcnt[q];
+    off += q < w ? c : 0;
+    tot += c;
+  }
+  *total = tot;
+  return off + (int)popc_below(m);
+}
+
+// The backward with two pixels per lane: a block of 128 threads (two waves) per 16x16 tile, wave w
+// holding rows 8w..8w+7 (the quadrants 2w and 2w + 1), lane l the pixels (l & 15, 8w + (l >> 4))
+// and (l & 15, 8w + 4 + (l >> 4)). Per walked entry the LDS reads, the per-entry bookkeeping and
+// the nine-value wave reduction are shared by the lane's two pixels, whose gradient terms are
+// added in the lane first. Per pixel the arithmetic is that of k_raster_bwd, so the gradients
+// agree up to the order of the float additions.
+constexpr int kBwd2Threads = 128;
+
+template <int MAXL, bool COUNT>
+__global__ __launch_bounds__(kBwd2Threads) void k_raster_bwd2(RenderDims d, Status* __restrict__ st,
+                                                              const uint2* __restrict__ ranges,
+                                                              const uint32_t* __restrict__ lists,
+                                                              const float4* __restrict__ rec,
+                                                              const float* __restrict__ t_final,
+                                                              const uint32_t* __restrict__ n_last,
+                                                              const float* __restrict__ image,
+                                                              const float* __restrict__ d_image,
+                                                              const float* __restrict__ target,
+                                                              float* __restrict__ g2d, float* __restrict__ loss_out) {
+  if (st->overflow) return;
+  const int per = (d.B * d.T + 7) / 8;
+  const int wid = xcd_item(blockIdx.x, per);
+  if (wid >= d.B * d.T) return;
+  const int bv = wid / d.T, tile = wid - bv * d.T;
+  const int tx = tile % d.TX, ty = tile / d.TX;
+  const int ox = tx * kTile, oy = ty * kTile;
+  const uint2 range = ranges[(size_t)bv * d.T + tile];
+  __shared__ float4 s_a[kTilePix];  // mx, my, o, index bits
+  __shared__ float4 s_b[kTilePix];  // scaled conic a2, b2, c2, (first layer | quadrant mask << 8) bits
+  __shared__ float4 s_c[kTilePix];  // r, g, b, list position bits
+  __shared__ float s_g[kTilePix][kGradLds];  // per-entry gradient sums of the two waves
+  __shared__ uint32_t s_wcnt[kBwd2Threads / 64];
+  __shared__ uint32_t s_lmax[kMaxLevels];
+  __shared__ float s_loss;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const uint32_t qbits = 3u << (8 + 2 * wv);
+  if (t < kMaxLevels) s_lmax[t] = 0;
+  if (t == 0) s_loss = 0.f;
+  for (int e = t; e < kTilePix; e += kBwd2Threads)
+    for (int v = 0; v < kGradLds; ++v) s_g[e][v] = 0.f;
+  __syncthreads();
+  const int px = ox + (lane & 15);
+  const int py0 = oy + 8 * wv + (lane >> 4);
+  const float fpx = (float)px + 0.5f;
+  const float fpy[2] = {(float)py0 + 0.5f, (float)(py0 + 4) + 0.5f};
+  const size_t HW = (size_t)d.W * d.H;
+  // per pixel p of the lane, as in k_raster_bwd
+  float Tr[2][MAXL], wr[2][MAXL], wg[2][MAXL], wb[2][MAXL], Q[2][MAXL];
+  uint32_t last[2][MAXL];
+  float loss = 0.f;
+  const float inv3hw = 1.0f / (3.0f * (float)HW);
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int py = py0 + 4 * p;
+    const bool inside = px < d.W && py < d.H;
+    const size_t pix = (size_t)py * d.W + px;
+#pragma unroll
+    for (int l = 0; l < MAXL; ++l) {
+      Tr[p][l] = 0.f; wr[p][l] = wg[p][l] = wb[p][l] = 0.f; last[p][l] = 0;
+      if (inside && l < d.L) {
+        const size_t o = (size_t)bv * d.L + l;
+        Tr[p][l] = t_final[o * HW + pix];
+        last[p][l] = n_last[o * HW + pix];
+        float w3[3];
+        for (int ch = 0; ch < 3; ++ch) {
+          if (d_image) {
+            w3[ch] = d_image[(o * 3 + ch) * HW + pix];
+          } else {
+            const float diff = image[(o * 3 + ch) * HW + pix] - target[((size_t)bv * 3 + ch) * HW + pix];
+            const float sgn = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
+            w3[ch] = d.lw[l] * sgn * inv3hw;
+            loss += d.lw[l] * fabsf(diff) * inv3hw;
+          }
+        }
+        wr[p][l] = w3[0]; wg[p][l] = w3[1]; wb[p][l] = w3[2];
+        if (last[p][l]) atomicMax(&s_lmax[l], last[p][l]);
+      }
+      Q[p][l] = Tr[p][l] * (wr[p][l] * d.bg[0] + wg[p][l] * d.bg[1] + wb[p][l] * d.bg[2]);
+    }
+  }
+  if (loss_out) {
+    loss = wave_sum(loss);
+    if (lane == 0) atomicAdd(&s_loss, loss);
+  }
+  __syncthreads();
+  if (loss_out && t == 0) unsafeAtomicAdd(loss_out, s_loss);
+  uint32_t lmax[MAXL];
+  uint32_t ktop = 0;
+#pragma unroll
+  for (int l = 0; l < MAXL; ++l) {
+    lmax[l] = l < d.L ? s_lmax[l] : 0u;
+    ktop = max(ktop, lmax[l]);
+  }
+  uint32_t lw[MAXL];
+  {
+    uint32_t run = 0;
+#pragma unroll
+    for (int l = MAXL - 1; l >= 0; --l) {
+      run = max(run, wave_max_u(l < d.L ? max(last[0][l], last[1][l]) : 0u));
+      lw[l] = run;
+    }
+  }
+  const size_t recbase = (size_t)bv * d.n;
+  uint32_t n_eval = 0, n_contrib = 0;
+  int vid;
+  {
+    float pr[9] = {0.f, 1.f, 2.f, 3.f, 4.f, 5.f, 6.f, 7.f, 0.f};
+    reduce_scatter9(pr, lane);
+    vid = (int)(pr[0] * (1.f / 64.f) + 0.5f);
+  }
+  const int nb = d.batch;
+  for (int top = (int)ktop; top > 0; top -= nb) {
+    const int lo = max(0, top - nb);
+    __syncthreads();
+    // stage the needed entries of [lo, top) in order, kBwd2Threads list positions per sub-round
+    int cnt = 0;
+    for (int sub = 0; sub * kBwd2Threads < nb; ++sub) {
+      const int off = sub * kBwd2Threads + t;
+      const uint32_t k = (uint32_t)(lo + off);
+      uint32_t gi = 0xFFFFFFFFu;
+      bool need = false;
+      if (off < nb && (int)k < top) {
+        gi = lists[range.x + k];
+#pragma unroll
+        for (int l = 0; l < MAXL; ++l) need = need || (k < lmax[l] && gi < (uint32_t)d.lv[l]);
+      }
+      int csub;
+      const int slot = cnt + compact_slot_w<kBwd2Threads / 64>(need, s_wcnt, &csub);
+      if (need) {
+        const float4* r = rec + 3 * (recbase + gi);
+        const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+        const uint32_t qm = quad_mask(d, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, ox, oy);
+        s_a[slot] = make_float4(r0.x, r0.y, r1.y, __uint_as_float(gi));
+        s_b[slot] = make_float4(-0.5f * kLog2e * r0.z, -kLog2e * r0.w, -0.5f * kLog2e * r1.x,
+                                __uint_as_float(first_layer(d, gi) | (qm << 8)));
+        s_c[slot] = make_float4(r1.z, r1.w, r2.x, __uint_as_float(k));
+      }
+      cnt += csub;
+      __syncthreads();
+    }
+    for (int q = (cnt - 1) >> 6; q >= 0; --q) {
+      uint64_t m;
+      {
+        const int e = q * 64 + lane;
+        bool keep = false;
+        if (e < cnt) {
+          const uint32_t meta = __float_as_uint(s_b[e].w);
+          const uint32_t lm = meta & 0xFFu;
+          uint32_t lim = 0;
+#pragma unroll
+          for (int l = 0; l < MAXL; ++l) lim = lm == (uint32_t)l ? lw[l] : lim;
+          keep = (meta & qbits) && __float_as_uint(s_c[e].w) < lim;
+        }
+        m = __ballot(keep);
+      }
+      while (m != 0) {
+        const int bit = 63 - (int)__builtin_clzll(m);
+        m &= ~(1ull << bit);
+        const int j = (q << 6) + bit;
+        const float4 cb = s_b[j];
+        const float4 a = s_a[j];
+        const float4 col = s_c[j];
+        const uint32_t kk = __float_as_uint(col.w);
+        const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
+        const uint32_t lmask = 0xFFu << lmin;  // the entry's layers (uniform)
+        float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const AlphaEval ev = alpha_eval(fpx, fpy[p], a.x, a.y, cb.x, cb.y, cb.z, a.z);
+          const bool hit = ev.ga >= d.alpha_min;
+          const float al = __builtin_amdgcn_fmed3f(ev.ga, 0.f, d.alpha_max);  // min(alpha_max, ga), ga >= 0
+          const float oma = 1.f - al;
+          const float ioma = __builtin_amdgcn_rcpf(oma);
+          float gr = 0.f, gg = 0.f, gb = 0.f, dal = 0.f;
+          bool cand = false;
+#pragma unroll
+          for (int l = 0; l < MAXL; ++l) {
+            if (!((lmask >> l) & 1u)) continue;
+            const bool before = kk < last[p][l];
+            if (COUNT) cand |= before;
+            if (!(hit & before)) continue;
+            const float Tb = Tr[p][l] * ioma;  // transmittance in front of this Gaussian
+            const float wT = al * Tb;
+            gr = fmaf(wr[p][l], wT, gr);
+            gg = fmaf(wg[p][l], wT, gg);
+            gb = fmaf(wb[p][l], wT, gb);
+            const float wc = fmaf(wr[p][l], col.x, fmaf(wg[p][l], col.y, wb[p][l] * col.z));
+            dal = fmaf(Tb, wc, fmaf(-Q[p][l], ioma, dal));
+            Q[p][l] = fmaf(wT, wc, Q[p][l]);
+            Tr[p][l] = Tb;
+            if (COUNT) ++n_contrib;
+          }
+          if (COUNT) n_eval += cand ? 1u : 0u;
+          // the clamp at alpha_max has zero derivative; dal is zero without a contribution
+          const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
+          const float dp = dl * ev.ga;
+          const float pdx = dp * ev.dx, pdy = dp * ev.dy;
+          g[0] += dp * fmaf(cb.x, ev.dx, ev.u);
+          g[1] += dp * (fmaf(cb.y, ev.dx, ev.v) + ev.v);
+          g[2] += pdx * ev.dx;
+          g[3] += pdx * ev.dy;
+          g[4] += pdy * ev.dy;
+          g[5] += dl * ev.G;
+          g[6] += gr;
+          g[7] += gg;
+          g[8] += gb;
+        }
+        reduce_scatter9(g, lane);
+        const bool lead = (lane & 7) == 0;
+        const float x = lead ? g[0] : g[8];
+        if ((lead || lane == 1) && x != 0.f) atomicAdd(&s_g[j][lead ? vid : 8], x);
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < cnt; e += kBwd2Threads) {
+      const uint32_t g_i = __float_as_uint(s_a[e].w);
+      float* dst = g2d + (recbase + g_i) * kGradStride;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) {
+        const float x = s_g[e][v];
+        if (x != 0.f) {
+          unsafeAtomicAdd(dst + v, x * kGradScale[v]);
+          s_g[e][v] = 0.f;
         }
       }
     }
@@ -1908,11 +2162,18 @@ hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, co
   const uint32_t* nl = (const uint32_t*)(ws + lo.n_last);
   float* g2d = (float*)(ws + lo.grad2d);
   const int per = (d.B * d.T + 7) / 8;
-  dim3 grid(per * 8), block(kTilePix);
+  dim3 grid(per * 8), block(kTilePix), block2(kBwd2Threads);
   const bool cnt = work_counting();
+  const bool two = d.bwd_pixels == 2;
 #define GS_BWD(L_)                                                                                          \
   do {                                                                                                      \
-    if (cnt)                                                                                                \
+    if (two && cnt)                                                                                         \
+      hipLaunchKernelGGL((k_raster_bwd2<L_, true>), grid, block2, 0, st, d, status, ranges, lists, rec, tf, nl, \
+                         image, d_image, target, g2d, loss_out);                                            \
+    else if (two)                                                                                           \
+      hipLaunchKernelGGL((k_raster_bwd2<L_, false>), grid, block2, 0, st, d, status, ranges, lists, rec, tf,  \
+                         nl, image, d_image, target, g2d, loss_out);                                        \
+    else if (cnt)                                                                                           \
       hipLaunchKernelGGL((k_raster_bwd<L_, true>), grid, block, 0, st, d, status, ranges, lists, rec, tf, nl, \
                          image, d_image, target, g2d, loss_out);                                            \
     else                                                                                                    \

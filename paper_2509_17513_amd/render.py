@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import os
 
 import torch
 
@@ -32,6 +33,8 @@ class RenderSettings:
     bin_chunk: int = 0
     row_seg: int = 0
     wave_layout: int = 0
+    lds_batch: int = 0
+    bwd_pixels: int = 0
 
     def c_struct(self, n: int) -> GsSettings:
         s = GsSettings()
@@ -51,6 +54,7 @@ class RenderSettings:
             s.bg[i] = self.bg[i]
         s.tile_w = s.tile_h = 0
         s.bin_chunk, s.row_seg, s.wave_layout = self.bin_chunk, self.row_seg, self.wave_layout
+        s.lds_batch, s.bwd_pixels = self.lds_batch, self.bwd_pixels
         return s
 
     @property
@@ -219,11 +223,15 @@ def render_backward(settings: RenderSettings, params: torch.Tensor, cams: torch.
     return d_params, d_residuals
 
 
+N_TUNE_TRIALS = 13
+TUNED_FIELDS = ("bin_chunk", "row_seg", "wave_layout", "lds_batch", "bwd_pixels")
+
+
 def autotune(settings: RenderSettings, params: torch.Tensor, cams: torch.Tensor, ws: Workspace, n_frames: int = 1,
              residuals: torch.Tensor | None = None, image: torch.Tensor | None = None):
-    """Launch shapes for this workload (gs_autotune_render): returns (tuned settings, the eight trial
-    times in ms per forward + backward, -1 for a trial whose image differed). The workspace must
-    already hold the pairs (render once with check_overflow first)."""
+    """Launch shapes for this workload (gs_autotune_render): returns (tuned settings, the thirteen
+    trial times in ms per forward + backward, -1 for a trial whose image differed). The workspace
+    must already hold the pairs (render once with check_overflow first)."""
     dev = params.device
     n = params.shape[1]
     B = cams.shape[0]
@@ -234,13 +242,53 @@ def autotune(settings: RenderSettings, params: torch.Tensor, cams: torch.Tensor,
     dr = torch.zeros_like(residuals) if residuals is not None else None
     s = settings.c_struct(n)
     best = GsSettings()
-    times = (ctypes.c_float * 8)()
+    times = (ctypes.c_float * N_TUNE_TRIALS)()
     check(lib().gs_autotune_render(ctypes.byref(s), n, _ptr(params), n_frames, _ptr(residuals), B // n_frames,
                                    _ptr(cams), _ptr(image), _ptr(dp), _ptr(dr), _ptr(ws.buf), ws.nbytes, _stream(dev),
                                    ctypes.byref(best), times), "gs_autotune_render")
-    tuned = dataclasses.replace(settings, bin_chunk=best.bin_chunk, row_seg=best.row_seg,
-                                wave_layout=best.wave_layout)
+    tuned = dataclasses.replace(settings, **{f: getattr(best, f) for f in TUNED_FIELDS})
     return tuned, list(times)
+
+
+def tune_cache_path() -> str:
+    """The JSON tuning cache: $GS4D_TUNE_CACHE, else ~/.cache/gs4d/autotune.json."""
+    return os.environ.get("GS4D_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "gs4d",
+                                                             "autotune.json")
+
+
+def tune_key(settings: RenderSettings, n: int, n_frames: int, n_views: int, device) -> str:
+    """Cache key: the GPU architecture and every property of the workload the shapes depend on."""
+    arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+    lv = ",".join(str(int(v)) for v in (settings.level_counts or (n,)))
+    return (f"{arch}|n={n}|frames={n_frames}|views={n_views}|{settings.width}x{settings.height}|"
+            f"sh={settings.sh_degree}|levels={lv}|res={settings.res_channels}")
+
+
+def autotune_cached(settings: RenderSettings, params: torch.Tensor, cams: torch.Tensor, ws: Workspace,
+                    n_frames: int = 1, residuals: torch.Tensor | None = None, image: torch.Tensor | None = None,
+                    path: str | None = None):
+    """autotune() through the JSON tuning cache: a workload already tuned on this architecture
+    takes its stored shapes (no trials); otherwise the trials run and their winner is stored.
+    Returns (tuned settings, trial times, True if the shapes came from the cache)."""
+    import json
+    path = path or tune_cache_path()
+    key = tune_key(settings, params.shape[1], n_frames, cams.shape[0] // n_frames, params.device)
+    try:
+        with open(path) as fh:
+            db = json.load(fh)
+    except (OSError, ValueError):
+        db = {}
+    hit = db.get(key)
+    if isinstance(hit, dict) and all(isinstance(hit.get(f), int) for f in TUNED_FIELDS):
+        return dataclasses.replace(settings, **{f: hit[f] for f in TUNED_FIELDS}), hit.get("trial_ms"), True
+    tuned, times = autotune(settings, params, cams, ws, n_frames, residuals, image)
+    db[key] = {**{f: getattr(tuned, f) for f in TUNED_FIELDS}, "trial_ms": times}
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(db, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return tuned, times, False
 
 
 class LossWorkspace:

@@ -55,13 +55,17 @@ class Adam:
         self.eps = eps
 
     def step(self, grad: torch.Tensor, lr: float, t: int, start: int = 0, count: int | None = None,
-             bf16_copy: torch.Tensor | None = None):
+             bf16_copy: torch.Tensor | None = None, t_dev: torch.Tensor | None = None):
+        """One Adam update with step number t, or with the step number held in the device int32
+        t_dev (read when the kernel runs: a captured step replays with the right corrections)."""
         count = self.p.numel() - start if count is None else count
         cp = None if bf16_copy is None else ctypes.c_void_p(bf16_copy.data_ptr() + 2 * start)
-        check(lib().gs_adam_step(count, _off(self.p, start), _off(grad, start), _off(self.m, start),
-                                 _off(self.v, start), cp, ctypes.c_float(lr), ctypes.c_float(self.b1),
-                                 ctypes.c_float(self.b2), ctypes.c_float(self.eps), t, _s(self.p.device)),
-              "gs_adam_step")
+        args = (count, _off(self.p, start), _off(grad, start), _off(self.m, start), _off(self.v, start), cp,
+                ctypes.c_float(lr), ctypes.c_float(self.b1), ctypes.c_float(self.b2), ctypes.c_float(self.eps))
+        if t_dev is None:
+            check(lib().gs_adam_step(*args, t, _s(self.p.device)), "gs_adam_step")
+        else:
+            check(lib().gs_adam_step_dev(*args, _p(t_dev), _s(self.p.device)), "gs_adam_step_dev")
 
 
 def _bf16_bits(x: np.ndarray) -> np.ndarray:
@@ -107,8 +111,10 @@ class RateModel:
         check(lib().gs_rate_init_output_bias(attrs.shape[1], self.n_attr, _p(attrs), ctypes.c_float(self.step_size),
                                              _p(self.b), _p(acc), _s(self.b.device)), "gs_rate_init_output_bias")
 
-    def desc(self, n, mode, level_counts, level_weights, lambda_rate, seed=0, offset=0, fit_scale=None):
+    def desc(self, n, mode, level_counts, level_weights, lambda_rate, seed=0, offset=0, fit_scale=None,
+             offset_dev=None):
         d = _lib.GsRateDesc()
+        d.offset_dev = None if offset_dev is None else offset_dev.data_ptr()
         d.n, d.n_attr, d.step, d.mode, d.seed, d.offset = n, self.n_attr, self.step_size, mode, seed, offset
         d.n_levels = len(level_counts)
         for i, v in enumerate(level_counts):
@@ -120,9 +126,10 @@ class RateModel:
         return d
 
     def run(self, attrs_ptr, n, ctx, mode, level_counts, level_weights, lambda_rate=0.0, seed=0, offset=0,
-            d_attrs_ptr=None, grads=True, sym_bits=None):
-        """Accumulates bits / loss (and gradients) of one pass; zero them first with reset()."""
-        d = self.desc(n, mode, level_counts, level_weights, lambda_rate, seed, offset)
+            d_attrs_ptr=None, grads=True, sym_bits=None, offset_dev=None):
+        """Accumulates bits / loss (and gradients) of one pass; zero them first with reset().
+        offset_dev: a device uint64 holding the noise counter offset (instead of offset)."""
+        d = self.desc(n, mode, level_counts, level_weights, lambda_rate, seed, offset, offset_dev=offset_dev)
         check(lib().gs_rate_model(ctypes.byref(d), attrs_ptr, _p(ctx), _p(self.w16), _p(self.b), _p(self.bits),
                                   _p(self.loss), _p(sym_bits), d_attrs_ptr, _p(self.dw) if grads else None,
                                   _p(self.db) if grads else None, _s(self.w.device)), "gs_rate_model")
@@ -147,10 +154,10 @@ class RateModel:
         zero(self.bits)
         zero(self.loss)
 
-    def adam(self, lr: float):
+    def adam(self, lr: float, t_dev: torch.Tensor | None = None):
         self.t += 1
-        self.opt_w.step(self.dw, lr, self.t, bf16_copy=self.w16)
-        self.opt_b.step(self.db, lr, self.t)
+        self.opt_w.step(self.dw, lr, self.t, bf16_copy=self.w16, t_dev=t_dev)
+        self.opt_b.step(self.db, lr, self.t, t_dev=t_dev)
 
 
 def context(params: torch.Tensor, extent: float, level_counts, out: torch.Tensor | None = None):
@@ -227,11 +234,19 @@ class JointTrainer:
             self.loss_ws = LossWorkspace(settings, cams.shape[0], params.device)
 
     def step(self, check_overflow: bool | None = None):
-        n = self.n
-        zero(self.loss)
         if check_overflow is None:
             check_overflow = self.t % self.check_every == 0
+        self._forward(check_overflow)
+        self._rest()
+
+    def _forward(self, check_overflow=False):
+        zero(self.loss)
         render_forward(self.st, self.p, self.cams, ws=self.ws, image=self.img, check_overflow=check_overflow)
+
+    def _rest(self, counters=None):
+        """Everything after the forward render. counters = (t_dev, off_dev): the step number and
+        the rate's noise offset are taken from (and advanced in) device memory, for capture."""
+        n = self.n
         if self.lambda_ssim > 0:
             color_loss(self.st, self.img, self.tgt, self.lambda_ssim, d_image=self.d_img, loss=self.loss,
                        ws=self.loss_ws)
@@ -239,14 +254,19 @@ class JointTrainer:
         else:
             render_backward(self.st, self.p, self.cams, self.ws, image=self.img, target=self.tgt, d_params=self.dp,
                             loss=self.loss)
+        t_dev, off_dev = counters if counters is not None else (None, None)
         if self.rate is not None:
             self.rate.reset()
             context(self.p, self.extent, self.levels, self.ctx)
             A = self.rate.n_attr
             self.rate.run(_off(self.p, 3 * n), n, self.ctx, 1, self.levels, self.level_w, self.lam,
                           seed=self.seed, offset=self.t * A * n,
-                          d_attrs_ptr=_off(self.dp, 3 * n) if self.lam > 0 else None)
-            self.rate.adam(self.lrs.mlp)
+                          d_attrs_ptr=_off(self.dp, 3 * n) if self.lam > 0 else None, offset_dev=off_dev)
+        if counters is not None:
+            A = self.rate.n_attr if self.rate is not None else 0
+            check(lib().gs_advance_counters(_p(t_dev), _p(off_dev), A * n, _s(self.p.device)), "gs_advance_counters")
+        if self.rate is not None:
+            self.rate.adam(self.lrs.mlp, t_dev=t_dev)
         if self.kde is not None:
             # the rate of the attribute rows (everything but the means), noisy symbols, its
             # gradient added into the same rows of d_params
@@ -259,7 +279,50 @@ class JointTrainer:
         for lo, hi, r in ((0, 3, lr.mean), (3, 6, lr.log_scale), (6, 10, lr.quat), (10, 11, lr.logit),
                           (11, 14, lr.sh_dc), (14, 11 + K, lr.sh_rest)):
             if hi > lo:
-                self.opt.step(self.dp, r, self.t, start=lo * n, count=(hi - lo) * n)
+                self.opt.step(self.dp, r, self.t, start=lo * n, count=(hi - lo) * n, t_dev=t_dev)
+
+    def capture(self):
+        """Captures one training step in two hipGraphs (torch.cuda.CUDAGraph): the forward render,
+        and everything after it (colour loss backward, context, learned rate with its gradient, the
+        Adams), with the step number and the rate's noise offset in device counters that the graph
+        advances, so that replays (step_graph) train exactly like eager steps. The KDE rate is not
+        captured (its noise offset is a host argument)."""
+        if self.kde is not None:
+            raise ValueError("the KDE rate path is not captured")
+        dev = self.p.device
+        A = self.rate.n_attr if self.rate is not None else 0
+        self.t_dev = torch.tensor([self.t], dtype=torch.int32, device=dev)
+        self.off_dev = torch.tensor([self.t * A * self.n], dtype=torch.int64, device=dev)
+        if self.rate is not None:
+            self.rate.t = self.t
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        self.g_fwd, self.g_rest = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.g_fwd, stream=side):
+            self._forward(False)
+        t0 = self.t
+        with torch.cuda.graph(self.g_rest, stream=side):
+            self._rest((self.t_dev, self.off_dev))
+        self.t = t0  # capture ran no step
+        if self.rate is not None:
+            self.rate.t = t0
+        torch.cuda.current_stream(dev).wait_stream(side)
+
+    def step_graph(self):
+        """One training step by replaying the captured graphs. Every check_every steps the pair-list
+        status is read between the forward and the rest: an overflow grows the workspace,
+        recaptures and redoes the forward before any gradient is taken."""
+        self.g_fwd.replay()
+        if self.t % self.check_every == 0:
+            ok, needed = self.ws.status()
+            if not ok:
+                self.ws.allocate(int(needed * 1.15) + 1024)
+                self._forward(True)
+                self.capture()
+        self.g_rest.replay()
+        self.t += 1
+        if self.rate is not None:
+            self.rate.t = self.t
 
     def histogram_rate(self):
         """Histogram bits per attribute of the current attributes (float64 numpy)."""

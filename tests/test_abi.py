@@ -77,16 +77,17 @@ def test_workspace_size_and_validation(L):
     assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 1, 10, ctypes.byref(sz)) == 0
     assert L.gs_error_string(-3) == b"pair list capacity exceeded"
     # launch shapes: only the listed values, and the workspace does not depend on them
-    for field, value in (("bin_chunk", 300), ("bin_chunk", 4096), ("row_seg", 512), ("wave_layout", 3)):
+    for field, value in (("bin_chunk", 300), ("bin_chunk", 4096), ("row_seg", 512), ("wave_layout", 3),
+                         ("lds_batch", 100), ("lds_batch", 512), ("bwd_pixels", 3)):
         st = _settings(1000)
         setattr(st, field, value)
         assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 2, 10000, ctypes.byref(sz2)) == -1, (field, value)
     ref = ctypes.c_size_t()
     st = _settings(1000)
     assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 2, 10000, ctypes.byref(ref)) == 0
-    for bc, rs, wl in ((512, 1024, 1), (2048, 4096, 2), (1024, 2048, 0)):
+    for bc, rs, wl, lb in ((512, 1024, 1, 64), (2048, 4096, 2, 128), (1024, 2048, 0, 256)):
         st = _settings(1000)
-        st.bin_chunk, st.row_seg, st.wave_layout = bc, rs, wl
+        st.bin_chunk, st.row_seg, st.wave_layout, st.lds_batch = bc, rs, wl, lb
         assert L.gs_workspace_size(ctypes.byref(st), 1000, 1, 2, 10000, ctypes.byref(sz2)) == 0
         assert sz2.value == ref.value
 

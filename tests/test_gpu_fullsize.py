@@ -20,10 +20,10 @@ def _case(msg):
     print(f"\n[case] {msg}", flush=True)
 
 
-def _forward(w):
+def _forward(w, bwd_pixels=0):
     from paper_2509_17513_amd import render_forward
     dev = torch.device("cuda:0")
-    st = gpu_settings(w)
+    st = gpu_settings(w, bwd_pixels=bwd_pixels)
     p = torch.from_numpy(w.params).to(dev)
     c = torch.from_numpy(w.cams).to(dev)
     r = None if w.residuals is None else torch.from_numpy(w.residuals).to(dev)
@@ -72,11 +72,13 @@ def _window_dimage(w, img, views, x0, y0, size, seed):
     return d
 
 
-def test_batched_300k_windowed_gradients_match_oracle():
-    _case("300k Gaussians, 3 ring views 960x540, 6 layers: gradient of a windowed loss vs oracle")
+@pytest.mark.parametrize("bwd_pixels", [1, 2])
+def test_batched_300k_windowed_gradients_match_oracle(bwd_pixels):
+    _case(f"300k Gaussians, 3 ring views 960x540, 6 layers: gradient of a windowed loss vs oracle "
+          f"({bwd_pixels} pixel(s) per lane)")
     from paper_2509_17513_amd import render_backward
     w = synth.config_batched(view_indices=(0, 8, 16))
-    img, ws, (p, c, r, st) = _forward(w)
+    img, ws, (p, c, r, st) = _forward(w, bwd_pixels)
     ost = oracle_settings(w)
     d = _window_dimage(w, img, (0, 2), 440, 230, 64, 102)
     # pixel-levels whose FP32 / FP64 decisions may differ carry no weight on either side
