@@ -82,9 +82,10 @@ def code_text(src: str) -> str:
 
 
 def source_hash(read=None):
-    """Hash of the code of the render and loss kernels and their host orchestration."""
+    """Hash of the code of every kernel source and the host orchestration (what the counters depend on)."""
     h = hashlib.sha256()
-    for f in ("gs_render.hip", "gs_api.hip", "gs_internal.h", "gs_loss.hip"):
+    for f in ("gs_render.hip", "gs_api.hip", "gs_internal.h", "gs_loss.hip", "gs_rate.hip", "gs_motion.hip",
+              "gs_entropy.hip", "gs_bitstream.hip"):
         if read is None:
             with open(os.path.join(ROOT, "paper_2509_17513_amd", "csrc", f)) as fh:
                 txt = fh.read()
@@ -612,7 +613,8 @@ def main():
     ap.add_argument("--no-bitstream", action="store_true",
                     help="skip the significance-order / 2D-map coding and client-render measurement")
     ap.add_argument("--no-autotune", action="store_true", help="no autotuning: default shapes or --shapes")
-    ap.add_argument("--shapes", default="", help="launch shapes bin_chunk,row_seg,wave_layout (with --no-autotune)")
+    ap.add_argument("--shapes", default="",
+                    help="launch shapes bin_chunk,row_seg,wave_layout[,lds_batch[,bwd_pixels]] (with --no-autotune)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -649,9 +651,13 @@ def main():
     img, ws = render_forward(st, p, c, ws=Workspace(st, w.n, 1, B, dev, pair_capacity=40 * w.n * B))
     tune = None
     if args.shapes:
-        bc, rs, wl = (int(x) for x in args.shapes.split(","))
-        st = dataclasses.replace(st, bin_chunk=bc, row_seg=rs, wave_layout=wl)
-        tune = {"bin_chunk": bc, "row_seg": rs, "wave_layout": wl, "lds_batch": st.lds_batch, "trial_ms": None}
+        vals = [int(x) for x in args.shapes.split(",")]
+        if len(vals) not in (3, 4, 5):
+            sys.exit("--shapes: bin_chunk,row_seg,wave_layout[,lds_batch[,bwd_pixels]]")
+        names = ("bin_chunk", "row_seg", "wave_layout", "lds_batch", "bwd_pixels")
+        st = dataclasses.replace(st, **dict(zip(names, vals)))
+        tune = {k: getattr(st, k) for k in names}
+        tune["trial_ms"] = None
     if not args.no_autotune:
         from paper_2509_17513_amd import autotune_cached
         from paper_2509_17513_amd.render import tune_cache_path
@@ -940,12 +946,16 @@ def main():
             torch.cuda.empty_cache()
             out["rate_judge"] = bench_rate_judge(torch, dev, args.judge_steps)
     if args.copy_calibration:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        # one launch of the library's plain copy kernel (k_peak_copy) over 1 GiB: its FETCH_SIZE and
+        # WRITE_SIZE readings against the known 1 GiB read and written scale every other kernel's
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        _lib.check(L.gs_peak_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                  ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)), "gs_peak_copy")
         torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        out["copy_calibration_bytes"] = {"kernel": "k_peak_copy", "read": nbytes, "write": nbytes}
         del src, dst
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baselines")
