@@ -81,11 +81,19 @@ def code_text(src: str) -> str:
     return "\n".join(ln for ln in lines if ln)
 
 
-def source_hash(read=None):
-    """Hash of the code of every kernel source and the host orchestration (what the counters depend on)."""
+# the sources each kernel's counters depend on (its own file, and the host code that launches it)
+KERNEL_SOURCES = {
+    "rate_mlp": ("gs_rate.hip",),
+    "motion_fwd": ("gs_motion.hip",), "motion_bwd": ("gs_motion.hip",), "motion_wgrad": ("gs_motion.hip",),
+    "ssim_fwd": ("gs_loss.hip",), "ssim_bwd": ("gs_loss.hip",),
+}
+RENDER_SOURCES = ("gs_render.hip", "gs_api.hip", "gs_internal.h")
+
+
+def source_hash(kernel, read=None):
+    """Hash of the code of the sources `kernel`'s counters depend on."""
     h = hashlib.sha256()
-    for f in ("gs_render.hip", "gs_api.hip", "gs_internal.h", "gs_loss.hip", "gs_rate.hip", "gs_motion.hip",
-              "gs_entropy.hip", "gs_bitstream.hip"):
+    for f in KERNEL_SOURCES.get(kernel, RENDER_SOURCES):
         if read is None:
             with open(os.path.join(ROOT, "paper_2509_17513_amd", "csrc", f)) as fh:
                 txt = fh.read()
@@ -105,7 +113,7 @@ def read_traffic(kernel):
         rec = json.load(open(p))
     except Exception:
         return None
-    if rec.get("source_hash") != source_hash():
+    if rec.get("source_hash") != source_hash(kernel):
         return None
     return rec.get("traffic_bytes_per_launch")
 
