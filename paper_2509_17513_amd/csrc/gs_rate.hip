@@ -36,6 +36,7 @@ constexpr int kWPerAttr = kW1 + kW2 + kW3;
 constexpr int kBPerAttr = kHid + kHid + 2;
 constexpr float kPFloor = 1e-9f;
 constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kLog2e = 1.4426950408889634f;
 
 // FP32 -> BF16, round to nearest even, on the hardware converter (v_cvt_pk_bf16_f32)
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -45,6 +46,13 @@ __device__ __forceinline__ uint32_t f32x2_to_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// Stores the two BF16 halves of a packed pair at p[i0] and p[i1]. The empty asm makes the pair
+// opaque, so the halves are taken from its bits instead of being converted from float again.
+__device__ __forceinline__ void store_pair(uint16_t* p, int i0, int i1, uint32_t hp) {
+  asm("" : "+v"(hp));
+  p[i0] = (uint16_t)hp;
+  p[i1] = (uint16_t)(hp >> 16);
+}
 
 // ------------------------------------------------------------------ context
 // x = [mu / extent (3), sin / cos(pi 2^k mu / extent) for k = 0, 1 (12), (layer - 1) / 5 (1)]
@@ -219,19 +227,22 @@ __device__ __forceinline__ bf16x8 pack8(const uint16_t* h) {
 __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {  // 16-byte aligned
   return __builtin_bit_cast(bf16x8, *(const uint4*)p);
 }
-// Eight values of a [o][64] matrix column: rows 0..3 and 8..11 from p (row stride 64).
+// W2 in LDS: row o2 padded to kW2Row BF16 (144 bytes: 16-byte reads of consecutive rows, and
+// 16-bit reads of a column by two row groups 4 apart, touch distinct banks), column i at
+// position w2_pos(i), i.e. bits 2 and 3 of i swapped, so that the eight contraction values a lane
+// holds for one layer-2 K-step (i = 16 ks + 4 g + {0..3} and 16 ks + 8 + 4 g + {0..3}) are one
+// contiguous 16-byte run.
+constexpr int kW2Row = 72;
+__device__ __forceinline__ int w2_pos(int i) { return (i & ~12) | ((i & 4) << 1) | ((i & 8) >> 1); }
+// Eight values of column p of W2 (pointer at row 0 of the group): rows 0..3 and 8..11.
 __device__ __forceinline__ bf16x8 load_col8(const uint16_t* p) {
   uint32_t u[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int r0 = 2 * j < 4 ? 2 * j : 2 * j + 4;
-    u[j] = (uint32_t)p[r0 * kHid] | ((uint32_t)p[(r0 + 1) * kHid] << 16);
+    u[j] = (uint32_t)p[r0 * kW2Row] | ((uint32_t)p[(r0 + 1) * kW2Row] << 16);
   }
   return __builtin_bit_cast(bf16x8, make_uint4(u[0], u[1], u[2], u[3]));
-}
-__device__ __forceinline__ bf16x8 load4x2(const uint16_t* p0, const uint16_t* p1) {  // two 8-byte halves
-  const uint2 a = *(const uint2*)p0, b = *(const uint2*)p1;
-  return __builtin_bit_cast(bf16x8, make_uint4(a.x, a.y, b.x, b.y));
 }
 
 // tanh-approximated GELU, 0.5 x (1 + tanh(u)) with u = c (x + 0.044715 x^3), c = sqrt(2 / pi),
@@ -244,12 +255,22 @@ __device__ __forceinline__ float gelu_s(float x) {
   const float e = __builtin_amdgcn_exp2f(x * fmaf(x * x, kGeluE1, kGeluE0));
   return __builtin_amdgcn_rcpf(1.f + e);
 }
-__device__ __forceinline__ float gelu_f(float x) { return x * gelu_s(x); }
-// d/dx [x s] = s + x s (1 - s) 2 u', with 2 u' = 2 c (1 + 3 * 0.044715 x^2)
-__device__ __forceinline__ float gelu_grad_f(float x) {
-  const float s = gelu_s(x);
+// d/dx [x s] = s + x s (1 - s) 2 u', with 2 u' = 2 c (1 + 3 * 0.044715 x^2), from s = gelu_s(x)
+// (the training forward evaluates the sigmoid once for GELU and its derivative)
+__device__ __forceinline__ float gelu_grad_s(float x, float s) {
   const float du2 = fmaf(x * x, 2.f * kGeluC * 3.f * 0.044715f, 2.f * kGeluC);
   return fmaf(x * du2, fmaf(-s, s, s), s);
+}
+
+// Staging slot (in BF16 elements) of row r, symbol s of a per-wave [R rows][32 symbols] tile kept
+// chunk-major: the 16-byte chunk of symbols 8c..8c+7 of row r sits at chunk index R c + (r ^ c)
+// (c < 4). An MFMA operand read (consecutive rows, one chunk) is then one contiguous run of
+// 16-byte chunks, and a staging write (rows r and r + 4, all 32 symbols) spreads over distinct
+// banks.
+template <int R>
+__device__ __forceinline__ int stg(int r, int s) {
+  const int c = s >> 3;
+  return (R * c + (r ^ c)) * 8 + (s & 7);
 }
 
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
@@ -264,43 +285,48 @@ __device__ __forceinline__ void laplace_bits(float y, float m, float b, float q,
   const float h = 0.5f * q;
   const float d = y - m;
   const float t = fabsf(d);
+  // divisions by b, b^2 and P as products with hardware reciprocals (b >= q/16 > 0, P >= 1e-9 where
+  // used): their ~1 ulp is far inside the per-symbol accuracy the rate needs
+  const float rb = __builtin_amdgcn_rcpf(b);
+  const float qb = q * rb;
   float lp, dlt, dlb;
   if (t >= h) {
-    lp = -kLn2 - (t - h) / b + logf(-expm1f(-q / b));
-    dlt = -1.f / b;
-    dlb = (t - h) / (b * b) - (q / (b * b)) / expm1f(q / b);
+    const float th = (t - h) * rb;
+    lp = -kLn2 - th + logf(-expm1f(-qb));
+    dlt = -rb;
+    dlb = rb * (th - qb * __builtin_amdgcn_rcpf(expm1f(qb)));
   } else {
-    const float ea = expf(-(h + t) / b), eb = expf(-(h - t) / b);
+    const float ea = expf(-(h + t) * rb), eb = expf(-(h - t) * rb);
     const float P = 1.f - 0.5f * ea - 0.5f * eb;
     lp = logf(P);
-    dlt = (0.5f * ea / b - 0.5f * eb / b) / P;
-    dlb = (-0.5f * ea * (h + t) / (b * b) - 0.5f * eb * (h - t) / (b * b)) / P;
+    const float rP = __builtin_amdgcn_rcpf(P);
+    dlt = 0.5f * rb * (ea - eb) * rP;
+    dlb = -0.5f * rb * rb * (ea * (h + t) + eb * (h - t)) * rP;
   }
   const float lfloor = -20.723265836946411f;  // ln 1e-9
   if (!(lp >= lfloor)) {
-    bits = -lfloor / kLn2;
+    bits = -lfloor * kLog2e;
     dy = 0.f;
     db = 0.f;
     return;
   }
-  bits = -lp / kLn2;
+  bits = -lp * kLog2e;
   const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-  dy = -dlt * sg / kLn2;
-  db = -dlb / kLn2;
+  dy = -dlt * sg * kLog2e;
+  db = -dlb * kLog2e;
 }
 
 struct RateShared {
-  uint16_t w1[kHid * kCtx];    // [o][f]
-  uint16_t w2[kHid * kHid];    // [o2][i]
+  uint16_t w2[kHid * kW2Row];  // [o2][w2_pos(i)], rows padded
   float w3[2 * kHid];
   float b1[kHid], b2[kHid], b3[2];
 };
-struct RateWaveTmp {           // transposed per-wave staging for the weight gradients
-  uint16_t h1[kHid * 32];      // [i][s]
-  uint16_t h2[kHid * 32];      // [o2][s]
-  uint16_t d2[kHid * 32];      // [o2][s]
-  uint16_t d1[kHid * 32];      // [i][s]
-  uint16_t x[kCtx * 32];       // [f][s]
+struct RateWaveTmp {           // transposed per-wave staging for the weight gradients (slots: stg)
+  uint16_t h1[kHid * 32];      // rows i, 32 symbols
+  uint16_t h2[kHid * 32];      // rows o2
+  uint16_t d2[kHid * 32];      // rows o2
+  uint16_t d1[kHid * 32];      // rows i
+  uint16_t x[kCtx * 32];       // rows f
   uint16_t dout[2 * 32];       // [r][s], BF16 (the operand of the layer-3 weight gradient)
 };
 
@@ -320,10 +346,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int sl = lane & 31, g = lane >> 5;
   const uint16_t* Wa = W + (size_t)a * kWPerAttr;
   const float* Ba = Bv + (size_t)a * kBPerAttr;
-  for (int j = tid; j < kW1; j += 256) sh.w1[j] = Wa[j];
-  for (int j = tid; j < kW2; j += 256) {
-    const uint16_t v = Wa[kW1 + j];
-    sh.w2[j] = v;
+  for (int j = tid; j < kW2; j += 256) sh.w2[(j >> 6) * kW2Row + w2_pos(j & 63)] = Wa[kW1 + j];
+  // the layer-1 weight operand (rows 32 h + sl of W1, contraction slots 8 g ..): in registers when
+  // training (the staging area leaves no LDS for it), else in LDS after the shared weights
+  bf16x8 w1f[2];
+  uint16_t* w1s = (uint16_t*)wt;
+  if constexpr (GRAD) {
+    w1f[0] = load8(Wa + sl * kCtx + 8 * g);
+    w1f[1] = load8(Wa + (32 + sl) * kCtx + 8 * g);
+  } else {
+    for (int j = tid; j < kW1; j += 256) w1s[j] = Wa[j];
   }
   for (int j = tid; j < kW3; j += 256) sh.w3[j] = bf16_to_f32(Wa[kW1 + kW2 + j]);
   if (tid < kHid) {
@@ -343,8 +375,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // Weight gradients are split over the block's four waves: wave w accumulates rows 16w..16w+15
   // of dW2 and dW1 and columns 16w..16w+15 of dW3, over the symbols of all four waves (their
   // staged activations are read from LDS), so each wave holds 24 accumulators instead of 96.
-  f32x4 acc2[4], acc1, acc3;
-  float db1 = 0.f, db2 = 0.f, db30 = 0.f, db31 = 0.f;
+  f32x4 acc2[4], acc1, acc3, accb1, accb2;  // accb: bias sums (every column holds them)
+  float db30 = 0.f, db31 = 0.f;
   if constexpr (GRAD) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -352,9 +384,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (int u = 0; u < 4; ++u) acc2[u][r] = 0.f;
       acc1[r] = 0.f;
       acc3[r] = 0.f;
+      accb1[r] = 0.f;
+      accb2[r] = 0.f;
     }
   }
   RateWaveTmp& T = wt[wave];
+  float* gp1s = (float*)T.d2;  // spans d2 and d1
   const f32x16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
   for (int it = 0; it < iters; ++it) {
@@ -370,8 +405,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     f32x16 c1[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
-      c1[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(&sh.w1[(32 * h + sl) * kCtx + 8 * g]), bx, zero16, 0, 0,
-                                                      0);
+      c1[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(GRAD ? w1f[h] : load8(&w1s[(32 * h + sl) * kCtx + 8 * g]), bx,
+                                                      zero16, 0, 0, 0);
     // bias + GELU + BF16, packed straight into the B operand of layer 2
     uint32_t b2[4][4];
 #pragma unroll
@@ -383,10 +418,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int r = 0; r < 16; r += 2) {
         const int o = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o + 1 for r + 1
-        const uint32_t hp = f32x2_to_bf16x2(gelu_f(c1[h][r] + sh.b1[o]), gelu_f(c1[h][r + 1] + sh.b1[o + 1]));
+        const float x0 = c1[h][r] + sh.b1[o], x1 = c1[h][r + 1] + sh.b1[o + 1];
+        const float s0 = gelu_s(x0), s1 = gelu_s(x1);
+        const uint32_t hp = f32x2_to_bf16x2(x0 * s0, x1 * s1);
         if constexpr (GRAD) {
-          T.h1[o * 32 + sl] = (uint16_t)hp;
-          T.h1[(o + 1) * 32 + sl] = (uint16_t)(hp >> 16);
+          // GELU'(Z1) from the same sigmoid, kept in the wave's d2 | d1 staging area (8 KB, unused
+          // until the backward) as [value r][lane] until dZ1 is formed
+          gp1s[(16 * h + r) * 64 + lane] = gelu_grad_s(x0, s0);
+          gp1s[(16 * h + r + 1) * 64 + lane] = gelu_grad_s(x1, s1);
+          store_pair(T.h1, stg<kHid>(o, sl), stg<kHid>(o + 1, sl), hp);
         }
         b2[2 * h + (r >> 3)][(r & 7) >> 1] = hp;
       }
@@ -397,9 +437,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       c2[h2] = zero16;
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
-        const uint16_t* row = &sh.w2[(32 * h2 + sl) * kHid + 16 * ks + 4 * g];
         c2[h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            load4x2(row, row + 8), __builtin_bit_cast(bf16x8, make_uint4(b2[ks][0], b2[ks][1], b2[ks][2], b2[ks][3])),
+            load8(&sh.w2[(32 * h2 + sl) * kW2Row + 16 * ks + 8 * g]), __builtin_bit_cast(bf16x8, make_uint4(b2[ks][0], b2[ks][1], b2[ks][2], b2[ks][3])),
             c2[h2], 0, 0, 0);
       }
     }
@@ -411,12 +450,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (int r = 0; r < 16; r += 2) {
         const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o2 + 1 for r + 1
         const float z0 = c2[h][r] + sh.b2[o2], z1 = c2[h][r + 1] + sh.b2[o2 + 1];
-        c2[h][r] = z0;  // keep Z2 for the backward
-        c2[h][r + 1] = z1;
-        const uint32_t hp = f32x2_to_bf16x2(gelu_f(z0), gelu_f(z1));
+        const float s0 = gelu_s(z0), s1 = gelu_s(z1);
+        if constexpr (GRAD) {  // keep GELU'(Z2) for the backward
+          c2[h][r] = gelu_grad_s(z0, s0);
+          c2[h][r + 1] = gelu_grad_s(z1, s1);
+        }
+        const uint32_t hp = f32x2_to_bf16x2(z0 * s0, z1 * s1);
         if constexpr (GRAD) {
-          T.h2[o2 * 32 + sl] = (uint16_t)hp;
-          T.h2[(o2 + 1) * 32 + sl] = (uint16_t)(hp >> 16);
+          store_pair(T.h2, stg<kHid>(o2, sl), stg<kHid>(o2 + 1, sl), hp);
         }
         o0 = fmaf(sh.w3[o2], __uint_as_float(hp << 16), o0);
         o1 = fmaf(sh.w3[kHid + o2], __uint_as_float(hp << 16), o1);
@@ -459,7 +500,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     if constexpr (GRAD) {
       const float dout0 = valid ? -ra.wfit * dby : 0.f;
-      const float sig1 = 1.f / (1.f + expf(-o1));
+      const float sig1 = __builtin_amdgcn_rcpf(1.f + expf(-o1));
       const float dout1 = valid ? ra.wfit * dbb * sig1 : 0.f;
       // dZ2 = (W3^T dout) * GELU'(Z2), packed into the B operand of dH1^T = W2^T dZ2^T
       uint32_t bd[4][4];
@@ -474,10 +515,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o2 + 1 for r + 1
           const float dh0 = dout0 * sh.w3[o2] + dout1 * sh.w3[kHid + o2];
           const float dh1 = dout0 * sh.w3[o2 + 1] + dout1 * sh.w3[kHid + o2 + 1];
-          const uint32_t dp = f32x2_to_bf16x2(dh0 * gelu_grad_f(c2[h][r]), dh1 * gelu_grad_f(c2[h][r + 1]));
-          T.d2[o2 * 32 + sl] = (uint16_t)dp;
-          T.d2[(o2 + 1) * 32 + sl] = (uint16_t)(dp >> 16);
-          bd[2 * h + (r >> 3)][(r & 7) >> 1] = dp;
+          bd[2 * h + (r >> 3)][(r & 7) >> 1] = f32x2_to_bf16x2(dh0 * c2[h][r], dh1 * c2[h][r + 1]);
         }
       f32x16 c3[2];
 #pragma unroll
@@ -486,32 +524,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           // W2^T rows i, K = o2 in the order 16 ks + 4 g + {0..3, 8..11}: a column of W2
-          const uint16_t* col = &sh.w2[(16 * ks + 4 * g) * kHid + 32 * hi + sl];
+          const uint16_t* col = &sh.w2[(16 * ks + 4 * g) * kW2Row + 32 * hi + w2_pos(sl)];
           c3[hi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
               load_col8(col),
               __builtin_bit_cast(bf16x8, make_uint4(bd[ks][0], bd[ks][1], bd[ks][2], bd[ks][3])), c3[hi], 0, 0, 0);
         }
       }
-      // layer-1 pre-activations again (two MFMAs) for GELU'(Z1)
+      // dZ1 = dH1 * GELU'(Z1): every stashed value is read before the d1 and d2 staging writes
+      // that reuse its memory (LDS operations of a wave complete in order)
+      float gp1[32];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        c1[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(&sh.w1[(32 * h + sl) * kCtx + 8 * g]), bx, zero16, 0,
-                                                        0, 0);
+      for (int j = 0; j < 32; ++j) gp1[j] = gp1s[j * 64 + lane];
+      asm volatile("" ::: "memory");
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
           const int u = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // u + 1 for r + 1
-          const uint32_t dp = f32x2_to_bf16x2(c3[h][r] * gelu_grad_f(c1[h][r] + sh.b1[u]),
-                                              c3[h][r + 1] * gelu_grad_f(c1[h][r + 1] + sh.b1[u + 1]));
-          T.d1[u * 32 + sl] = (uint16_t)dp;
-          T.d1[(u + 1) * 32 + sl] = (uint16_t)(dp >> 16);
+          const uint32_t dp = f32x2_to_bf16x2(c3[h][r] * gp1[16 * h + r], c3[h][r + 1] * gp1[16 * h + r + 1]);
+          store_pair(T.d1, stg<kHid>(u, sl), stg<kHid>(u + 1, sl), dp);
+        }
+      // dZ2 into its staging rows (the B operand above holds it packed)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+          const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);
+          const uint32_t dp = bd[2 * h + (r >> 3)][(r & 7) >> 1];
+          store_pair(T.d2, stg<kHid>(o2, sl), stg<kHid>(o2 + 1, sl), dp);
         }
       {
         const uint4 xv = __builtin_bit_cast(uint4, bx);
         const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
-        for (int j = 0; j < 8; ++j) T.x[(8 * g + j) * 32 + sl] = (uint16_t)(xs[j >> 1] >> (16 * (j & 1)));
+        for (int j = 0; j < 8; ++j) T.x[stg<kCtx>(8 * g + j, sl)] = (uint16_t)(xs[j >> 1] >> (16 * (j & 1)));
       }
       if (g == 0) {
         T.dout[sl] = f32_to_bf16(dout0);
@@ -519,46 +565,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         db30 += dout0;
         db31 += dout1;
       }
-      // bias gradients of this wave's symbols: row sums (lane = row) over its 32 symbols
-      {
-        float s1 = 0.f, s2 = 0.f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint4 v1 = *(const uint4*)&T.d1[lane * 32 + 8 * j];
-          const uint4 v2 = *(const uint4*)&T.d2[lane * 32 + 8 * j];
-          const uint32_t w1s[4] = {v1.x, v1.y, v1.z, v1.w};
-          const uint32_t w2s[4] = {v2.x, v2.y, v2.z, v2.w};
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            s1 += __uint_as_float(w1s[k] << 16) + __uint_as_float(w1s[k] & 0xFFFF0000u);
-            s2 += __uint_as_float(w2s[k] << 16) + __uint_as_float(w2s[k] & 0xFFFF0000u);
-          }
-        }
-        db1 += s1;
-        db2 += s2;
-      }
       __syncthreads();
       // This wave's slices of the weight gradients over the 4 x 32 symbols of the block
       // (v_mfma_f32_16x16x32_bf16: lane l holds A row / B column l & 15 and K slots 8 (l >> 4) ..).
       //   dW2 rows 16w.. (16 x 64) += dZ2^T (16 x 32 s) H1 (32 s x 64)
       //   dW1 rows 16w.. (16 x 16) += dZ1^T (16 x 32 s) X (32 s x 16)
       //   dW3 columns 16w.. (2 x 16, rows padded to 16) += dout^T (2 x 32 s) H2 (32 s x 16)
+      //   db2, db1 rows 16w.. += dZ2^T, dZ1^T (16 x 32 s) times a matrix of ones (32 s x 16)
       {
         const int r16 = lane & 15, g16 = lane >> 4;
         const int row = 16 * wave + r16;
+        const bf16x8 ones = __builtin_bit_cast(bf16x8, make_uint4(0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u));
 #pragma unroll
         for (int src = 0; src < 4; ++src) {
           const RateWaveTmp& S = wt[src];
-          const bf16x8 a2 = load8(&S.d2[row * 32 + 8 * g16]);
+          const bf16x8 a2 = load8(&S.d2[stg<kHid>(row, 8 * g16)]);
 #pragma unroll
           for (int nt = 0; nt < 4; ++nt)
-            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, load8(&S.h1[(16 * nt + r16) * 32 + 8 * g16]),
+            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, load8(&S.h1[stg<kHid>(16 * nt + r16, 8 * g16)]),
                                                                 acc2[nt], 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(&S.d1[row * 32 + 8 * g16]),
-                                                          load8(&S.x[r16 * 32 + 8 * g16]), acc1, 0, 0, 0);
+          accb2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, ones, accb2, 0, 0, 0);
+          const bf16x8 a1 = load8(&S.d1[stg<kHid>(row, 8 * g16)]);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, load8(&S.x[stg<kCtx>(r16, 8 * g16)]), acc1, 0, 0, 0);
+          accb1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, ones, accb1, 0, 0, 0);
           const bf16x8 ad = r16 < 2 ? load8(&S.dout[r16 * 32 + 8 * g16])
                                     : __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-          acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, load8(&S.h2[row * 32 + 8 * g16]), acc3, 0, 0, 0);
+          acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, load8(&S.h2[stg<kHid>(row, 8 * g16)]), acc3, 0, 0, 0);
         }
       }
       __syncthreads();
@@ -583,8 +615,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (loss_out) atomicAdd(loss_out, (double)lsum);
   }
   if constexpr (GRAD) {
-    // the waves' slices are disjoint; the bias sums of the four waves are added in LDS (reusing
-    // the staging area), then one atomic per value
+    // the waves' slices are disjoint (the output-layer bias sums of the four waves are added in
+    // LDS, reusing the staging area), then one atomic per value
     float* acc = (float*)wt;
     for (int j = tid; j < kWPerAttr + kBPerAttr; j += 256) acc[j] = 0.f;
     __syncthreads();
@@ -597,6 +629,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int nt = 0; nt < 4; ++nt) acc[kW1 + o * kHid + 16 * nt + r16] = acc2[nt][r];
         acc[o * kCtx + r16] = acc1[r];
         if (4 * g16 + r < 2) acc[kW1 + kW2 + (4 * g16 + r) * kHid + 16 * wave + r16] = acc3[r];
+        if (r16 == 0) {
+          acc[kWPerAttr + o] = accb1[r];
+          acc[kWPerAttr + kHid + o] = accb2[r];
+        }
       }
     }
 #pragma unroll
@@ -604,8 +640,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       db30 += __shfl_xor(db30, off);
       db31 += __shfl_xor(db31, off);
     }
-    atomicAdd(&acc[kWPerAttr + lane], db1);
-    atomicAdd(&acc[kWPerAttr + kHid + lane], db2);
     if (lane == 0) {
       atomicAdd(&acc[kWPerAttr + 2 * kHid], db30);
       atomicAdd(&acc[kWPerAttr + 2 * kHid + 1], db31);
@@ -801,7 +835,7 @@ int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* 
   const int nchunks = (d.n + 31) / 32;
   const int nb = std::max(1, std::min(d.blocks_per_attr > 0 ? d.blocks_per_attr : 64, (nchunks + 3) / 4));
   const size_t shared = (sizeof(RateShared) + 15) & ~(size_t)15;
-  const size_t lds = grad ? shared + 4 * sizeof(RateWaveTmp) : shared;
+  const size_t lds = shared + (grad ? 4 * sizeof(RateWaveTmp) : (size_t)kW1 * sizeof(uint16_t));
   hipStream_t st = (hipStream_t)stream;
   ProfScope ps_(K_RATE_MLP, st);
   if (grad)
