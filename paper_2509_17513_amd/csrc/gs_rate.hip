@@ -316,6 +316,21 @@ __device__ __forceinline__ void laplace_bits(float y, float m, float b, float q,
   db = -dlb * kLog2e;
 }
 
+// Accumulator rows of the lane (o = 32 h + 8 (r / 4) + 4 g + (r & 3), r = 0..15) of a bias vector,
+// so that a layer's MFMA starts from its bias: four 16-byte LDS reads.
+__device__ __forceinline__ f32x16 bias_rows(const float* b, int h, int g) {
+  f32x16 v;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 x = *(const float4*)&b[32 * h + 8 * q + 4 * g];
+    v[4 * q] = x.x;
+    v[4 * q + 1] = x.y;
+    v[4 * q + 2] = x.z;
+    v[4 * q + 3] = x.w;
+  }
+  return v;
+}
+
 struct RateShared {
   uint16_t w2[kHid * kW2Row];  // [o2][w2_pos(i)], rows padded
   float w3[2 * kHid];
@@ -338,9 +353,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                   double* __restrict__ loss_out, float* __restrict__ sym_bits,
                                                   float* __restrict__ d_attrs, float* __restrict__ d_w,
                                                   float* __restrict__ d_b) {
+  // the weights in a static LDS array of their own, the staging in the dynamic one: the compiler
+  // then knows that staging stores leave the weights unchanged, and schedules weight reads early
+  __shared__ __align__(16) RateShared sh;
   extern __shared__ __align__(16) char smem[];
-  RateShared& sh = *(RateShared*)smem;
-  RateWaveTmp* wt = (RateWaveTmp*)(smem + ((sizeof(RateShared) + 15) & ~(size_t)15));
+  RateWaveTmp* wt = (RateWaveTmp*)smem;
   const int a = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sl = lane & 31, g = lane >> 5;
@@ -392,6 +409,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   float* gp1s = (float*)T.d2;  // spans d2 and d1
   const f32x16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
+  // the context features and the attribute value of a chunk's symbol, loaded one chunk ahead
+  auto fetch = [&](int it, bf16x8& x, float& y) {
+    const int s = ((it * gridDim.x + blockIdx.x) * 4 + wave) * 32 + sl;
+    const bool v = it < iters && s < n;
+    x = v ? load8(ctx + (size_t)s * kCtx + 8 * g) : __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+    y = v ? ya[s] : 0.f;
+  };
+  bf16x8 bx_next;
+  float y_next;
+  fetch(0, bx_next, y_next);
   for (int it = 0; it < iters; ++it) {
     // Weights, biases and operand fragments are re-read from LDS every chunk rather than held in
     // registers across the loop (holding all of them would exceed the register file).
@@ -399,26 +426,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int chunk = (it * gridDim.x + blockIdx.x) * 4 + wave;
     const int sidx = chunk * 32 + sl;
     const bool valid = sidx < n;
+    const bf16x8 bx = bx_next;
+    const float y_sym = y_next;
+    fetch(it + 1, bx_next, y_next);
     // ---- layer 1: Z1^T (64 x 32) = W1 (64 x 16) X^T (16 x 32)
-    const bf16x8 bx = valid ? load8(ctx + (size_t)sidx * kCtx + 8 * g)
-                            : __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
     f32x16 c1[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
       c1[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(GRAD ? w1f[h] : load8(&w1s[(32 * h + sl) * kCtx + 8 * g]), bx,
-                                                      zero16, 0, 0, 0);
-    // bias + GELU + BF16, packed straight into the B operand of layer 2
+                                                      bias_rows(sh.b1, h, g), 0, 0, 0);
+    // GELU + BF16 (the MFMA started from the bias), packed straight into the B operand of layer 2
     uint32_t b2[4][4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b2[ks][j] = 0u;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 16; r += 2) {
         const int o = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o + 1 for r + 1
-        const float x0 = c1[h][r] + sh.b1[o], x1 = c1[h][r + 1] + sh.b1[o + 1];
+        const float x0 = c1[h][r], x1 = c1[h][r + 1];
         const float s0 = gelu_s(x0), s1 = gelu_s(x1);
         const uint32_t hp = f32x2_to_bf16x2(x0 * s0, x1 * s1);
         if constexpr (GRAD) {
@@ -431,25 +455,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         b2[2 * h + (r >> 3)][(r & 7) >> 1] = hp;
       }
     // ---- layer 2: Z2^T (64 x 32) = W2 (64 x 64) H1^T (64 x 32), K in 4 steps of 16
-    f32x16 c2[2];
+    // (the two row halves alternate, so that consecutive MFMAs are independent)
+    f32x16 c2[2] = {bias_rows(sh.b2, 0, g), bias_rows(sh.b2, 1, g)};
 #pragma unroll
-    for (int h2 = 0; h2 < 2; ++h2) {
-      c2[h2] = zero16;
+    for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
+      for (int h2 = 0; h2 < 2; ++h2)
         c2[h2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            load8(&sh.w2[(32 * h2 + sl) * kW2Row + 16 * ks + 8 * g]), __builtin_bit_cast(bf16x8, make_uint4(b2[ks][0], b2[ks][1], b2[ks][2], b2[ks][3])),
-            c2[h2], 0, 0, 0);
-      }
-    }
-    // ---- bias + GELU; layer 3 (2 outputs) on the VALU, each lane holds half the hidden units
+            load8(&sh.w2[(32 * h2 + sl) * kW2Row + 16 * ks + 8 * g]),
+            __builtin_bit_cast(bf16x8, make_uint4(b2[ks][0], b2[ks][1], b2[ks][2], b2[ks][3])), c2[h2], 0, 0, 0);
+    // ---- GELU; layer 3 (2 outputs) on the VALU, each lane holds half the hidden units
     float o0 = 0.f, o1 = 0.f;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 16; r += 2) {
         const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o2 + 1 for r + 1
-        const float z0 = c2[h][r] + sh.b2[o2], z1 = c2[h][r + 1] + sh.b2[o2 + 1];
+        const float z0 = c2[h][r], z1 = c2[h][r + 1];
         const float s0 = gelu_s(z0), s1 = gelu_s(z1);
         if constexpr (GRAD) {  // keep GELU'(Z2) for the backward
           c2[h][r] = gelu_grad_s(z0, s0);
@@ -470,11 +492,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     o1 += sh.b3[1];
     // ---- discretised Laplace rate of the symbol
     const float m = o0;
-    const float sp = fmaxf(o1, 0.f) + log1pf(expf(-fabsf(o1)));
+    const float sp = fmaxf(o1, 0.f) + log1pf(__expf(-fabsf(o1)));
     const float bsc = sp + q * (1.f / 16.f);
     float bits = 0.f, dby = 0.f, dbb = 0.f, wsym = 0.f;
     if (valid) {
-      const float y = ya[sidx];
+      const float y = y_sym;
       float yh;
       if (ra.mode == 0) {
         yh = rintf(y / q) * q;
@@ -500,34 +522,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     if constexpr (GRAD) {
       const float dout0 = valid ? -ra.wfit * dby : 0.f;
-      const float sig1 = __builtin_amdgcn_rcpf(1.f + expf(-o1));
+      const float sig1 = __builtin_amdgcn_rcpf(1.f + __expf(-o1));
       const float dout1 = valid ? ra.wfit * dbb * sig1 : 0.f;
-      // dZ2 = (W3^T dout) * GELU'(Z2), packed into the B operand of dH1^T = W2^T dZ2^T
+      // dH2^T (64 x 32) = W3^T (64 x 2) dout (2 x 32) on the FP32 MFMA (v_mfma_f32_32x32x2_f32: lane l
+      // gives A row l & 31 and B column l & 31 at K = l >> 5, i.e. W3 row g and dout_g of the lane's
+      // symbol; the accumulator has the rows of c2), then dZ2 = dH2 * GELU'(Z2), packed into the B
+      // operand of dH1^T = W2^T dZ2^T
+      f32x16 dh[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        dh[h] = __builtin_amdgcn_mfma_f32_32x32x2f32(sh.w3[g * kHid + 32 * h + sl], g ? dout1 : dout0, zero16, 0, 0, 0);
       uint32_t bd[4][4];
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bd[ks][j] = 0u;
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
-          const int o2 = 32 * h + 8 * (r >> 2) + 4 * g + (r & 3);  // o2 + 1 for r + 1
-          const float dh0 = dout0 * sh.w3[o2] + dout1 * sh.w3[kHid + o2];
-          const float dh1 = dout0 * sh.w3[o2 + 1] + dout1 * sh.w3[kHid + o2 + 1];
-          bd[2 * h + (r >> 3)][(r & 7) >> 1] = f32x2_to_bf16x2(dh0 * c2[h][r], dh1 * c2[h][r + 1]);
+          bd[2 * h + (r >> 3)][(r & 7) >> 1] = f32x2_to_bf16x2(dh[h][r] * c2[h][r], dh[h][r + 1] * c2[h][r + 1]);
         }
       f32x16 c3[2];
 #pragma unroll
-      for (int hi = 0; hi < 2; ++hi) {
-        c3[hi] = zero16;
+      for (int ks = 0; ks < 4; ++ks) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
+        for (int hi = 0; hi < 2; ++hi) {
           // W2^T rows i, K = o2 in the order 16 ks + 4 g + {0..3, 8..11}: a column of W2
           const uint16_t* col = &sh.w2[(16 * ks + 4 * g) * kW2Row + 32 * hi + w2_pos(sl)];
           c3[hi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              load_col8(col),
-              __builtin_bit_cast(bf16x8, make_uint4(bd[ks][0], bd[ks][1], bd[ks][2], bd[ks][3])), c3[hi], 0, 0, 0);
+              load_col8(col), __builtin_bit_cast(bf16x8, make_uint4(bd[ks][0], bd[ks][1], bd[ks][2], bd[ks][3])),
+              ks == 0 ? zero16 : c3[hi], 0, 0, 0);
         }
       }
       // dZ1 = dH1 * GELU'(Z1): every stashed value is read before the d1 and d2 staging writes
@@ -834,8 +855,7 @@ int gs_rate_model(const gs_rate_desc* desc, const float* attrs, const uint16_t* 
   const bool grad = d_w || d_b;
   const int nchunks = (d.n + 31) / 32;
   const int nb = std::max(1, std::min(d.blocks_per_attr > 0 ? d.blocks_per_attr : 64, (nchunks + 3) / 4));
-  const size_t shared = (sizeof(RateShared) + 15) & ~(size_t)15;
-  const size_t lds = shared + (grad ? 4 * sizeof(RateWaveTmp) : (size_t)kW1 * sizeof(uint16_t));
+  const size_t lds = grad ? 4 * sizeof(RateWaveTmp) : (size_t)kW1 * sizeof(uint16_t);
   hipStream_t st = (hipStream_t)stream;
   ProfScope ps_(K_RATE_MLP, st);
   if (grad)
