@@ -1410,16 +1410,22 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
 }
 
 // Constant factors of the nine per-entry gradient sums of the backward (mean x, y; conic A, B, C;
-// opacity; colour r, g, b), applied once to each sum instead of to every pixel's term.
+// opacity; colour r, g, b), applied once to each sum instead of to every pixel's term. The opacity
+// sum is taken as the sum of dp = dL/dalpha * o * G (a term the mean and conic sums form anyway)
+// and divided by the entry's opacity o when it is flushed.
 constexpr float kGradScale[9] = {-kLn2, -kLn2, -0.5f, -1.f, -0.5f, 1.f, 1.f, 1.f, 1.f};
+
+// A float in LDS, addressed with 32-bit offsets.
+typedef __attribute__((address_space(3))) float lds_float;
 
 // Wave reduction of nine per-lane values. Values 0..7 are reduce-scattered:
 // each halving step pairs two values and exchanges the halves of the wave
 // that keep them (v_permlane32_swap, then v_permlane16_swap across rows, then a
 // row mirror), so that every aligned group of 8 lanes ends with the sum of one
 // value over all 64 lanes, which a butterfly inside the group completes. Value
-// 8 is reduced to every lane. On return g[0] holds the group's value and g[8]
-// value 8.
+// 8 is only summed inside each aligned group of 8 lanes (the same butterfly);
+// the caller adds the eight group sums. On return g[0] holds the group's value
+// and g[8] the group's sum of value 8.
 __device__ __forceinline__ void reduce_scatter9(float* g, int lane) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -1444,15 +1450,6 @@ __device__ __forceinline__ void reduce_scatter9(float* g, int lane) {
   v += dpp<kDppHalfMirror>(v);
   v += dpp<kDppXor2>(v);
   v += dpp<kDppXor1>(v);
-  v += dpp<kDppMirror>(v);
-  {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-  {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
   g[8] = v;
 }
 
@@ -1551,6 +1548,10 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
     reduce_scatter9(pr, lane);
     vid = (int)(pr[0] * (1.f / 64.f) + 0.5f);
   }
+  // after the reduction lane 8k adds value vid and lane 8k + 1 the group's sum of value 8 to the
+  // entry's LDS sums (an LDS atomic each; the eight value-8 adds meet on one address)
+  const bool adder = (lane & 7) < 2;
+  lds_float* const g_slot = (lds_float*)&s_g[0][0] + ((lane & 7) == 0 ? vid : 8);
   const int nb = d.batch;  // entries staged per round (<= kTilePix, threads t < nb stage one each)
   for (int top = (int)ktop; top > 0; top -= nb) {
     const int lo = max(0, top - nb);
@@ -1643,15 +1644,14 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
           // mean and conic gradients without their constant factors, which kGradScale applies to
           // the sums: conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2), so dL/dmx = -ln 2 dp (2 a2 dx + b2 dy)
           // = -ln 2 dp (u + a2 dx), dL/dmy = -ln 2 dp (b2 dx + 2 c2 dy) = -ln 2 dp (b2 dx + v + v),
-          // dL/d(A, B, C) = -(1/2, 1, 1/2) dp (dx^2, dx dy, dy^2)
+          // dL/d(A, B, C) = -(1/2, 1, 1/2) dp (dx^2, dx dy, dy^2), dL/do = sum dp / o
           const float pdx = dp * ev.dx, pdy = dp * ev.dy;
           float g[9] = {dp * fmaf(cb.x, ev.dx, ev.u), dp * (fmaf(cb.y, ev.dx, ev.v) + ev.v), pdx * ev.dx, pdx * ev.dy,
-                        pdy * ev.dy, dl * ev.G, gr, gg, gb};
+                        pdy * ev.dy, dp, gr, gg, gb};
           reduce_scatter9(g, lane);
-          // the group leaders add their value, lane 1 value 8 (one LDS atomic, per-lane addresses)
-          const bool lead = (lane & 7) == 0;
-          const float x = lead ? g[0] : g[8];
-          if ((lead || lane == 1) && x != 0.f) atomicAdd(&s_g[j][lead ? vid : 8], x);
+          const float x = (lane & 7) == 0 ? g[0] : g[8];
+          if (adder && x != 0.f)
+            __hip_atomic_fetch_add(g_slot + j * kGradLds, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
     }
@@ -1659,11 +1659,12 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
     if (t < cnt) {
       const uint32_t g_i = __float_as_uint(s_a[t].w);
       float* dst = g2d + (recbase + g_i) * kGradStride;
+      const float inv_o = __builtin_amdgcn_rcpf(s_a[t].z);
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
         const float x = s_g[t][v];
         if (x != 0.f) {
-          unsafeAtomicAdd(dst + v, x * kGradScale[v]);
+          unsafeAtomicAdd(dst + v, x * (v == 5 ? inv_o : kGradScale[v]));
           s_g[t][v] = 0.f;
         }
       }
@@ -1802,6 +1803,8 @@ __global__ __launch_bounds__(kBwd2Threads) void k_raster_bwd2(RenderDims d, Stat
     reduce_scatter9(pr, lane);
     vid = (int)(pr[0] * (1.f / 64.f) + 0.5f);
   }
+  const bool adder = (lane & 7) < 2;
+  lds_float* const g_slot = (lds_float*)&s_g[0][0] + ((lane & 7) == 0 ? vid : 8);
   const int nb = d.batch;
   for (int top = (int)ktop; top > 0; top -= nb) {
     const int lo = max(0, top - nb);
@@ -1894,26 +1897,27 @@ __global__ __launch_bounds__(kBwd2Threads) void k_raster_bwd2(RenderDims d, Stat
           g[2] += pdx * ev.dx;
           g[3] += pdx * ev.dy;
           g[4] += pdy * ev.dy;
-          g[5] += dl * ev.G;
+          g[5] += dp;
           g[6] += gr;
           g[7] += gg;
           g[8] += gb;
         }
         reduce_scatter9(g, lane);
-        const bool lead = (lane & 7) == 0;
-        const float x = lead ? g[0] : g[8];
-        if ((lead || lane == 1) && x != 0.f) atomicAdd(&s_g[j][lead ? vid : 8], x);
+        const float x = (lane & 7) == 0 ? g[0] : g[8];
+        if (adder && x != 0.f)
+            __hip_atomic_fetch_add(g_slot + j * kGradLds, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
     __syncthreads();
     for (int e = t; e < cnt; e += kBwd2Threads) {
       const uint32_t g_i = __float_as_uint(s_a[e].w);
       float* dst = g2d + (recbase + g_i) * kGradStride;
+      const float inv_o = __builtin_amdgcn_rcpf(s_a[e].z);
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
         const float x = s_g[e][v];
         if (x != 0.f) {
-          unsafeAtomicAdd(dst + v, x * kGradScale[v]);
+          unsafeAtomicAdd(dst + v, x * (v == 5 ? inv_o : kGradScale[v]));
           s_g[e][v] = 0.f;
         }
       }
