@@ -138,6 +138,33 @@ def hist_bits(attrs, step):
     return out
 
 
+def bucketed_hist_bits(attrs, step, bucket):
+    """Histogram rate conditioned on a bucket per Gaussian (e.g. its layer x position octant):
+    per attribute -sum_i log2(n(b_i, k_i) / N(b_i)), the empirical conditional entropy times N.
+    It is the rate a coder that knows each Gaussian's bucket reaches with per-bucket histograms;
+    with one bucket it is hist_bits. attrs [A][N], bucket [N] integer labels."""
+    attrs = np.asarray(attrs, np.float32)
+    bucket = np.asarray(bucket)
+    A, N = attrs.shape
+    out = np.zeros(A)
+    _, bi = np.unique(bucket, return_inverse=True)
+    nb = np.bincount(bi).astype(np.float64)
+    for a in range(A):
+        k = np.rint(attrs[a].astype(np.float64) / np.float64(np.float32(step)))
+        _, ki = np.unique(k, return_inverse=True)
+        _, cnt = np.unique(bi.astype(np.int64) * (ki.max() + 1) + ki, return_inverse=True)
+        n_bk = np.bincount(cnt).astype(np.float64)[cnt]
+        out[a] = -np.log2(n_bk / nb[bi]).sum()
+    return out
+
+
+def layer_octant_bucket(means, layer):
+    """Bucket label of each Gaussian: its layer (1..L) times the octant of its mean (sign of x, y, z)."""
+    m = np.asarray(means, np.float64)
+    octant = (m[0] >= 0).astype(np.int64) + 2 * (m[1] >= 0) + 4 * (m[2] >= 0)
+    return np.asarray(layer, np.int64) * 8 + octant
+
+
 # ------------------------------------------------------------------- context
 def context(means, extent, layer_of):
     """16 features per Gaussian: mean / extent (3), sin and cos of pi 2^k mean / extent for

@@ -3,8 +3,9 @@ the trained rate network gains over the method without it.
 
 A student scene is fitted to renders of a seeded teacher scene (all views and six nested layers
 at once). Checks: the layer-weighted L1 falls; the trained MLP's evaluation-mode rate is within 2%
-of the empirical-histogram rate of the final attributes (or below it: a conditional-coding gain
-from the context); the MLP's estimate error is no worse than a context-free Laplace fit and it
+of the empirical-histogram rate of the final attributes, on either side (the histogram rate
+conditioned on layer x position octant is reported beside it, as the rate a context could reach);
+the MLP's estimate error is no worse than a context-free Laplace fit and it
 strictly gains on the attributes the significance ordering makes layer-dependent (scales,
 opacity); and training with the rate term (lambda_rate > 0) cuts the histogram rate relative to
 lambda_rate = 0 at a small, reported L1 increase.
@@ -49,7 +50,7 @@ def _train(tr, steps):
 
 def test_joint_training_and_rate_network_gain():
     print("\n[case] joint training lambda_rate = 0 and > 0, 20k Gaussians, 4 views 240x136", flush=True)
-    from oracle.rate import gaussian_fit_bits, laplace_fit_bits
+    from oracle.rate import gaussian_fit_bits, laplace_fit_bits, layer_of
     steps = 120
     tr0 = _setup(0.0)
     l0 = _train(tr0, steps)
@@ -60,9 +61,14 @@ def test_joint_training_and_rate_network_gain():
     lap = laplace_fit_bits(attrs, 1 / 64)
     gau = gaussian_fit_bits(attrs, 1 / 64)
     R_mlp, R_hist, R_lap, R_gau = mlp.sum(), hist.sum(), lap.sum(), gau.sum()
-    print(f"bits: mlp {R_mlp:.0f} hist {R_hist:.0f} laplace-fit {R_lap:.0f} gaussian-fit {R_gau:.0f}; "
-          f"mlp vs hist {(R_mlp - R_hist) / R_hist:+.4f}", flush=True)
-    assert R_mlp <= 1.02 * R_hist
+    from oracle.rate import bucketed_hist_bits, layer_octant_bucket
+    n = attrs.shape[1]
+    R_bkt = bucketed_hist_bits(attrs, 1 / 64, layer_octant_bucket(tr0.p[0:3].cpu().numpy(),
+                                                                  layer_of(n, tr0.st.level_counts))).sum()
+    print(f"bits: mlp {R_mlp:.0f} hist {R_hist:.0f} layer-x-octant hist {R_bkt:.0f} laplace-fit {R_lap:.0f} "
+          f"gaussian-fit {R_gau:.0f}; mlp vs hist {(R_mlp - R_hist) / R_hist:+.4f}", flush=True)
+    # the judge, two-sided: within 2% of the histogram rate of the final attributes
+    assert abs(R_mlp - R_hist) <= 0.02 * R_hist
     e_mlp = abs(R_mlp - R_hist) / R_hist
     e_lap = abs(R_lap - R_hist) / R_hist
     assert e_mlp <= e_lap + 1e-3

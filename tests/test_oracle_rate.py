@@ -189,3 +189,25 @@ def test_context_free_fits_match_the_histogram_on_their_own_distributions():
     assert abs(lap[0] / h[0] - 1) < 5e-3 and abs(gau[1] / h[1] - 1) < 5e-3
     assert lap[1] > 1.01 * h[1] and gau[0] > 1.01 * h[0]
     assert np.all(lap >= h) and np.all(gau >= h)
+
+
+def test_bucketed_histogram_by_hand_and_its_bounds():
+    """The bucketed histogram rate: a hand count on a tiny case, one bucket == the plain histogram,
+    conditioning never adds bits, and buckets that split the symbols exactly remove them."""
+    q = 1.0 / 64
+    y = np.array([[0, 0, 1, 1, 1, 2]], np.float32) * q
+    b = np.array([0, 0, 0, 1, 1, 1])
+    # bucket 0 holds symbols {0: 2, 1: 1} of 3, bucket 1 {1: 2, 2: 1} of 3
+    want = -(2 * math.log2(2 / 3) + math.log2(1 / 3)) * 2
+    assert abs(rate.bucketed_hist_bits(y, q, b)[0] - want) < 1e-12
+    rng = np.random.default_rng(4)
+    a = rng.laplace(0, 0.1, (3, 5000)).astype(np.float32)
+    one = rate.bucketed_hist_bits(a, q, np.zeros(5000, int))
+    assert np.allclose(one, rate.hist_bits(a, q), rtol=0, atol=1e-6)
+    bk = rng.integers(0, 16, 5000)
+    assert np.all(rate.bucketed_hist_bits(a, q, bk) <= rate.hist_bits(a, q) + 1e-9)
+    # a bucket equal to the symbol itself leaves nothing to code
+    k = np.rint(a[0].astype(np.float64) / q).astype(np.int64)
+    assert abs(rate.bucketed_hist_bits(a[:1], q, k)[0]) < 1e-9
+    m = np.array([[-1.0, 1.0, -1.0, 1.0], [-1.0, -1.0, 1.0, 1.0], [1.0, 1.0, 1.0, -1.0]])
+    assert list(rate.layer_octant_bucket(m, [1, 1, 2, 2])) == [8 + 4, 8 + 5, 16 + 6, 16 + 3]
