@@ -85,6 +85,7 @@ def code_text(src: str) -> str:
 KERNEL_SOURCES = {
     "rate_mlp": ("gs_rate.hip",),
     "motion_fwd": ("gs_motion.hip",), "motion_bwd": ("gs_motion.hip",), "motion_wgrad": ("gs_motion.hip",),
+    "motion_table": ("gs_motion.hip",),
     "ssim_fwd": ("gs_loss.hip",), "ssim_bwd": ("gs_loss.hip",),
 }
 RENDER_SOURCES = ("gs_render.hip", "gs_api.hip", "gs_internal.h")

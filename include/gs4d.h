@@ -273,8 +273,9 @@ int gs_entropy_model(const gs_entropy_desc* desc, const float* attrs, double* bi
  * features, 2^15 entries per level, resolutions floor(16 b^l) from 16 to 1024; trilinear
  * interpolation of the cell corners, indexed densely while (N + 1)^3 <= 2^15, else by the
  * spatial hash (i ^ j 2654435761 ^ k 805459861) mod 2^15) inside the scene box, and two MLPs
- * (32 -> 64 -> 64 -> 3 and 32 -> 64 -> 64 -> 4, ReLU, FP32) predict each Gaussian's translation
- * d_mu and rotation quaternion dq = (1 + o0, o1, o2, o3), written as the residual channels 0..6
+ * (32 -> 64 -> 64 -> 3 and 32 -> 64 -> 64 -> 4, ReLU, FP32 on the matrix cores) predict each
+ * Gaussian's translation d_mu and rotation quaternion dq = (1 + o0, o1, o2, o3), written as the
+ * residual channels 0..6
  * of a frame (mu_t = mu_{t-1} + d_mu, q_t = dq (x) q_{t-1} in gs_render_forward's composition).
  *  table    [16][2^15][2] float features (gs_motion_sizes gives the float count)
  *  weights  W1 [64][32], b1, W2 [64][64], b2, W3 [3][64], b3 of the translation MLP, then the
@@ -283,9 +284,11 @@ int gs_entropy_model(const gs_entropy_desc* desc, const float* attrs, double* bi
  *  means    rows 0..2 of an array of row stride row_stride (the previous frame's positions)
  *  out      rows 0..6 of an array of row stride row_stride (a frame's residual block)
  *  d_out    rows 0..6 of dL/d(those residuals), row stride row_stride
- *  d_table, d_weights   accumulated (+=) with float atomics
- *  ws       gs_motion_workspace_size(n) bytes (the per-Gaussian activations and gradients the
- *           weight gradients are summed from)
+ *  d_table, d_weights   accumulated (+=): d_table from per-chunk partial tables summed in a
+ *           second pass (no atomics into it), d_weights from per-wave partial sums added with
+ *           float atomics
+ *  ws       gs_motion_workspace_size(n) bytes (the feature gradients of the Gaussians, the
+ *           waves' partial weight gradients and 8 partial tables of 4 MB)
  * Errors: GS_ERR_INVALID_ARG for n < 0, row_stride < n, a degenerate box or NULL buffers. */
 typedef struct {
   int32_t n;

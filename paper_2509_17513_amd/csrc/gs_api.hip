@@ -161,7 +161,7 @@ const char* kKernelNames[K_COUNT] = {
     "tile_ranges", "bin_emit", "raster_fwd", "zero", "raster_bwd", "project_bwd", "compose_bwd", "rate_ctx",
     "rate_mlp", "rate_hist_minmax", "rate_hist_count", "rate_hist_bits", "adam", "bin_gather", "row_count", "row_emit",
     "ssim_fwd", "ssim_bwd", "psi", "maps_range", "maps_keys", "maps_write", "maps_decode", "ent_stats", "ent_hist", "ent_cdf", "ent_eval", "motion_fwd", "motion_bwd",
-    "motion_wgrad"};
+    "motion_wgrad", "motion_table"};
 }  // namespace
 
 int prof_begin(int id, hipStream_t st) {

@@ -43,6 +43,7 @@ enum KernelId {
   K_MOTION_FWD,
   K_MOTION_BWD,
   K_MOTION_WGRAD,
+  K_MOTION_TABLE,
   K_COUNT
 };
 
