@@ -344,6 +344,18 @@ int gs_workspace_stats(void* ws, void* stream, gs_stats* out);
  * captured graph keeps the variant it captured). Returns the previous setting. */
 int gs_set_work_counters(int enable);
 
+/* Process-wide switch of the deterministic backward (off at load), a debug aid: while it is on,
+ * gs_workspace_size includes 144 bytes per (view, Gaussian) more and gs_render_backward runs a
+ * variant whose gradients and loss are the same bits on every run with the same inputs. The raster
+ * backward then adds each wave's per-entry sums into 128-bit fixed-point accumulators (the value
+ * times 2^64, saturated at 2^62, bits below 2^-64 dropped) with integer atomics, whose result does
+ * not depend on the order, and converts them once; every later sum of the backward already has a
+ * fixed order. It uses one pixel per lane (bwd_pixels is ignored) and no work counters, and is
+ * slower than the default, whose float atomics leave ulp-level run-to-run differences. Set it
+ * before sizing the workspace and before the forward whose state the backward uses. Host-only,
+ * thread-safe. Returns the previous setting. */
+int gs_set_deterministic(int enable);
+
 /* Text of an error code, and the last HIP error message of this thread. */
 const char* gs_error_string(int code);
 const char* gs_last_error(void);

@@ -6,7 +6,7 @@ package does not require a GPU; calling a render entry point does, and fails
 loudly if the library has not been built.
 """
 from .render import (LossWorkspace, RenderFunction, RenderSettings, Workspace, autotune, autotune_cached, color_loss,
-                     render, render_backward, render_forward, work_counters)
+                     deterministic, render, render_backward, render_forward, work_counters)
 
 __all__ = ["LossWorkspace", "RenderFunction", "RenderSettings", "Workspace", "autotune", "autotune_cached", "color_loss",
-           "render", "render_backward", "render_forward", "work_counters"]
+           "deterministic", "render", "render_backward", "render_forward", "work_counters"]

@@ -102,6 +102,7 @@ SIGNATURES = {
     "gs_last_error": ([], ctypes.c_char_p),
     "gs_workspace_stats": ([P, P, P], ctypes.c_int),
     "gs_set_work_counters": ([ctypes.c_int], ctypes.c_int),
+    "gs_set_deterministic": ([ctypes.c_int], ctypes.c_int),
     "gs_zero": ([P, SZ, P], ctypes.c_int),
     "gs_profile_enable": ([ctypes.c_int], ctypes.c_int),
     "gs_profile_collect": ([I32, P, P], ctypes.c_int),

@@ -113,6 +113,7 @@ int make_dims(const gs_settings* s, int32_t n, int32_t F, int32_t V, int64_t cap
   if (d.batch != 64 && d.batch != 128 && d.batch != 256) return fail_arg("lds_batch must be 0, 64, 128 or 256");
   d.bwd_pixels = s->bwd_pixels == 0 ? 1 : s->bwd_pixels;
   if (d.bwd_pixels != 1 && d.bwd_pixels != 2) return fail_arg("bwd_pixels must be 0, 1 or 2");
+  d.det = deterministic() ? 1 : 0;
   d.n_sort_chunks = (n + kSortChunk - 1) / kSortChunk;
   d.n_bin_chunks = (n + d.bin_chunk - 1) / d.bin_chunk;
   d.n_row_segs = (n + d.row_seg - 1) / d.row_seg;
@@ -129,6 +130,8 @@ int report_arg(const char* msg) { return fail_arg(msg); }
 
 std::atomic<int> g_work_counting{0};
 bool work_counting() { return g_work_counting.load(std::memory_order_relaxed) != 0; }
+std::atomic<int> g_deterministic{0};
+bool deterministic() { return g_deterministic.load(std::memory_order_relaxed) != 0; }
 int report_hip(hipError_t e, const char* where) { return fail_hip(e, where); }
 int require_device() { return check_device(); }
 
@@ -215,6 +218,10 @@ Layout make_layout(const RenderDims& d) {
   lo.composed = take((size_t)d.F * d.Rc * d.n * 4);
   lo.d_composed = take((size_t)d.F * d.Rc * d.n * 4);
   lo.check = take(256);  // the autotuner's image checksum
+  // deterministic backward: 128-bit fixed-point sums of the nine gradient values per (view,
+  // Gaussian) and of the loss
+  lo.grad2d_fx = take(d.det ? Bn * 9 * 16 : 0);
+  lo.loss_fx = take(d.det ? 16 : 0);
   // the pair lists are last, so every other offset is independent of their capacity
   lo.lists = take((size_t)d.capacity * 4);
   lo.row_lists = take((size_t)d.row_capacity * 8);
@@ -362,19 +369,24 @@ int gs_render_backward(const gs_settings* s, int32_t n, const float* params, int
   char* w = (char*)ws;
   hipError_t e;
   if ((e = launch_zero(w + lo.status + offsetof(Status, bwd_evals), 16, st)) != hipSuccess) return fail_hip(e, "zero");
+  if (d.det && (e = launch_zero(w + lo.loss_fx, 16, st)) != hipSuccess) return fail_hip(e, "zero");
   if (n == 0) {
     if (loss_out || target) {
       // the loss of an empty scene still depends on the background; run the raster backward for it
       if ((e = launch_raster_bwd(d, w, lo, image, d_image, target, loss_out, st)) != hipSuccess)
         return fail_hip(e, "raster_bwd");
+      if (d.det && (e = launch_fx_finish(d, w, lo, loss_out, st)) != hipSuccess) return fail_hip(e, "fx_finish");
     }
     return GS_OK;
   }
   if ((e = launch_zero(w + lo.grad2d, (size_t)d.B * d.n * kGradStride * 4, st)) != hipSuccess) return fail_hip(e, "zero");
+  if (d.det && (e = launch_zero(w + lo.grad2d_fx, (size_t)d.B * d.n * 9 * 16, st)) != hipSuccess)
+    return fail_hip(e, "zero");
   if (d.Rc > 0 && (e = launch_zero(w + lo.d_composed, (size_t)d.F * d.Rc * d.n * 4, st)) != hipSuccess)
     return fail_hip(e, "zero");
   if ((e = launch_raster_bwd(d, w, lo, image, d_image, target, loss_out, st)) != hipSuccess)
     return fail_hip(e, "raster_bwd");
+  if (d.det && (e = launch_fx_finish(d, w, lo, loss_out, st)) != hipSuccess) return fail_hip(e, "fx_finish");
   if ((e = launch_project_bwd(d, params, d.Rc > 0 ? residuals : nullptr, (const float*)(w + lo.composed), cams, w, lo, d_params,
                               st)) != hipSuccess)
     return fail_hip(e, "project_bwd");
@@ -504,6 +516,8 @@ int gs_autotune_render(const gs_settings* s, int32_t n, const float* params, int
 }
 
 int gs_set_work_counters(int enable) { return g_work_counting.exchange(enable ? 1 : 0); }
+
+int gs_set_deterministic(int enable) { return g_deterministic.exchange(enable ? 1 : 0); }
 
 int gs_workspace_stats(void* ws, void* stream, gs_stats* out) {
   if (!ws || !out) return fail_arg("NULL argument");

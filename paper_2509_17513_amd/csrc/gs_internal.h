@@ -49,6 +49,7 @@ struct RenderDims {
   int wave_layout;                    // 1: 8x8 quadrant per wave, 2: 16x4 strip per wave
   int batch;                          // list entries staged in LDS per round of the raster passes
   int bwd_pixels;                     // pixels per lane of the backward raster: 1 or 2
+  int det;                            // deterministic backward (gs_set_deterministic)
   int n_bin_chunks_max, n_row_segs_max;  // at the smallest shapes (workspace sizing)
   unsigned long long capacity;      // (tile, Gaussian) pairs
   unsigned long long row_capacity;  // (tile row, Gaussian) pairs
@@ -57,13 +58,16 @@ struct RenderDims {
 // Byte offsets inside the workspace.
 struct Layout {
   size_t status, records, rects, keys0, vals0, keys1, vals1, sort_hist, bin_rec, bin_hist, row_tot, row_ranges,
-      tile_hist, tile_tot, ranges, t_final, n_last, grad2d, composed, d_composed, check, lists, row_lists, total;
+      tile_hist, tile_tot, ranges, t_final, n_last, grad2d, composed, d_composed, check, grad2d_fx, loss_fx, lists,
+      row_lists, total;
 };
 
 Layout make_layout(const RenderDims& d);
 
 // Whether the raster passes count their work (gs_set_work_counters; off by default).
 bool work_counting();
+// Whether the backward runs its deterministic variant (gs_set_deterministic; off by default).
+bool deterministic();
 
 // ---- launchers (gs_render.hip) ----
 hipError_t launch_compose_fwd(const RenderDims& d, const float* params, const float* res, float* composed,
@@ -77,6 +81,8 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
 hipError_t launch_raster_fwd(const RenderDims& d, char* ws, const Layout& lo, float* image, hipStream_t st);
 hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, const float* image,
                              const float* d_image, const float* target, float* loss_out, hipStream_t st);
+// deterministic backward: the fixed-point sums of the raster backward into grad2d (and loss_out +=)
+hipError_t launch_fx_finish(const RenderDims& d, char* ws, const Layout& lo, float* loss_out, hipStream_t st);
 hipError_t launch_project_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,
                               const gs_camera* cams, char* ws, const Layout& lo, float* d_params, hipStream_t st);
 hipError_t launch_compose_bwd(const RenderDims& d, const float* params, const float* res, const float* composed,

@@ -1453,7 +1453,30 @@ __device__ __forceinline__ void reduce_scatter9(float* g, int lane) {
   g[8] = v;
 }
 
-template <int MAXL, bool COUNT>
+// Deterministic accumulation: a float x is added to a 128-bit two's-complement fixed-point sum
+// (low word: the fraction, 2^-64 units; high word: the integer part) with two 64-bit integer
+// atomics, the carry out of the low word going into the high word. Integer addition does not
+// depend on the order, so the sum is the same on every run; bits of x below 2^-64 are dropped and
+// |x| is saturated at 2^62.
+__device__ __forceinline__ void fx_add(unsigned long long* p, float x) {
+  double a = fabs((double)x);
+  if (!(a < 0x1p62)) a = 0x1p62;
+  const double ip = floor(a);
+  unsigned long long lo = (unsigned long long)((a - ip) * 0x1p64);  // a - ip is exact and < 1
+  unsigned long long hi = (unsigned long long)ip;
+  if (x < 0.f) {  // negate the 128-bit value
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  const unsigned long long old = atomicAdd(p, lo);
+  atomicAdd(p + 1, hi + (old + lo < old ? 1ull : 0ull));
+}
+
+__device__ __forceinline__ float fx_value(const unsigned long long* p) {
+  return (float)((double)(long long)p[1] + (double)p[0] * 0x1p-64);
+}
+
+template <int MAXL, bool COUNT, bool DET>
 __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ lists,
@@ -1463,7 +1486,9 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
                                                          const float* __restrict__ image,
                                                          const float* __restrict__ d_image,
                                                          const float* __restrict__ target,
-                                                         float* __restrict__ g2d, float* __restrict__ loss_out) {
+                                                         float* __restrict__ g2d, float* __restrict__ loss_out,
+                                                         unsigned long long* __restrict__ g2d_fx,
+                                                         unsigned long long* __restrict__ loss_fx) {
   if (st->overflow) return;
   TileCtx c;
   if (!tile_ctx(d, ranges, c)) return;
@@ -1515,10 +1540,15 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   }
   if (loss_out) {
     loss = wave_sum(loss);
-    if ((t & 63) == 0) atomicAdd(&s_loss, loss);
+    if ((t & 63) == 0) {
+      if (DET)
+        fx_add(loss_fx, loss);
+      else
+        atomicAdd(&s_loss, loss);
+    }
   }
   __syncthreads();
-  if (loss_out && t == 0) unsafeAtomicAdd(loss_out, s_loss);
+  if (!DET && loss_out && t == 0) unsafeAtomicAdd(loss_out, s_loss);
   uint32_t lmax[MAXL];
   uint32_t ktop = 0;
 #pragma unroll
@@ -1649,14 +1679,35 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
           float g[9] = {dp * fmaf(cb.x, ev.dx, ev.u), dp * (fmaf(cb.y, ev.dx, ev.v) + ev.v), pdx * ev.dx, pdx * ev.dy,
                         pdy * ev.dy, dp, gr, gg, gb};
           reduce_scatter9(g, lane);
-          const float x = (lane & 7) == 0 ? g[0] : g[8];
-          if (adder && x != 0.f)
-            __hip_atomic_fetch_add(g_slot + j * kGradLds, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (DET) {
+            // value 8 summed over the eight groups too (every lane of a group holds the same value)
+            float v8 = g[8];
+            {
+              const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v8), __float_as_uint(v8), false, false);
+              v8 = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+            }
+            {
+              const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v8), __float_as_uint(v8), false, false);
+              v8 = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+            }
+            v8 += dpp<kDppMirror>(v8);
+            // this wave's sums of the entry, scaled as in the flush below, into the fixed-point sums
+            const int v = (lane & 7) == 0 ? vid : 8;
+            const float x = (lane & 7) == 0 ? g[0] : v8;
+            if ((lane & 7) == 0 || lane == 1) {
+              const float sc = v == 5 ? __builtin_amdgcn_rcpf(a.z) : kGradScale[v];
+              if (x != 0.f) fx_add(g2d_fx + (((recbase + __float_as_uint(a.w)) * 9 + v) << 1), x * sc);
+            }
+          } else {
+            const float x = (lane & 7) == 0 ? g[0] : g[8];
+            if (adder && x != 0.f)
+              __hip_atomic_fetch_add(g_slot + j * kGradLds, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
         }
       }
     }
     __syncthreads();
-    if (t < cnt) {
+    if (!DET && t < cnt) {
       const uint32_t g_i = __float_as_uint(s_a[t].w);
       float* dst = g2d + (recbase + g_i) * kGradStride;
       const float inv_o = __builtin_amdgcn_rcpf(s_a[t].z);
@@ -2167,8 +2218,12 @@ hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, co
   float* g2d = (float*)(ws + lo.grad2d);
   const int per = (d.B * d.T + 7) / 8;
   dim3 grid(per * 8), block(kTilePix), block2(kBwd2Threads);
-  const bool cnt = work_counting();
-  const bool two = d.bwd_pixels == 2;
+  // the deterministic variant: one pixel per lane, no counting, fixed-point sums (launch_fx_finish)
+  const bool det = d.det != 0;
+  const bool cnt = work_counting() && !det;
+  const bool two = d.bwd_pixels == 2 && !det;
+  unsigned long long* gfx = det ? (unsigned long long*)(ws + lo.grad2d_fx) : nullptr;
+  unsigned long long* lfx = det ? (unsigned long long*)(ws + lo.loss_fx) : nullptr;
 #define GS_BWD(L_)                                                                                          \
   do {                                                                                                      \
     if (two && cnt)                                                                                         \
@@ -2177,12 +2232,15 @@ hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, co
     else if (two)                                                                                           \
       hipLaunchKernelGGL((k_raster_bwd2<L_, false>), grid, block2, 0, st, d, status, ranges, lists, rec, tf,  \
                          nl, image, d_image, target, g2d, loss_out);                                        \
+    else if (det)                                                                                           \
+      hipLaunchKernelGGL((k_raster_bwd<L_, false, true>), grid, block, 0, st, d, status, ranges, lists, rec, tf, \
+                         nl, image, d_image, target, g2d, loss_out, gfx, lfx);                              \
     else if (cnt)                                                                                           \
-      hipLaunchKernelGGL((k_raster_bwd<L_, true>), grid, block, 0, st, d, status, ranges, lists, rec, tf, nl, \
-                         image, d_image, target, g2d, loss_out);                                            \
+      hipLaunchKernelGGL((k_raster_bwd<L_, true, false>), grid, block, 0, st, d, status, ranges, lists, rec, tf, \
+                         nl, image, d_image, target, g2d, loss_out, gfx, lfx);                              \
     else                                                                                                    \
-      hipLaunchKernelGGL((k_raster_bwd<L_, false>), grid, block, 0, st, d, status, ranges, lists, rec, tf, nl, \
-                         image, d_image, target, g2d, loss_out);                                            \
+      hipLaunchKernelGGL((k_raster_bwd<L_, false, false>), grid, block, 0, st, d, status, ranges, lists, rec, \
+                         tf, nl, image, d_image, target, g2d, loss_out, gfx, lfx);                          \
   } while (0)
   ProfScope ps_(K_RASTER_BWD, st);
   if (d.L == 1) GS_BWD(1);
@@ -2191,6 +2249,23 @@ hipError_t launch_raster_bwd(const RenderDims& d, char* ws, const Layout& lo, co
   else if (d.L <= 6) GS_BWD(6);
   else GS_BWD(8);
 #undef GS_BWD
+  return hipGetLastError();
+}
+
+// The deterministic backward's fixed-point sums into the gradient records (and the loss).
+__global__ __launch_bounds__(256) void k_fx_finish(size_t count, const unsigned long long* __restrict__ g2d_fx,
+                                                   float* __restrict__ g2d, const unsigned long long* __restrict__ loss_fx,
+                                                   float* __restrict__ loss_out) {
+  const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;  // (view, Gaussian) * 9 + value
+  if (k < count) g2d[(k / 9) * kGradStride + k % 9] = fx_value(g2d_fx + 2 * k);
+  if (k == 0 && loss_out) loss_out[0] += fx_value(loss_fx);
+}
+
+hipError_t launch_fx_finish(const RenderDims& d, char* ws, const Layout& lo, float* loss_out, hipStream_t st) {
+  const size_t count = (size_t)d.B * d.n * 9;
+  hipLaunchKernelGGL(k_fx_finish, dim3((unsigned)((count + 255) / 256 > 0 ? (count + 255) / 256 : 1)), dim3(256), 0,
+                     st, count, (const unsigned long long*)(ws + lo.grad2d_fx), (float*)(ws + lo.grad2d),
+                     (const unsigned long long*)(ws + lo.loss_fx), loss_out);
   return hipGetLastError();
 }
 

@@ -134,6 +134,20 @@ class Workspace:
                                                   "bwd_contribs")}
 
 
+class deterministic:
+    """Context in which workspaces are sized for, and backward passes run, the deterministic
+    backward (gs_set_deterministic): the same gradient and loss bits on every run. Enter it before
+    creating the workspace and running the forward."""
+
+    def __enter__(self):
+        self.prev = lib().gs_set_deterministic(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().gs_set_deterministic(self.prev)
+        return False
+
+
 class work_counters:
     """Context in which raster passes run their work-counting variant (gs_set_work_counters)."""
 

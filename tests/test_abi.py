@@ -190,6 +190,27 @@ def test_work_counter_switch_is_host_only_and_returns_previous(L):
         L.gs_set_work_counters(prev)
 
 
+def test_deterministic_switch_sizes_the_workspace_for_its_fixed_point_sums(L):
+    """The deterministic backward's switch is host-only, returns the previous setting, and while it
+    is on the workspace holds 144 more bytes (nine 128-bit sums) per (view, Gaussian)."""
+    from paper_2509_17513_amd import RenderSettings
+    st = RenderSettings(64, 48, 1, (100,), (1.0,)).c_struct(100)
+    size = ctypes.c_size_t()
+    assert L.gs_workspace_size(ctypes.byref(st), 100, 1, 3, 1000, ctypes.byref(size)) == 0
+    base = size.value
+    prev = L.gs_set_deterministic(1)
+    try:
+        assert L.gs_set_deterministic(1) == 1
+        assert L.gs_workspace_size(ctypes.byref(st), 100, 1, 3, 1000, ctypes.byref(size)) == 0
+        assert size.value >= base + 3 * 100 * 144 + 16
+        assert size.value <= base + 3 * 100 * 144 + 16 + 512  # two 256-byte alignments
+        assert L.gs_set_deterministic(0) == 1
+        assert L.gs_workspace_size(ctypes.byref(st), 100, 1, 3, 1000, ctypes.byref(size)) == 0
+        assert size.value == base
+    finally:
+        L.gs_set_deterministic(prev)
+
+
 def test_render_backward_checks_every_shape_on_the_host():
     """The C ABI cannot see a tensor's extent, so the binding checks the shape of every buffer
     render_backward passes: a d_image shaped like the target, a narrower d_params or a wrong
