@@ -673,31 +673,39 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(RenderDims d, const
   hist[((size_t)b * 256 + t) * d.n_sort_chunks + chunk] = h[t];
 }
 
-// Exclusive scan of one segment's [256][chunks] digit-major histogram.
+// Stable scatter of one pass. Wave w owns the 512 consecutive keys [start + 512 w, start + 512 w
+// + 512) of the block's chunk, eight rounds of 64 in order; a key's rank among the wave's keys of
+// its digit is the count of that digit in the wave's earlier rounds (a running count in LDS, read by
+// every peer and advanced by the round's first peer) plus its rank among this round's peers (eight
+// ballots). One barrier later the block turns the four waves' counts into per-wave offsets (thread
+// t for digit t), so positions follow the input order with two barriers per chunk.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RenderDims d, const uint32_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                uint32_t* __restrict__ kout,
                                                                uint32_t* __restrict__ vout,
                                                                const uint32_t* __restrict__ hist, int shift) {
-  __shared__ uint32_t goff[256], base[256];
-  __shared__ uint32_t wcnt[4][256], woff[4][256];
-  const int t = threadIdx.x, w = t >> 6;
+  static_assert(kSortThreads == 256 && kSortItems == 8, "four waves of eight rounds of 64 keys");
+  __shared__ uint32_t wcnt[4][256];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int b = blockIdx.y, chunk = blockIdx.x;
   const size_t seg = (size_t)b * d.n;
-  goff[t] = hist[((size_t)b * 256 + t) * d.n_sort_chunks + chunk];
-  base[t] = 0;
   for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
+  const uint32_t goff = hist[((size_t)b * 256 + t) * d.n_sort_chunks + chunk];
   __syncthreads();
-  const int start = chunk * kSortChunk;
+  const int start = chunk * kSortChunk + w * (kSortItems * 64);
+  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+#pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
-    const int e = start + it * kSortThreads + t;
+    const int e = start + it * 64 + lane;
     const bool valid = e < d.n;
-    uint32_t key = 0, val = 0, dg = 0;
-    if (valid) {
-      key = kin[seg + e];
-      val = vin[seg + e];
-      dg = (key >> shift) & 255u;
-    }
+    key[it] = valid ? kin[seg + e] : 0u;
+    val[it] = valid ? vin[seg + e] : 0u;
+  }
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int e = start + it * 64 + lane;
+    const bool valid = e < d.n;
+    const uint32_t dg = (key[it] >> shift) & 255u;
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -705,24 +713,34 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RenderDims d, co
       const unsigned long long bb = __ballot(valid && on);
       peers &= on ? bb : ~bb;
     }
-    const uint32_t rank = popc_below(peers);
-    if (valid && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    {
-      uint32_t run = base[t];
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t c = wcnt[k][t];
-        woff[k][t] = run;
-        wcnt[k][t] = 0;
-        run += c;
-      }
-      base[t] = run;
+    const uint32_t below = popc_below(peers);
+    // LDS operations of one wave complete in order: every peer reads the count before the
+    // round's first peer advances it
+    const uint32_t prev = valid ? wcnt[w][dg] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) wcnt[w][dg] = prev + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    rank[it] = prev + below;
+  }
+  __syncthreads();
+  {
+    // per-wave offsets of digit t inside the chunk's run of that digit
+    uint32_t run = goff;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t c = wcnt[k][t];
+      wcnt[k][t] = run;
+      run += c;
     }
-    __syncthreads();
-    if (valid) {
-      const uint32_t pos = goff[dg] + woff[w][dg] + rank;
-      kout[seg + pos] = key;
-      vout[seg + pos] = val;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int e = start + it * 64 + lane;
+    if (e < d.n) {
+      const uint32_t pos = wcnt[w][(key[it] >> shift) & 255u] + rank[it];
+      kout[seg + pos] = key[it];
+      vout[seg + pos] = val[it];
     }
   }
 }
