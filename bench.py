@@ -44,7 +44,7 @@ ALU_PEAK_OPS = 256 * 64 * 2.4e9
 #  backward, per (pixel, entry, layer) contribution: T in front (1), alpha T (1), colour gradient
 #  (3 FMA), w . c (2 FMA + 1), the alpha gradient (2 FMA), the colour behind (1 FMA)      = 19
 FWD_FLOP_EVAL, FWD_FLOP_CONTRIB = 11, 9
-BWD_FLOP_EVAL, BWD_FLOP_CONTRIB = 36, 19
+BWD_FLOP_EVAL, BWD_FLOP_CONTRIB = 28, 19
 # algorithmic VALU operations per image element (pixel, channel, layer) of the D-SSIM kernels:
 # forward = two 11-tap passes of x, x^2, x y (66) + the two products + the per-pixel SSIM value and
 # derivatives (30), plus the target's two moments shared by the L layers; backward = two passes of

@@ -510,8 +510,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(RenderDims d, const float* 
       const gs_camera cam = cams[b];
       const ViewProj vp = view_proj(d, cam, mu64, fg);
       if (!vp.valid) continue;
-      // conic (A, B, C) -> covariance (a, b, c)
       const float A = vp.A, B = vp.B, C = vp.C;
+      // the record holds the moments (sum dp dx, sum dp dy); dL/dm = [[A, B], [B, C]] of them
+      {
+        const float mx = gr[0], my = gr[1];
+        gr[0] = fmaf(A, mx, B * my);
+        gr[1] = fmaf(B, mx, C * my);
+      }
+      // conic (A, B, C) -> covariance (a, b, c)
       const float gA = gr[2], gB = gr[3], gC = gr[4];
       const float ga = -(gA * A * A + gB * A * B + gC * B * B);
       const float gb = -(2.f * gA * A * B + gB * (A * C + B * B) + 2.f * gC * B * C);
@@ -1427,11 +1433,14 @@ __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <
   }
 }
 
-// Constant factors of the nine per-entry gradient sums of the backward (mean x, y; conic A, B, C;
-// opacity; colour r, g, b), applied once to each sum instead of to every pixel's term. The opacity
-// sum is taken as the sum of dp = dL/dalpha * o * G (a term the mean and conic sums form anyway)
-// and divided by the entry's opacity o when it is flushed.
-constexpr float kGradScale[9] = {-kLn2, -kLn2, -0.5f, -1.f, -0.5f, 1.f, 1.f, 1.f, 1.f};
+// The nine per-entry sums of the backward are moments of dp = dL/dalpha * o * G over the pixels
+// (dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2, dp), with dx, dy the offset of the pixel from the
+// mean, and the colour gradients (r, g, b); their constant factors are applied once to each sum:
+// dL/d(A, B, C) = -(1/2, 1, 1/2) (sum dp dx^2, sum dp dx dy, sum dp dy^2), dL/do = sum dp / o (the
+// flush divides by o). The gradient record keeps the first two as moments: the mean gradient,
+// dL/dm = [[A, B], [B, C]] (sum dp dx, sum dp dy), is formed by the projection backward, which has
+// the conic at hand, once per (view, Gaussian).
+constexpr float kGradScale[9] = {1.f, 1.f, -0.5f, -1.f, -0.5f, 1.f, 1.f, 1.f, 1.f};
 
 // A float in LDS, addressed with 32-bit offsets.
 typedef __attribute__((address_space(3))) float lds_float;
@@ -1689,13 +1698,9 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
           // the clamp at alpha_max has zero derivative; dal is zero without a contribution
           const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
           const float dp = dl * ev.ga;
-          // mean and conic gradients without their constant factors, which kGradScale applies to
-          // the sums: conic (A, B, C) = -ln 2 (2 a2, b2, 2 c2), so dL/dmx = -ln 2 dp (2 a2 dx + b2 dy)
-          // = -ln 2 dp (u + a2 dx), dL/dmy = -ln 2 dp (b2 dx + 2 c2 dy) = -ln 2 dp (b2 dx + v + v),
-          // dL/d(A, B, C) = -(1/2, 1, 1/2) dp (dx^2, dx dy, dy^2), dL/do = sum dp / o
+          // the moments of dp and the colour gradients (kGradScale)
           const float pdx = dp * ev.dx, pdy = dp * ev.dy;
-          float g[9] = {dp * fmaf(cb.x, ev.dx, ev.u), dp * (fmaf(cb.y, ev.dx, ev.v) + ev.v), pdx * ev.dx, pdx * ev.dy,
-                        pdy * ev.dy, dp, gr, gg, gb};
+          float g[9] = {pdx, pdy, pdx * ev.dx, pdx * ev.dy, pdy * ev.dy, dp, gr, gg, gb};
           reduce_scatter9(g, lane);
           if (DET) {
             // value 8 summed over the eight groups too (every lane of a group holds the same value)
@@ -1961,8 +1966,8 @@ __global__ __launch_bounds__(kBwd2Threads) void k_raster_bwd2(RenderDims d, Stat
           const float dl = ev.ga <= d.alpha_max ? dal : 0.f;
           const float dp = dl * ev.ga;
           const float pdx = dp * ev.dx, pdy = dp * ev.dy;
-          g[0] += dp * fmaf(cb.x, ev.dx, ev.u);
-          g[1] += dp * (fmaf(cb.y, ev.dx, ev.v) + ev.v);
+          g[0] += pdx;
+          g[1] += pdy;
           g[2] += pdx * ev.dx;
           g[3] += pdx * ev.dy;
           g[4] += pdy * ev.dy;
