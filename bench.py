@@ -38,9 +38,10 @@ ALU_PEAK_OPS = 256 * 64 * 2.4e9
 #  evaluation of one Gaussian at one pixel: offset (2), quadratic form u = a dx + b dy, v = c dy,
 #  u dx + v dy (7), exp2 (1), times the opacity (1)                                      = 11
 #  forward compositing update of one layer: 1 - alpha, T (1 - alpha), alpha T, C += c alpha T (3 FMA) = 9
-#  backward, per (pixel, entry) walked: the evaluation (11), 1 - alpha and its reciprocal (2), the
-#  mean / conic / opacity gradient terms formed once from the layers' sum (14) and their addition
-#  into the entry's nine sums (9)                                                         = 36
+#  backward, per (pixel, entry) walked: the evaluation (11), 1 - alpha and its reciprocal (2),
+#  dp = dL/dalpha o G (1), the moments dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2 (5) and the
+#  addition of the nine per-pixel values into the entry's sums (9)                        = 28
+#  (the mean gradient is formed from the two first moments once per (view, Gaussian))
 #  backward, per (pixel, entry, layer) contribution: T in front (1), alpha T (1), colour gradient
 #  (3 FMA), w . c (2 FMA + 1), the alpha gradient (2 FMA), the colour behind (1 FMA)      = 19
 FWD_FLOP_EVAL, FWD_FLOP_CONTRIB = 11, 9
