@@ -918,13 +918,13 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
 // (frame-view, row) list; lane l owns tile column l (and l + 64 when the image
 // is wider than 64 tiles, TWO) and appends, in list (= depth) order, every
 // entry whose column range covers it, so each lane writes its own tile list
-// sequentially.
-template <bool EMIT, bool TWO>
+// sequentially, from the offset the counting pass (k_tile_count) and the scans give.
+template <bool TWO>
 __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __restrict__ st,
                                                  const uint2* __restrict__ row_ranges,
-                                                 const uint2* __restrict__ row_lists, uint32_t* __restrict__ hist,
+                                                 const uint2* __restrict__ row_lists, const uint32_t* __restrict__ hist,
                                                  const uint2* __restrict__ ranges, uint32_t* __restrict__ lists) {
-  // emit: each lane appends its tile's entries to a 32-entry ring in LDS indexed by list
+  // each lane appends its tile's entries to a 32-entry ring in LDS indexed by list
   // position; every 16 entries of the segment the wave drains, per lane, the unaligned head up to
   // the next 16-entry boundary of the list and then whole aligned 16-entry runs (four 16-byte
   // stores each), so that at most 31 entries are outstanding
@@ -938,13 +938,11 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
   if (start >= rr.y) return;
   const uint32_t end = min(start + (uint32_t)d.row_seg, rr.y);
   const int tx0 = lane, tx1 = lane + 64;
-  uint32_t* hb = hist + (((size_t)b * d.TY + ty) * d.n_row_segs + s) * d.TX;
-  uint32_t c0 = 0, c1 = 0;   // next list position to fill (emit) or count
-  uint32_t w0 = 0, w1 = 0;   // next list position to write out (emit)
-  if (EMIT) {
-    if (tx0 < d.TX) c0 = w0 = ranges[(size_t)b * d.T + ty * d.TX + tx0].x + hb[tx0];
-    if (tx1 < d.TX) c1 = w1 = ranges[(size_t)b * d.T + ty * d.TX + tx1].x + hb[tx1];
-  }
+  const uint32_t* hb = hist + (((size_t)b * d.TY + ty) * d.n_row_segs + s) * d.TX;
+  uint32_t c0 = 0, c1 = 0;   // next list position to fill
+  uint32_t w0 = 0, w1 = 0;   // next list position to write out
+  if (tx0 < d.TX) c0 = w0 = ranges[(size_t)b * d.T + ty * d.TX + tx0].x + hb[tx0];
+  if (tx1 < d.TX) c1 = w1 = ranges[(size_t)b * d.T + ty * d.TX + tx1].x + hb[tx1];
   const unsigned long long cap = d.capacity;
   auto drain = [&](int q, uint32_t c, uint32_t& w, bool last) {
     const uint32_t* ring = wbuf[q][lane];
@@ -991,26 +989,55 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
         const int txl = (int)(rg & 0xFFFF), txh = (int)(rg >> 16);
         const bool h0 = (tx0 >= txl) & (tx0 <= txh);
         const bool h1 = TWO && ((tx1 >= txl) & (tx1 <= txh));
-        if (EMIT) {
-          const uint32_t gi = __builtin_amdgcn_readlane(ent.x, j);
-          wbuf[0][lane][h0 ? (c0 & (kRing - 1)) : kRing] = gi;
-          if (TWO) wbuf[TWO ? 1 : 0][lane][h1 ? (c1 & (kRing - 1)) : kRing] = gi;
-        }
+        const uint32_t gi = __builtin_amdgcn_readlane(ent.x, j);
+        wbuf[0][lane][h0 ? (c0 & (kRing - 1)) : kRing] = gi;
+        if (TWO) wbuf[TWO ? 1 : 0][lane][h1 ? (c1 & (kRing - 1)) : kRing] = gi;
         c0 += h0 ? 1u : 0u;
         if (TWO) c1 += h1 ? 1u : 0u;
       }
-      if (EMIT) {
-        drain(0, c0, w0, false);
-        if (TWO) drain(TWO ? 1 : 0, c1, w1, false);
-      }
+      drain(0, c0, w0, false);
+      if (TWO) drain(TWO ? 1 : 0, c1, w1, false);
     }
   }
-  if (EMIT) {
-    drain(0, c0, w0, true);
-    if (TWO) drain(TWO ? 1 : 0, c1, w1, true);
-  } else {
-    if (tx0 < d.TX) hb[tx0] = c0;
-    if (TWO && tx1 < d.TX) hb[tx1] = c1;
+  drain(0, c0, w0, true);
+  if (TWO) drain(TWO ? 1 : 0, c1, w1, true);
+}
+
+// Level 2, counting: the number of entries of a segment of row_seg entries of a (frame-view, row)
+// list whose column range covers each tile of the row, as a difference array: an entry adds 1 at
+// its first column and -1 after its last (LDS atomics), and a prefix sum over the columns gives the
+// counts (the same integers the emitting pass then places). One wave per segment.
+__global__ __launch_bounds__(64) void k_tile_count(RenderDims d, const Status* __restrict__ st,
+                                                   const uint2* __restrict__ row_ranges,
+                                                   const uint2* __restrict__ row_lists, uint32_t* __restrict__ hist) {
+  __shared__ int diff[kMaxTilesX + 1];
+  if (st->overflow & 2u) return;
+  const int lane = threadIdx.x;
+  const int s = blockIdx.x, ty = blockIdx.y, b = blockIdx.z;
+  const uint2 rr = row_ranges[(size_t)b * d.TY + ty];
+  const uint32_t start = rr.x + (uint32_t)s * (uint32_t)d.row_seg;
+  if (start >= rr.y) return;
+  const uint32_t end = min(start + (uint32_t)d.row_seg, rr.y);
+  for (int j = lane; j <= d.TX; j += 64) diff[j] = 0;
+  __syncthreads();
+  for (uint32_t e = start + lane; e < end; e += 64) {
+    const uint32_t rg = row_lists[e].y;
+    const int txl = (int)(rg & 0xFFFF), txh = (int)(rg >> 16);  // txl <= txh < TX
+    atomicAdd(&diff[txl], 1);
+    atomicAdd(&diff[txh + 1], -1);
+  }
+  __syncthreads();
+  uint32_t* hb = hist + (((size_t)b * d.TY + ty) * d.n_row_segs + s) * d.TX;
+  int carry = 0;
+  for (int t0 = 0; t0 < d.TX; t0 += 64) {
+    int v = t0 + lane < d.TX ? diff[t0 + lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(v, off);
+      if (lane >= off) v += u;
+    }
+    if (t0 + lane < d.TX) hb[t0 + lane] = (uint32_t)(carry + v);
+    carry += __shfl(v, 63);
   }
 }
 
@@ -2174,12 +2201,7 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   }
   if (d.n_row_segs > 0) {
     ProfScope ps_(K_BIN_COUNT, st);
-    if (d.TX > 64)
-      hipLaunchKernelGGL((k_tile_bin<false, true>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
-                         lists);
-    else
-      hipLaunchKernelGGL((k_tile_bin<false, false>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
-                         lists);
+    hipLaunchKernelGGL(k_tile_count, grid2, dim3(64), 0, st, d, status, rranges, rlists, thist);
   }
   {
     ProfScope ps_(K_TILE_RANGES, st);
@@ -2189,10 +2211,10 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   if (d.n_row_segs > 0) {
     ProfScope ps_(K_BIN_EMIT, st);
     if (d.TX > 64)
-      hipLaunchKernelGGL((k_tile_bin<true, true>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
+      hipLaunchKernelGGL((k_tile_bin<true>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
                          lists);
     else
-      hipLaunchKernelGGL((k_tile_bin<true, false>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
+      hipLaunchKernelGGL((k_tile_bin<false>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
                          lists);
   }
   return hipGetLastError();
