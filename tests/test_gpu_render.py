@@ -564,3 +564,23 @@ def test_deterministic_backward_repeats_bit_for_bit_and_matches_oracle():
     dp, _ = render_backward(st, p, c, ws, image=img, d_image=d_image)
     bad, worst = grad_mismatch(dp.cpu().numpy().astype(np.float64), dp_ref, param_groups(w.sh_degree))
     assert bad == 0
+
+
+def test_deterministic_backward_of_an_empty_scene_gives_the_background_loss():
+    _case("deterministic backward, empty scene: the loss of the background against the target")
+    from paper_2509_17513_amd import RenderSettings, deterministic, render_backward, render_forward
+    dev = _dev()
+    W, H = 37, 21
+    st = RenderSettings(W, H, 0, (0,), (1.0,), bg=(0.25, 0.5, 0.75))
+    p = torch.zeros((14, 0), dtype=torch.float32, device=dev)
+    c = torch.from_numpy(synth.identity_camera(W, H, 37.0)[None]).to(dev)
+    tgt_h = synth.target_images(1, W, H, 5)
+    tgt = torch.from_numpy(tgt_h).to(dev)
+    with deterministic():
+        img, ws = render_forward(st, p, c)
+        loss = torch.zeros(1, device=dev)
+        render_backward(st, p, c, ws, image=img, target=tgt, loss=loss)
+        torch.cuda.synchronize()
+    bg = np.array([0.25, 0.5, 0.75], np.float64)[:, None, None]
+    want = np.abs(bg - tgt_h[0].astype(np.float64)).mean()
+    assert abs(float(loss.item()) - want) <= 1e-5 * want, (float(loss.item()), want)
