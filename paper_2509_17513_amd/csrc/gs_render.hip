@@ -455,8 +455,11 @@ __global__ __launch_bounds__(256) void k_project_fwd(RenderDims d, const float* 
           view_color<DEG>(cam, g, rgb, raw, dir, &il, Y);
           rec[3 * bi + 0] = make_float4(vp.mx, vp.my, vp.A, vp.B);
           rec[3 * bi + 1] = make_float4(vp.C, fg.o, rgb[0], rgb[1]);
-          rec[3 * bi + 2] = make_float4(rgb[2], vp.tz, 0.f, 0.f);
-          rects[bi] = make_uint2((uint32_t)cx0 | ((uint32_t)cx1 << 16), (uint32_t)cy0 | ((uint32_t)cy1 << 16));
+          // the tile rectangle also rides in the record's spare words, so that the binning gather
+          // reads one contiguous 48-byte record per depth-sorted Gaussian
+          const uint2 rc = make_uint2((uint32_t)cx0 | ((uint32_t)cx1 << 16), (uint32_t)cy0 | ((uint32_t)cy1 << 16));
+          rec[3 * bi + 2] = make_float4(rgb[2], vp.tz, __uint_as_float(rc.x), __uint_as_float(rc.y));
+          rects[bi] = rc;
           key = __float_as_uint(vp.tz);
         }
       }
@@ -758,7 +761,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(RenderDims d, co
 // sequentially.
 __global__ __launch_bounds__(256) void k_bin_gather(RenderDims d, const uint32_t* __restrict__ skeys,
                                                     const uint32_t* __restrict__ svals,
-                                                    const uint2* __restrict__ rects, const float4* __restrict__ rec,
+                                                    const float4* __restrict__ rec,
                                                     float4* __restrict__ brec) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
@@ -768,8 +771,8 @@ __global__ __launch_bounds__(256) void k_bin_gather(RenderDims d, const uint32_t
   float4 o2 = make_float4(-1.f, 0.f, 0.f, 0.f);
   if (skeys[seg + k] != 0xFFFFFFFFu) {
     const uint32_t i = svals[seg + k];
-    const float4 r0 = rec[3 * (seg + i)], r1 = rec[3 * (seg + i) + 1];
-    const uint2 rc = rects[seg + i];
+    const float4 r0 = rec[3 * (seg + i)], r1 = rec[3 * (seg + i) + 1], r2 = rec[3 * (seg + i) + 2];
+    const uint2 rc = make_uint2(__float_as_uint(r2.z), __float_as_uint(r2.w));  // the tile rectangle
     // quadratic-form threshold of alpha >= alpha_min, with a relative margin of 1e-3 (hardware
     // log, reciprocal and square root: their ~1e-7 relative errors are far inside the margins)
     const float tau = 2.f * (__logf(r1.y) - __logf(d.alpha_min)) * 1.001f + 1e-3f;
@@ -2164,7 +2167,6 @@ hipError_t launch_radix_sort(int n, uint32_t* keys[2], uint32_t* vals[2], uint32
 
 hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t* svals, char* ws, const Layout& lo,
                       hipStream_t st) {
-  const uint2* rects = (const uint2*)(ws + lo.rects);
   const float4* rec = (const float4*)(ws + lo.records);
   float4* brec = (float4*)(ws + lo.bin_rec);
   uint32_t* rhist = (uint32_t*)(ws + lo.bin_hist);
@@ -2182,7 +2184,7 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   if (d.n_bin_chunks > 0) {
     {
       ProfScope ps_(K_BIN_GATHER, st);
-      hipLaunchKernelGGL(k_bin_gather, dim3((d.n + 255) / 256, d.B), dim3(256), 0, st, d, skeys, svals, rects, rec,
+      hipLaunchKernelGGL(k_bin_gather, dim3((d.n + 255) / 256, d.B), dim3(256), 0, st, d, skeys, svals, rec,
                          brec);
     }
     ProfScope ps_(K_ROW_COUNT, st);
