@@ -835,7 +835,8 @@ __device__ __forceinline__ int wave_max_i(int v) {
 // ballot ranks the hitting lanes, so the entries of a row keep the depth order
 // of the batch (a stable counting sort; the per-row counters live in LDS).
 // Gaussians taller than kRowPre rows evaluate their further rows inside the
-// row loop. An entry is (Gaussian index, tile-column range in the row).
+// row loop. An entry is (Gaussian index, tile-column range in the row), the range packed as
+// first column | column count << 16.
 template <bool EMIT>
 __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ svals, const float4* __restrict__ brec,
@@ -879,7 +880,7 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
       int txl = 0, txh = 0;
       const bool h = ok && y0 + r <= y1 && el.row(d, y0 + r, x0, x1, txl, txh);
       hm |= h ? 1u << r : 0u;
-      s_pk[lane][r] = (uint32_t)txl | ((uint32_t)txh << 16);
+      s_pk[lane][r] = (uint32_t)txl | ((uint32_t)(txh - txl + 1) << 16);
     }
     const bool tall = ok && y1 - y0 >= kRowPre;
     int ylo = hm ? y0 + __builtin_ctz(hm) : 0x7FFFFFFF;
@@ -899,7 +900,7 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
         int txl = 0, txh = 0;
         if (tall && r >= (uint32_t)kRowPre && ty <= y1 && el.row(d, ty, x0, x1, txl, txh)) {
           hit = true;
-          rg = (uint32_t)txl | ((uint32_t)txh << 16);
+          rg = (uint32_t)txl | ((uint32_t)(txh - txl + 1) << 16);
         }
       }
       const unsigned long long m = __ballot(hit);
@@ -917,20 +918,34 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
     for (int t = lane; t < TY; t += 64) bh[t] = cnt[t];
 }
 
+// c + bit `lane` of the wave-uniform mask m: the mask is the carry-in of an add, so a lane learns
+// whether a column range given as a lane mask covers it without a compare of its own.
+__device__ __forceinline__ uint32_t add_lane_bit(uint32_t c, unsigned long long m) {
+  uint32_t r;
+  unsigned long long carry_out;
+  asm("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(carry_out) : "v"(c), "s"(m));
+  return r;
+}
+
 // Level 2: tiles of one row. One wave takes a segment of row_seg entries of a
 // (frame-view, row) list; lane l owns tile column l (and l + 64 when the image
-// is wider than 64 tiles, TWO) and appends, in list (= depth) order, every
+// is 64 or more tiles wide, TWO) and appends, in list (= depth) order, every
 // entry whose column range covers it, so each lane writes its own tile list
 // sequentially, from the offset the counting pass (k_tile_count) and the scans give.
+//
+// A lane stages its tile's entries in a 32-entry ring in LDS indexed by list position. Every
+// entry is written at the lane's next free slot, whether or not it covers the lane's tile; the
+// lane's counter advances only if it does, so a miss is overwritten by the next hit. Every 16
+// entries of the segment the wave drains, per lane, the unaligned head up to the next 16-entry
+// boundary of the list and then whole aligned 16-entry runs (four 16-byte stores each): at most
+// 30 entries are outstanding when one is staged, so the slot it writes never holds one.
+// One column per lane (up to 63 tiles): the entries are wave-uniform loads, and an entry's range
+// becomes a 64-bit lane mask (a bit field) that is the carry-in of the counter's add.
 template <bool TWO>
 __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __restrict__ st,
                                                  const uint2* __restrict__ row_ranges,
                                                  const uint2* __restrict__ row_lists, const uint32_t* __restrict__ hist,
                                                  const uint2* __restrict__ ranges, uint32_t* __restrict__ lists) {
-  // each lane appends its tile's entries to a 32-entry ring in LDS indexed by list
-  // position; every 16 entries of the segment the wave drains, per lane, the unaligned head up to
-  // the next 16-entry boundary of the list and then whole aligned 16-entry runs (four 16-byte
-  // stores each), so that at most 31 entries are outstanding
   constexpr int kRing = 32, kStride = 36;  // stride: 16-byte aligned rows, spread banks; slot 32 is a sink
   __shared__ __align__(16) uint32_t wbuf[TWO ? 2 : 1][64][kStride];
   if (st->overflow & 2u) return;
@@ -976,30 +991,67 @@ __global__ __launch_bounds__(64) void k_tile_bin(RenderDims d, const Status* __r
       w = c;
     }
   };
-  for (uint32_t base = start; base < end; base += 64) {
-    const uint32_t e = base + lane;
-    // entries past the end of the segment get an empty column range
-    const uint2 ent = e < end ? row_lists[e] : make_uint2(0u, 1u);
-    const int nin = (int)min(64u, end - base);
-    // blocks of 16 entries with no branch per entry: a lane whose tile the entry does not cover
-    // writes the ring's spare slot kRing and does not advance; one drain per block, so that at
-    // most 16 entries per lane are new since the last drain
-    for (int jb = 0; jb < nin; jb += 16) {
+  if constexpr (!TWO) {
+    uint32_t* const ring = wbuf[0][lane];
+    auto stage = [&](const uint2 en) {
+      // lanes [first, first + count) of the entry's range: first < 64 is the low 6 bits of en.y
+      // and the count (1..63) its high half
+      const uint32_t y = __builtin_amdgcn_readfirstlane(en.y);  // wave-uniform (a no-op when scalar)
+      unsigned long long m;
+      asm("s_bfm_b64 %0, %1, %2" : "=s"(m) : "s"(y >> 16), "s"(y));
+      ring[c0 & (kRing - 1)] = en.x;
+      c0 = add_lane_bit(c0, m);
+    };
+    // whole blocks of 16 entries (wave-uniform loads); block k + 1 is requested once the first
+    // entry of block k is staged, since waiting for any scalar load waits for all of them
+    const uint32_t nfull = (end - start) >> 4;
+    uint2 ea[16], eb[16];
+    auto load = [&](uint2(&e)[16], uint32_t k) {
+      const uint2* blk = row_lists + start + 16u * k;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int j = jb + u;
-        const uint32_t rg = __builtin_amdgcn_readlane(ent.y, j);
-        const int txl = (int)(rg & 0xFFFF), txh = (int)(rg >> 16);
-        const bool h0 = (tx0 >= txl) & (tx0 <= txh);
-        const bool h1 = TWO && ((tx1 >= txl) & (tx1 <= txh));
-        const uint32_t gi = __builtin_amdgcn_readlane(ent.x, j);
-        wbuf[0][lane][h0 ? (c0 & (kRing - 1)) : kRing] = gi;
-        if (TWO) wbuf[TWO ? 1 : 0][lane][h1 ? (c1 & (kRing - 1)) : kRing] = gi;
-        c0 += h0 ? 1u : 0u;
-        if (TWO) c1 += h1 ? 1u : 0u;
-      }
+      for (int u = 0; u < 16; ++u) e[u] = blk[u];
+    };
+    if (nfull > 0u) load(ea, 0u);
+    for (uint32_t k = 0; k < nfull; k += 2u) {
+      stage(ea[0]);
+      if (k + 1u < nfull) load(eb, k + 1u);
+#pragma unroll
+      for (int u = 1; u < 16; ++u) stage(ea[u]);
       drain(0, c0, w0, false);
-      if (TWO) drain(TWO ? 1 : 0, c1, w1, false);
+      if (k + 1u >= nfull) break;
+      stage(eb[0]);
+      if (k + 2u < nfull) load(ea, k + 2u);
+#pragma unroll
+      for (int u = 1; u < 16; ++u) stage(eb[u]);
+      drain(0, c0, w0, false);
+    }
+    for (uint32_t q = start + 16u * nfull; q < end; ++q) stage(row_lists[q]);
+  } else {
+    for (uint32_t base = start; base < end; base += 64) {
+      const uint32_t e = base + lane;
+      // entries past the end of the segment get an empty column range
+      const uint2 ent = e < end ? row_lists[e] : make_uint2(0u, 0u);
+      const int nin = (int)min(64u, end - base);
+      // blocks of 16 entries with no branch per entry: a lane whose tile the entry does not cover
+      // writes the ring's spare slot kRing and does not advance; one drain per block, so that at
+      // most 16 entries per lane are new since the last drain
+      for (int jb = 0; jb < nin; jb += 16) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int j = jb + u;
+          const uint32_t rg = __builtin_amdgcn_readlane(ent.y, j);
+          const int txl = (int)(rg & 0xFFFF), txe = txl + (int)(rg >> 16);
+          const bool h0 = (tx0 >= txl) & (tx0 < txe);
+          const bool h1 = (tx1 >= txl) & (tx1 < txe);
+          const uint32_t gi = __builtin_amdgcn_readlane(ent.x, j);
+          wbuf[0][lane][h0 ? (c0 & (kRing - 1)) : kRing] = gi;
+          wbuf[TWO ? 1 : 0][lane][h1 ? (c1 & (kRing - 1)) : kRing] = gi;
+          c0 += h0 ? 1u : 0u;
+          c1 += h1 ? 1u : 0u;
+        }
+        drain(0, c0, w0, false);
+        drain(TWO ? 1 : 0, c1, w1, false);
+      }
     }
   }
   drain(0, c0, w0, true);
@@ -1025,9 +1077,9 @@ __global__ __launch_bounds__(64) void k_tile_count(RenderDims d, const Status* _
   __syncthreads();
   for (uint32_t e = start + lane; e < end; e += 64) {
     const uint32_t rg = row_lists[e].y;
-    const int txl = (int)(rg & 0xFFFF), txh = (int)(rg >> 16);  // txl <= txh < TX
+    const int txl = (int)(rg & 0xFFFF), txe = txl + (int)(rg >> 16);  // txl < txe <= TX
     atomicAdd(&diff[txl], 1);
-    atomicAdd(&diff[txh + 1], -1);
+    atomicAdd(&diff[txe], -1);
   }
   __syncthreads();
   uint32_t* hb = hist + (((size_t)b * d.TY + ty) * d.n_row_segs + s) * d.TX;
@@ -2212,7 +2264,7 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   }
   if (d.n_row_segs > 0) {
     ProfScope ps_(K_BIN_EMIT, st);
-    if (d.TX > 64)
+    if (d.TX > 63)  // one column per lane needs column counts below 64
       hipLaunchKernelGGL((k_tile_bin<true>), grid2, dim3(64), 0, st, d, status, rranges, rlists, thist, ranges,
                          lists);
     else
