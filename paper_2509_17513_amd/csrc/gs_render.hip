@@ -828,28 +828,44 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-// Level 1: rows. Each wave walks bin_chunk depth-sorted Gaussians of one
-// frame-view, 64 at a time with one Gaussian per lane. A lane evaluates the
-// first kRowPre tile rows of its Gaussian up front (column ranges kept in
-// LDS); the wave then visits the tile rows the batch reaches, and per row a
-// ballot ranks the hitting lanes, so the entries of a row keep the depth order
-// of the batch (a stable counting sort; the per-row counters live in LDS).
-// Gaussians taller than kRowPre rows evaluate their further rows inside the
-// row loop. An entry is (Gaussian index, tile-column range in the row), the range packed as
-// first column | column count << 16.
+// Tile rows [r0, r1] whose band of pixel-centre heights (16 ty + 0.5 .. min(16 ty + 16, H) - 0.5)
+// meets the ellipse's vertical extent [my - dym, my + dym], widened by 0.01 pixel, intersected with
+// the rectangle's rows [y0, y1]; empty when r0 > r1. A closed form, so that the counting pass needs
+// no per-row work and the emitting pass visits exactly the rows it counted.
+__device__ __forceinline__ void ellipse_row_span(const RenderDims& d, float my, float dym, int y0, int y1, int& r0,
+                                                 int& r1) {
+  const float top = my - dym - 0.01f, bot = my + dym + 0.01f;
+  const float fl = ceilf((top - 15.5f) * (1.f / kTile));
+  const float fh = floorf((bot - 0.5f) * (1.f / kTile));
+  r0 = max(y0, (int)fminf(fmaxf(fl, -1.f), (float)d.TY));
+  r1 = min(y1, (int)fminf(fmaxf(fh, -1.f), (float)d.TY));
+  if (!(top <= (float)d.H - 0.5f)) r1 = r0 - 1;  // below the last row of pixel centres
+}
+
+// Level 1: rows. Each wave walks bin_chunk depth-sorted Gaussians of one frame-view, 64 at a time
+// with one Gaussian per lane. Every row of a Gaussian's span (ellipse_row_span) gets one entry
+// (Gaussian index, tile-column range in the row), the range packed as first column | column count
+// << 16 (a count of 0 when the ellipse misses the row's pixel centres after all).
+// Counting pass: the per-row counts of the chunk, as a difference array over the rows (two LDS
+// atomics per Gaussian) and a prefix sum.
+// Emitting pass: a lane evaluates the column ranges of the first kRowPre rows of its span up front
+// (kept in LDS); the wave then visits the rows the batch reaches, and per row a ballot ranks the
+// hitting lanes, so the entries of a row keep the depth order of the batch (a stable counting
+// sort; the per-row write positions live in LDS). Gaussians taller than kRowPre rows evaluate
+// their further rows inside the row loop.
 template <bool EMIT>
 __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ svals, const float4* __restrict__ brec,
                                                 uint32_t* __restrict__ hist, const uint2* __restrict__ row_ranges,
                                                 uint2* __restrict__ row_lists) {
   constexpr int kRowPre = 8;
-  extern __shared__ uint32_t cnt[];
+  extern __shared__ uint32_t cnt[];  // TY + 1 words
   __shared__ uint32_t s_pk[64][kRowPre + 1];  // per lane: packed column ranges of its first rows
   const int lane = threadIdx.x;
   const int b = blockIdx.y, chunk = blockIdx.x;
   const int TY = d.TY;
   uint32_t* bh = hist + ((size_t)b * d.n_bin_chunks + chunk) * TY;
-  for (int t = lane; t < TY; t += 64) cnt[t] = EMIT ? row_ranges[(size_t)b * TY + t].x + bh[t] : 0u;
+  for (int t = lane; t <= TY; t += 64) cnt[t] = EMIT && t < TY ? row_ranges[(size_t)b * TY + t].x + bh[t] : 0u;
   __syncthreads();
   const size_t seg = (size_t)b * d.n;
   const int start = chunk * d.bin_chunk;
@@ -859,7 +875,7 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
     uint32_t gi = 0;
     bool ok = false;
     EllipseRows el{};
-    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+    int x0 = 0, x1 = -1, r0 = 0, r1 = -1;
     if (e < end) {
       ok = skeys[seg + e] != 0xFFFFFFFFu;
       if (ok) {
@@ -869,44 +885,44 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
         const uint32_t rx = __float_as_uint(q2.z), ry = __float_as_uint(q2.w);
         x0 = (int)(rx & 0xFFFF);
         x1 = (int)(rx >> 16);
-        y0 = (int)(ry & 0xFFFF);
-        y1 = (int)(ry >> 16);
+        ellipse_row_span(d, el.my, el.dym, (int)(ry & 0xFFFF), (int)(ry >> 16), r0, r1);
       }
     }
     if (__ballot(ok) == 0ull) break;  // culled keys sort last
-    uint32_t hm = 0;
+    const bool any = r0 <= r1;
+    if (!EMIT) {
+      if (any) {
+        atomicAdd(&cnt[r0], 1u);
+        atomicAdd(&cnt[r1 + 1], 0xFFFFFFFFu);  // -1
+      }
+      continue;
+    }
+    // column ranges of the first rows of the span, as many as the wave's tallest span needs
+    const int npre = min(kRowPre, wave_max_i(any ? r1 - r0 + 1 : 0));
 #pragma unroll
     for (int r = 0; r < kRowPre; ++r) {
+      if (r >= npre) break;
       int txl = 0, txh = 0;
-      const bool h = ok && y0 + r <= y1 && el.row(d, y0 + r, x0, x1, txl, txh);
-      hm |= h ? 1u << r : 0u;
-      s_pk[lane][r] = (uint32_t)txl | ((uint32_t)(txh - txl + 1) << 16);
+      const bool h = el.row(d, r0 + r, x0, x1, txl, txh);
+      s_pk[lane][r] = h ? (uint32_t)txl | ((uint32_t)(txh - txl + 1) << 16) : 0u;
     }
-    const bool tall = ok && y1 - y0 >= kRowPre;
-    int ylo = hm ? y0 + __builtin_ctz(hm) : 0x7FFFFFFF;
-    int yhi = hm ? y0 + 31 - __builtin_clz(hm) : -1;
-    if (tall) {
-      ylo = min(ylo, y0 + kRowPre);
-      yhi = y1;
-    }
+    const bool tall = any && r1 - r0 >= kRowPre;
     const bool any_tall = __ballot(tall) != 0ull;
-    ylo = wave_min_i(ylo);
-    yhi = wave_max_i(yhi);
+    const int ylo = wave_min_i(any ? r0 : 0x7FFFFFFF);
+    const int yhi = wave_max_i(any ? r1 : -1);
     for (int ty = ylo; ty <= yhi; ++ty) {
-      const uint32_t r = (uint32_t)(ty - y0);
-      bool hit = r < (uint32_t)kRowPre && ((hm >> r) & 1u);
+      const uint32_t r = (uint32_t)(ty - r0);
+      const bool hit = any && ty >= r0 && ty <= r1;
       uint32_t rg = s_pk[lane][min(r, (uint32_t)kRowPre - 1u)];
-      if (any_tall) {
+      if (any_tall && r >= (uint32_t)kRowPre) {
         int txl = 0, txh = 0;
-        if (tall && r >= (uint32_t)kRowPre && ty <= y1 && el.row(d, ty, x0, x1, txl, txh)) {
-          hit = true;
-          rg = (uint32_t)txl | ((uint32_t)(txh - txl + 1) << 16);
-        }
+        const bool h = el.row(d, ty, x0, x1, txl, txh);
+        rg = h ? (uint32_t)txl | ((uint32_t)(txh - txl + 1) << 16) : 0u;
       }
       const unsigned long long m = __ballot(hit);
       if (m == 0ull) continue;
       const uint32_t pos0 = cnt[ty];
-      if (EMIT && hit) {
+      if (hit) {
         const uint32_t pos = pos0 + popc_below(m);
         if (pos < d.row_capacity) row_lists[pos] = make_uint2(gi, rg);
       }
@@ -914,8 +930,19 @@ __global__ __launch_bounds__(64) void k_row_bin(RenderDims d, const uint32_t* __
     }
   }
   __syncthreads();
-  if (!EMIT)
-    for (int t = lane; t < TY; t += 64) bh[t] = cnt[t];
+  if (!EMIT) {  // counts = prefix sums of the difference array
+    uint32_t carry = 0;
+    for (int t0 = 0; t0 < TY; t0 += 64) {
+      uint32_t v = t0 + lane < TY ? cnt[t0 + lane] : 0u;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+      }
+      if (t0 + lane < TY) bh[t0 + lane] = carry + v;
+      carry += __shfl(v, 63);
+    }
+  }
 }
 
 // c + bit `lane` of the wave-uniform mask m: the mask is the carry-in of an add, so a lane learns
@@ -2231,7 +2258,7 @@ hipError_t launch_bin(const RenderDims& d, const uint32_t* skeys, const uint32_t
   uint32_t* tot = (uint32_t*)(ws + lo.tile_tot);
   Status* status = (Status*)(ws + lo.status);
   dim3 grid1(d.n_bin_chunks, d.B);
-  const size_t lds1 = (size_t)d.TY * sizeof(uint32_t);
+  const size_t lds1 = (size_t)(d.TY + 1) * sizeof(uint32_t);
   dim3 grid2(d.n_row_segs, d.TY, d.B);
   if (d.n_bin_chunks > 0) {
     {
