@@ -1782,10 +1782,12 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
         // cand: the pixel lies before the last contributor of some layer the entry belongs to; the
         // per-layer comparisons serve both the count and the layer updates (bitwise, no branches)
         bool cand = false;
-        const uint32_t lmask = 0xFFu << lmin;  // the entry's layers (uniform)
+        // the entry's layers are lmin and above: walked from the top down to a uniform exit, so
+        // that the layers below lmin cost nothing (a uniform test per layer is turned into lane
+        // masking, a compare and a handful of scalar operations per skipped layer)
 #pragma unroll
-        for (int l = 0; l < MAXL; ++l) {
-          if (!((lmask >> l) & 1u)) continue;
+        for (int l = MAXL - 1; l >= 0; --l) {
+          if ((uint32_t)l < lmin) break;
           const bool before = kk < last[l];
           if (COUNT) cand |= before;
           if (!(hit & before)) continue;
