@@ -2044,7 +2044,6 @@ __global__ __launch_bounds__(kBwd2Threads) void k_raster_bwd2(RenderDims d, Stat
         const float4 col = s_c[j];
         const uint32_t kk = __float_as_uint(col.w);
         const uint32_t lmin = __builtin_amdgcn_readfirstlane(__float_as_uint(cb.w)) & 0xFFu;
-        const uint32_t lmask = 0xFFu << lmin;  // the entry's layers (uniform)
         float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -2055,9 +2054,11 @@ __global__ __launch_bounds__(kBwd2Threads) void k_raster_bwd2(RenderDims d, Stat
           const float ioma = __builtin_amdgcn_rcpf(oma);
           float gr = 0.f, gg = 0.f, gb = 0.f, dal = 0.f;
           bool cand = false;
+          // the entry's layers, lmin and above, from the top down to a uniform exit (as in
+          // k_raster_bwd)
 #pragma unroll
-          for (int l = 0; l < MAXL; ++l) {
-            if (!((lmask >> l) & 1u)) continue;
+          for (int l = MAXL - 1; l >= 0; --l) {
+            if ((uint32_t)l < lmin) break;
             const bool before = kk < last[p][l];
             if (COUNT) cand |= before;
             if (!(hit & before)) continue;
