@@ -143,16 +143,19 @@ def test_overflow_reports_needed_pairs_and_retry_matches():
     assert torch.equal(img1, img2)
 
 
-def test_tile_coverage_is_conservative():
-    _case("every oracle contribution lies in an emitted tile")
-    w = _small_ring(n=1500, seed=49, w=96, h=80, views=(4,), levels=False)
-    img, ws, _ = _gpu_forward(w)
+def _tile_sets(ws):
+    """The Gaussian indices of every tile's list (one frame-view), and the layout."""
     lo = ws.layout()
     buf = ws.buf.cpu().numpy()
     T = lo.tiles_x * lo.tiles_y
     ranges = buf[lo.ranges:lo.ranges + 8 * T].view(np.uint32).reshape(T, 2)
     lists = buf[lo.lists:lo.lists + 4 * int(ranges[-1, 1])].view(np.uint32)
-    in_tile = [set(lists[s:e].tolist()) for s, e in ranges]
+    return [set(lists[s:e].tolist()) for s, e in ranges], lo
+
+
+def _missed_contributions(w, in_tile, tiles_x):
+    """The number of (Gaussian, tile) pairs where the oracle's Gaussian reaches alpha >= 1/255 at a
+    pixel centre of the tile but the tile's list does not hold it."""
     pr = oracle.project(oracle_settings(w), w.params, w.cams)[0]
     u = np.arange(w.width) + 0.5
     v = np.arange(w.height) + 0.5
@@ -165,10 +168,40 @@ def test_tile_coverage_is_conservative():
         dy = v[:, None] - pr[i, 3]
         a = pr[i, 10] * np.exp(-0.5 * (pr[i, 7] * dx * dx + 2 * pr[i, 8] * dx * dy + pr[i, 9] * dy * dy))
         ys, xs = np.nonzero(a >= amin * (1 - 1e-4))
-        for t in set(((ys // 16) * lo.tiles_x + xs // 16).tolist()):
+        for t in set(((ys // 16) * tiles_x + xs // 16).tolist()):
             if i not in in_tile[t]:
                 missed += 1
-    assert missed == 0
+    return missed
+
+
+def test_tile_coverage_is_conservative():
+    _case("every oracle contribution lies in an emitted tile")
+    w = _small_ring(n=1500, seed=49, w=96, h=80, views=(4,), levels=False)
+    img, ws, _ = _gpu_forward(w)
+    in_tile, lo = _tile_sets(ws)
+    assert _missed_contributions(w, in_tile, lo.tiles_x) == 0
+
+
+@pytest.mark.parametrize("width", [1008, 1024])
+def test_tile_lists_at_the_one_column_per_lane_limit(width):
+    # 63 tile columns are emitted with one column per lane (a column range becomes a 64-bit lane
+    # mask); 64 and more with two columns per lane
+    _case(f"forward {width}x48 ({width // 16} tile columns), Gaussians spanning every column")
+    w = _small_ring(n=1500, seed=53, w=width, h=48, views=(2,), levels=False)
+    w.params[3:6, :12] = np.log(0.8)  # twelve Gaussians wider than the image
+    w.params[10, :12] = 3.0
+    img, ws, _ = _gpu_forward(w)
+    in_tile, lo = _tile_sets(ws)
+    assert lo.tiles_x == width // 16
+    # some Gaussian is listed in every tile of a row
+    row = [in_tile[lo.tiles_x + tx] for tx in range(lo.tiles_x)]
+    assert set.intersection(*row), "no Gaussian spans the middle tile row"
+    assert _missed_contributions(w, in_tile, lo.tiles_x) == 0
+    ref = oracle.render(oracle_settings(w), w.params, w.cams, variants=True)
+    bad, amb, excl, err = image_mismatch(_flat(img), ref)
+    print(f"bad={bad} ambiguous={amb} excluded={excl} max_err={err:.3g}")
+    assert bad == 0
+    assert excl <= 1e-4 * ref["nvar"].size + 2
 
 
 @pytest.mark.parametrize("bwd_pixels", [1, 2])
