@@ -1613,7 +1613,7 @@ __device__ __forceinline__ float fx_value(const unsigned long long* p) {
 }
 
 template <int MAXL, bool COUNT, bool DET>
-__global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* __restrict__ st,
+__global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <= 6 ? 7 : 1))) void k_raster_bwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ lists,
                                                          const float4* __restrict__ rec,
@@ -1689,7 +1689,7 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
   uint32_t ktop = 0;
 #pragma unroll
   for (int l = 0; l < MAXL; ++l) {
-    lmax[l] = l < d.L ? s_lmax[l] : 0u;
+    lmax[l] = __builtin_amdgcn_readfirstlane(l < d.L ? s_lmax[l] : 0u);  // block-uniform: scalar registers
     ktop = max(ktop, lmax[l]);
   }
   // per wave: lw[m] = the largest last-contributor position over its pixels and the layers l >= m,
@@ -1700,7 +1700,7 @@ __global__ __launch_bounds__(kTilePix) void k_raster_bwd(RenderDims d, Status* _
 #pragma unroll
     for (int l = MAXL - 1; l >= 0; --l) {
       run = max(run, wave_max_u(l < d.L ? last[l] : 0u));
-      lw[l] = run;
+      lw[l] = __builtin_amdgcn_readfirstlane(run);  // wave-uniform
     }
   }
   const size_t recbase = (size_t)c.b * d.n;
