@@ -1411,8 +1411,9 @@ __device__ __forceinline__ void open_state(const RenderDims& d, const float* Tr,
   }
 }
 
-// at least 7 waves per SIMD for up to 6 layers (71 VGPRs, no spills): the walk has long LDS and
-// exp latencies, and a seventh wave hid more of them than the registers it costs
+// at least 7 waves per SIMD for up to 6 layers (72 VGPRs; one value spilled before the walk and
+// reloaded for the output): the walk has long LDS and exp latencies, and a seventh wave hid more
+// of them than the registers it costs (eight waves need spills inside the walk and are slower)
 template <int MAXL, bool COUNT>
 __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <= 6 ? 7 : 1))) void k_raster_fwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
@@ -1612,6 +1613,8 @@ __device__ __forceinline__ float fx_value(const unsigned long long* p) {
   return (float)((double)(long long)p[1] + (double)p[0] * 0x1p-64);
 }
 
+// at least 7 waves per SIMD for up to 6 layers (72 VGPRs, the layer bounds in scalar registers):
+// a seventh wave hides more of the walk's LDS and exp latencies than six waves with 78 registers
 template <int MAXL, bool COUNT, bool DET>
 __global__ __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(MAXL <= 6 ? 7 : 1))) void k_raster_bwd(RenderDims d, Status* __restrict__ st,
                                                          const uint2* __restrict__ ranges,
