@@ -497,16 +497,21 @@ __global__ __launch_bounds__(256) void k_project_bwd(RenderDims d, const float* 
     float dsh[3 * K];
 #pragma unroll
     for (int c = 0; c < 3 * K; ++c) dsh[c] = 0.f;
+    // the gradient record of view v + 1 is loaded while view v is processed (one wave per SIMD
+    // here: nothing else would hide the load)
+    float4 n0, n1;
+    float n8;
+    auto load_rec = [&](int b) {
+      const float* gp = g2d + ((size_t)b * n + i) * kGradStride;
+      n0 = ((const float4*)gp)[0];
+      n1 = ((const float4*)gp)[1];
+      n8 = gp[8];
+    };
+    if (d.V > 0) load_rec(f * d.V);
     for (int v = 0; v < d.V; ++v) {
       const int b = f * d.V + v;
-      float gr[9];
-      {
-        const float4* gp = (const float4*)(g2d + ((size_t)b * n + i) * kGradStride);
-        const float4 g0 = gp[0], g1 = gp[1];
-        const float g8 = g2d[((size_t)b * n + i) * kGradStride + 8];
-        gr[0] = g0.x; gr[1] = g0.y; gr[2] = g0.z; gr[3] = g0.w;
-        gr[4] = g1.x; gr[5] = g1.y; gr[6] = g1.z; gr[7] = g1.w; gr[8] = g8;
-      }
+      float gr[9] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w, n8};
+      if (v + 1 < d.V) load_rec(b + 1);
       bool any = false;
       for (int c = 0; c < 9; ++c) any = any || (gr[c] != 0.f);
       if (!any) continue;
